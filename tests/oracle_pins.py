@@ -1,0 +1,369 @@
+"""Pins for the FP64 oracle: checks against what mathematics and independent solvers fix.
+
+Each pin takes the path of an oracle library so that the same checks can run against a deliberately
+broken copy of the oracle (see test_oracle_mutants.py). A pin raises AssertionError on failure.
+
+Sources of truth used here, none of them the oracle itself:
+  * brute-force vertex enumeration on tiny boxed LPs (an LP over a polytope attains its optimum at
+    a vertex);
+  * HiGHS through scipy.optimize.linprog (a library routine);
+  * closed forms: box-only LP, single-row fractional knapsack (greedy by ratio), disjoint set cover,
+    the Pock-Chambolle pass on a 2x2 matrix, hand-computed residuals and PDHG steps;
+  * LP duality (primal = dual objective at an optimum) and the KKT conditions;
+  * fixed-point property: a PDHG step from an optimal primal-dual pair does not move it;
+  * scipy.sparse for the matrix product and the transpose.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+from scipy.optimize import linprog
+
+import oracle
+from paper_2503_10344_amd import generators as g
+
+L_, G_, E_ = ord("L"), ord("G"), ord("E")
+
+
+def _lp_from_dense(A, b, sense, c, l, u, name="dense"):
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    rows, cols = np.nonzero(A)
+    rp = np.zeros(m + 1, np.int32)
+    np.cumsum(np.bincount(rows, minlength=m), out=rp[1:])
+    return g.LP(m, n, rp, cols.astype(np.int32), A[rows, cols].copy(), np.asarray(c, float),
+                np.asarray(b, float), np.asarray(sense, np.uint8), np.asarray(l, float),
+                np.asarray(u, float), name=name)
+
+
+def highs(lp):
+    """Solve with HiGHS; returns (objective, x, y) with y in the sign convention
+    c'x - y'(Ax - b): y >= 0 on >= rows, y <= 0 on <= rows."""
+    A = lp.to_scipy()
+    ub_rows = np.nonzero(lp.sense != E_)[0]
+    eq_rows = np.nonzero(lp.sense == E_)[0]
+    sign = np.where(lp.sense[ub_rows] == G_, -1.0, 1.0)
+    A_ub = A[ub_rows].multiply(sign[:, None]).tocsr() if ub_rows.size else None
+    b_ub = lp.b[ub_rows] * sign if ub_rows.size else None
+    A_eq = A[eq_rows] if eq_rows.size else None
+    b_eq = lp.b[eq_rows] if eq_rows.size else None
+    bounds = [(None if not np.isfinite(lo) else lo, None if not np.isfinite(hi) else hi)
+              for lo, hi in zip(lp.l, lp.u)]
+    res = linprog(lp.c, A_ub=A_ub, b_ub=b_ub, A_eq=A_eq, b_eq=b_eq, bounds=bounds, method="highs")
+    assert res.status == 0, res.message
+    y = np.zeros(lp.m)
+    if ub_rows.size:
+        y[ub_rows] = res.ineqlin.marginals * sign
+    if eq_rows.size:
+        y[eq_rows] = res.eqlin.marginals
+    return float(res.fun), np.asarray(res.x), y
+
+
+def brute_force(lp):
+    """Minimum of c'x over the vertices of {x : rows, l <= x <= u} (finite box)."""
+    A = np.zeros((lp.m, lp.n))
+    for i in range(lp.m):
+        A[i, lp.col[lp.row_ptr[i]:lp.row_ptr[i + 1]]] = lp.val[lp.row_ptr[i]:lp.row_ptr[i + 1]]
+    cons = []  # (coefficients, rhs)
+    for i in range(lp.m):
+        cons.append((A[i], lp.b[i]))
+    for j in range(lp.n):
+        e = np.zeros(lp.n)
+        e[j] = 1.0
+        cons.append((e, lp.l[j]))
+        cons.append((e, lp.u[j]))
+    eq = [i for i in range(lp.m) if lp.sense[i] == E_]
+    others = [k for k in range(len(cons)) if k not in eq]
+    best = np.inf
+    need = lp.n - len(eq)
+    for extra in itertools.combinations(others, need):
+        idx = list(eq) + list(extra)
+        M = np.array([cons[k][0] for k in idx])
+        r = np.array([cons[k][1] for k in idx])
+        if abs(np.linalg.det(M)) < 1e-12:
+            continue
+        x = np.linalg.solve(M, r)
+        ax = A @ x
+        ok = np.all(x >= lp.l - 1e-9) and np.all(x <= lp.u + 1e-9)
+        ok &= np.all(np.where(lp.sense == L_, ax <= lp.b + 1e-9, True))
+        ok &= np.all(np.where(lp.sense == G_, ax >= lp.b - 1e-9, True))
+        ok &= np.all(np.where(lp.sense == E_, np.abs(ax - lp.b) <= 1e-9, True))
+        if ok:
+            best = min(best, float(lp.c @ x))
+    return best
+
+
+def _close(a, b, rel):
+    return abs(a - b) <= rel * max(1.0, abs(b))
+
+
+# ------------------------------------------------------------------------------------------------
+def pin_bruteforce(lib=oracle.LIB):
+    for seed in range(6):
+        lp = g.tiny_lp(seed, m=3 + seed % 3, n=3 + (seed // 2) % 3)
+        fstar = brute_force(lp)
+        assert np.isfinite(fstar)
+        r = oracle.solve(lp, tol=1e-9, iter_limit=400_000, lib_path=lib)
+        assert r.status == oracle.OPTIMAL, (seed, r.status)
+        assert _close(r.pobj, fstar, 1e-6) and _close(r.dobj, fstar, 1e-6), (seed, r.pobj, r.dobj, fstar)
+
+
+def pin_highs_setcover(lib=oracle.LIB):
+    for seed in range(2):
+        lp = g.set_cover(seed, m=120, n=300, k=4)
+        f, _, _ = highs(lp)
+        r = oracle.solve(lp, tol=1e-8, iter_limit=400_000, lib_path=lib)
+        assert r.status == oracle.OPTIMAL
+        assert _close(r.pobj, f, 1e-6), (r.pobj, f)
+
+
+def pin_highs_general(lib=oracle.LIB):
+    for seed in range(2):
+        lp = g.general_sparse(seed, m=60, n=120, cap=20)
+        f, _, _ = highs(lp)
+        r = oracle.solve(lp, tol=1e-8, iter_limit=600_000, lib_path=lib)
+        assert r.status == oracle.OPTIMAL, r.status
+        assert _close(r.pobj, f, 1e-6) and _close(r.dobj, f, 1e-6), (r.pobj, r.dobj, f)
+        # the returned point satisfies the tolerance when re-evaluated from scratch
+        assert oracle.kkt(lp, r.x, r.y, lib_path=lib)["rel_kkt"] <= 1e-8 * 1.01
+
+
+def pin_energy_small(lib=oracle.LIB):
+    lp = g.energy(3, T=12, N=4, K=3, E=6)
+    f, _, _ = highs(lp)
+    r = oracle.solve(lp, tol=1e-7, iter_limit=800_000, lib_path=lib)
+    assert r.status == oracle.OPTIMAL
+    assert _close(r.pobj, f, 1e-5), (r.pobj, f)
+
+
+def pin_box_only(lib=oracle.LIB):
+    """No rows: x_j = l_j if c_j > 0, u_j if c_j < 0."""
+    c = np.array([3.0, -2.0, 1.0, -0.5, 4.0, 1.0, -2.0])
+    l = np.array([-1.0, 0.0, 2.0, -3.0, 0.5, -2.0, -np.inf])
+    u = np.array([1.0, 5.0, 4.0, 3.0, 2.0, np.inf, 0.0])
+    n = c.size
+    lp = g.LP(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), c, np.zeros(0),
+              np.zeros(0, np.uint8), l, u, name="box")
+    xstar = np.where(c > 0, l, u)
+    fstar = float(c @ xstar)
+    r = oracle.solve(lp, tol=1e-10, iter_limit=20_000, lib_path=lib)
+    assert r.status == oracle.OPTIMAL
+    assert np.allclose(r.x, xstar, atol=1e-8), (r.x, xstar)
+    assert _close(r.pobj, fstar, 1e-9)
+
+
+def pin_knapsack(lib=oracle.LIB):
+    """max p'x s.t. w'x <= W, 0 <= x <= 1: greedy by p/w, the last item fractional."""
+    rng = np.random.default_rng(5)
+    n = 12
+    p = rng.integers(1, 50, n).astype(float)
+    w = rng.integers(1, 30, n).astype(float)
+    W = 0.4 * w.sum()
+    order = np.argsort(-p / w, kind="stable")
+    cap, fstar = W, 0.0
+    for j in order:
+        take = min(1.0, cap / w[j])
+        fstar += take * p[j]
+        cap -= take * w[j]
+        if cap <= 0:
+            break
+    lp = _lp_from_dense(w[None, :], [W], [L_], -p, np.zeros(n), np.ones(n), "knapsack")
+    r = oracle.solve(lp, tol=1e-9, iter_limit=400_000, lib_path=lib)
+    assert r.status == oracle.OPTIMAL
+    assert _close(r.pobj, -fstar, 1e-7), (r.pobj, -fstar)
+    # the row is tight and its dual is the critical ratio, with the <= sign convention
+    jcrit = [j for j in order if 1e-6 < r.x[j] < 1 - 1e-6]
+    if jcrit:
+        assert abs(r.y[0] - (-p[jcrit[0]] / w[jcrit[0]])) < 1e-5, (r.y, jcrit)
+
+
+def pin_disjoint_cover(lib=oracle.LIB):
+    """Rows covered by disjoint column groups: optimum picks the cheapest column of each row."""
+    rng = np.random.default_rng(11)
+    m, per = 9, 4
+    n = m * per
+    A = np.zeros((m, n))
+    c = rng.integers(1, 100, n).astype(float)
+    for i in range(m):
+        A[i, i * per:(i + 1) * per] = 1.0
+    fstar = sum(c[i * per:(i + 1) * per].min() for i in range(m))
+    lp = _lp_from_dense(A, np.ones(m), [G_] * m, c, np.zeros(n), np.ones(n), "disjoint")
+    r = oracle.solve(lp, tol=1e-9, iter_limit=200_000, lib_path=lib)
+    assert r.status == oracle.OPTIMAL
+    assert _close(r.pobj, fstar, 1e-7), (r.pobj, fstar)
+
+
+def pin_duality_and_kkt(lib=oracle.LIB):
+    """At a 1e-8 solution: primal = dual objective, y has the sign of its row, complementary
+    slackness, and the reduced cost r = c - A'y points into the active bounds."""
+    lp = g.general_sparse(4, m=50, n=100, cap=15)
+    r = oracle.solve(lp, tol=1e-9, iter_limit=800_000, lib_path=lib)
+    assert r.status == oracle.OPTIMAL
+    assert abs(r.pobj - r.dobj) <= 1e-7 * (1 + abs(r.pobj))
+    A = lp.to_scipy()
+    ax = A @ r.x
+    assert np.all(r.y[lp.sense == G_] >= 0) and np.all(r.y[lp.sense == L_] <= 0)
+    scale = 1 + np.abs(lp.b).max()
+    assert np.all(np.abs(r.y * (ax - lp.b)) <= 1e-6 * scale * (1 + np.abs(r.y).max()))
+    rc = lp.c - A.T @ r.y
+    assert np.allclose(rc, r.rc, atol=1e-9 * (1 + np.abs(rc).max()))
+    interior = (r.x > lp.l + 1e-5) & (r.x < lp.u - 1e-5)
+    assert np.all(np.abs(rc[interior]) <= 1e-5 * (1 + np.abs(lp.c).max()))
+    at_lo = np.abs(r.x - lp.l) <= 1e-7
+    at_hi = np.abs(r.x - lp.u) <= 1e-7
+    assert np.all(rc[at_lo & ~at_hi] >= -1e-5 * (1 + np.abs(lp.c).max()))
+    assert np.all(rc[at_hi & ~at_lo] <= 1e-5 * (1 + np.abs(lp.c).max()))
+
+
+def pin_fixed_point(lib=oracle.LIB):
+    """One PDHG step from HiGHS's optimal (x*, y*) leaves it in place, for any step sizes."""
+    for seed in range(2):
+        lp = g.general_sparse(10 + seed, m=40, n=80, cap=12)
+        f, xs, ys = highs(lp)
+        for tau, sigma in ((0.1, 0.2), (1.0, 0.05)):
+            xn, yn = oracle.pdhg_step(lp, xs, ys, tau, sigma, lib_path=lib)
+            assert np.abs(xn - xs).max() <= 1e-9 * (1 + np.abs(xs).max()), np.abs(xn - xs).max()
+            assert np.abs(yn - ys).max() <= 1e-9 * (1 + np.abs(ys).max()), np.abs(yn - ys).max()
+
+
+def pin_step_by_hand(lib=oracle.LIB):
+    """Hand-computed steps on one variable and one row, one case per row sense."""
+    # min 2x s.t. x >= 1 (G), 0 <= x <= 10, from x = 0.5, y = 0.25, tau = 0.1, sigma = 0.2:
+    # x' = 0.5 - 0.1 (2 - 0.25) = 0.325 ; y' = max(0, 0.25 + 0.2 (1 - (2*0.325 - 0.5))) = 0.42
+    lp = _lp_from_dense([[1.0]], [1.0], [G_], [2.0], [0.0], [10.0])
+    xn, yn = oracle.pdhg_step(lp, [0.5], [0.25], 0.1, 0.2, lib_path=lib)
+    assert abs(xn[0] - 0.325) < 1e-15 and abs(yn[0] - 0.42) < 1e-15, (xn, yn)
+    # same data with a <= row: y' = min(0, 0.25 + 0.2 * 0.85) = 0
+    lp = _lp_from_dense([[1.0]], [1.0], [L_], [2.0], [0.0], [10.0])
+    xn, yn = oracle.pdhg_step(lp, [0.5], [0.25], 0.1, 0.2, lib_path=lib)
+    assert abs(xn[0] - 0.325) < 1e-15 and yn[0] == 0.0
+    # = row with coefficient 3: x' = clip(0.5 - 0.1 (2 - 0.75), 0, 10) = 0.375 ;
+    # y' = 0.25 + 0.2 (1 - 3 (0.75 - 0.5)) = 0.3
+    lp = _lp_from_dense([[3.0]], [1.0], [E_], [2.0], [0.0], [10.0])
+    xn, yn = oracle.pdhg_step(lp, [0.5], [0.25], 0.1, 0.2, lib_path=lib)
+    assert abs(xn[0] - 0.375) < 1e-15 and abs(yn[0] - 0.3) < 1e-15, (xn, yn)
+    # the primal projection clips at the upper bound: c = -50 pushes x up to u = 0.6
+    lp = _lp_from_dense([[1.0]], [1.0], [G_], [-50.0], [0.0], [0.6])
+    xn, _ = oracle.pdhg_step(lp, [0.5], [0.0], 0.1, 0.2, lib_path=lib)
+    assert xn[0] == 0.6
+
+
+def pin_kkt_by_hand(lib=oracle.LIB):
+    """Residuals of a perturbed point computed by hand.
+
+    min x1 + x2 + x3 + x4  s.t.  x1 + x2 + x3 >= 1 (G),  x1 - x2 = 0 (E),  x2 + x4 <= 2 (L)
+    0 <= x1, x2 <= 10, x3 free, x4 >= 0.
+    At x = (0.2, 0.3, 0.1, 0.5), y = (0.5, 0.1, -0.2):
+      Ax = (0.6, -0.1, 0.8); r_p = (max(1 - 0.6, 0), 0 - (-0.1), min(2 - 0.8, 0)) = (0.4, 0.1, 0)
+      A'y = (0.6, 0.2, 0.5, -0.2); g = c - A'y = (0.4, 0.8, 0.5, 1.2)
+      lambda = (0.4, 0.8, 0, 1.2) (x3 free -> 0; x4 lower only -> max(g, 0)); r_d = (0, 0, 0.5, 0)
+      pobj = 1.1; dobj = b'y + sum l lambda+ - sum u lambda- = (0.5 + 0 - 0.4) + 0 = 0.1
+      rel_p = sqrt(0.17) / (1 + sqrt(5)); rel_d = 0.5 / (1 + 2); rel_gap = 1.0 / (1 + 1.1 + 0.1)
+    """
+    A = [[1, 1, 1, 0], [1, -1, 0, 0], [0, 1, 0, 1]]
+    lp = _lp_from_dense(A, [1.0, 0.0, 2.0], [G_, E_, L_], [1.0, 1.0, 1.0, 1.0],
+                        [0.0, 0.0, -np.inf, 0.0], [10.0, 10.0, np.inf, np.inf])
+    out = oracle.kkt(lp, [0.2, 0.3, 0.1, 0.5], [0.5, 0.1, -0.2], lib_path=lib)
+    assert abs(out["rel_p"] - np.sqrt(0.17) / (1 + np.sqrt(5.0))) < 1e-14, out
+    assert abs(out["rel_d"] - 0.5 / 3.0) < 1e-14, out
+    assert abs(out["pobj"] - 1.1) < 1e-14 and abs(out["dobj"] - 0.1) < 1e-14, out
+    assert abs(out["rel_gap"] - 1.0 / 2.2) < 1e-14, out
+    # an upper-bound-only column with positive g is dual infeasible; negative g enters via u
+    lp2 = _lp_from_dense([[1.0, 1.0]], [1.0], [G_], [1.0, -1.0], [0.0, -np.inf], [1.0, 3.0])
+    out = oracle.kkt(lp2, [0.5, 0.5], [0.5], lib_path=lib)
+    # g = (0.5, -1.5): lambda = (0.5, -1.5), r_d = 0 ; dobj = 0.5 + 0 * 0.5 + 3 * (-1.5) = -4.0
+    assert abs(out["rel_d"]) < 1e-15 and abs(out["dobj"] - (-4.0)) < 1e-14, out
+    out = oracle.kkt(lp2, [0.5, 0.5], [2.0], lib_path=lib)
+    # g = (-1.0, -3.0): lambda = (-1.0, -3.0) ; dobj = 2 + 1 * (-1) + 3 * (-3) = -8
+    assert abs(out["dobj"] - (-8.0)) < 1e-14, out
+
+
+def pin_kkt_at_highs(lib=oracle.LIB):
+    lp = g.general_sparse(21, m=50, n=100, cap=15)
+    f, xs, ys = highs(lp)
+    out = oracle.kkt(lp, xs, ys, lib_path=lib)
+    assert out["rel_kkt"] <= 1e-9, out
+    assert _close(out["pobj"], f, 1e-12)
+
+
+def pin_scaling(lib=oracle.LIB):
+    lp = g.general_sparse(3, m=80, n=150, cap=30)
+    A = lp.to_scipy().toarray()
+    # Ruiz only: every row and column inf-norm approaches 1
+    Dr, Dc, sv = oracle.scale(lp, ruiz_iters=10, pock_chambolle=False, lib_path=lib)
+    S = np.zeros_like(A)
+    for i in range(lp.m):
+        S[i, lp.col[lp.row_ptr[i]:lp.row_ptr[i + 1]]] = sv[lp.row_ptr[i]:lp.row_ptr[i + 1]]
+    rmax = np.abs(S).max(axis=1)
+    cmax = np.abs(S).max(axis=0)
+    nz_c = np.abs(A).max(axis=0) > 0
+    assert np.all(np.abs(rmax - 1) < 2e-2) and np.all(np.abs(cmax[nz_c] - 1) < 2e-2), (rmax, cmax)
+    # the scaled values equal Dr A Dc
+    assert np.allclose(S, Dr[:, None] * A * Dc[None, :], rtol=1e-13, atol=0)
+    # the full preconditioner keeps the LP's optimum: solve the scaled LP with HiGHS and map back
+    Dr, Dc, sv = oracle.scale(lp, lib_path=lib)
+    slp = g.LP(lp.m, lp.n, lp.row_ptr, lp.col, sv, lp.c * Dc, lp.b * Dr, lp.sense, lp.l / Dc,
+               lp.u / Dc)
+    f0, _, _ = highs(lp)
+    f1, xs1, _ = highs(slp)
+    assert _close(f0, f1, 1e-8)
+    # Pock-Chambolle alone on a 2x2 by hand: a_ij / sqrt(rowsum_i * colsum_j)
+    lp22 = _lp_from_dense([[1.0, 2.0], [3.0, 4.0]], [1, 1], [E_, E_], [0, 0], [0, 0], [1, 1])
+    Dr, Dc, sv = oracle.scale(lp22, ruiz_iters=0, pock_chambolle=True, lib_path=lib)
+    want = np.array([1 / np.sqrt(3 * 4), 2 / np.sqrt(3 * 6), 3 / np.sqrt(7 * 4), 4 / np.sqrt(7 * 6)])
+    assert np.allclose(sv, want, rtol=1e-15), (sv, want)
+    assert np.allclose(Dr, 1 / np.sqrt([3.0, 7.0])) and np.allclose(Dc, 1 / np.sqrt([4.0, 6.0]))
+
+
+def pin_spmv_transpose(lib=oracle.LIB):
+    lp = g.general_sparse(1, m=300, n=500, cap=60)
+    A = lp.to_scipy()
+    x = np.random.default_rng(0).standard_normal(lp.n)
+    assert np.allclose(oracle.spmv(lp.row_ptr, lp.col, lp.val, x, lib_path=lib), A @ x, rtol=1e-13, atol=1e-13)
+    trp, tci, tv = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col, lp.val, lib_path=lib)
+    T = A.T.tocsr()
+    T.sort_indices()
+    assert np.array_equal(trp, T.indptr) and np.array_equal(tci, T.indices) and np.array_equal(tv, T.data)
+
+
+def pin_warm_start(lib=oracle.LIB):
+    """Started at an optimal pair, the solve stops at its first evaluation."""
+    lp = g.general_sparse(30, m=40, n=80, cap=12)
+    f, xs, ys = highs(lp)
+    r = oracle.solve(lp, tol=1e-7, iter_limit=10_000, x0=xs, y0=ys, lib_path=lib)
+    assert r.status == oracle.OPTIMAL and r.iterations == 64, (r.status, r.iterations)
+    assert _close(r.pobj, f, 1e-7)
+
+
+def pin_step_condition(lib=oracle.LIB):
+    """Every accepted step satisfies the adaptive step-size condition of PDLP,
+    eta * 2 |dy' A~ dx| <= omega |dx|^2 + |dy|^2 / omega, checked from the recorded iterates."""
+    lp = g.general_sparse(8, m=60, n=120, cap=20)
+    K = 150
+    r = oracle.solve(lp, tol=0.0, iter_limit=K, trace_len=K, lib_path=lib)
+    Dr, Dc, sv = oracle.scale(lp, lib_path=lib)
+    import scipy.sparse as sp
+    As = sp.csr_matrix((sv, lp.col, lp.row_ptr), shape=(lp.m, lp.n))
+    tr = r.trace
+    xs = [np.zeros(lp.n)] + [tr["x"][k] / Dc for k in range(K)]
+    ys = [np.zeros(lp.m)] + [tr["y"][k] / Dr for k in range(K)]
+    n_acc = 0
+    for k in range(2, K + 1):
+        flags = tr["flags"][k - 1]
+        eta_used = tr["eta"][k - 2]
+        omega = tr["omega"][k - 2]
+        if flags & 1 and not (flags & 4):
+            dx = xs[k] - xs[k - 1]
+            dy = ys[k] - ys[k - 1]
+            lhs = eta_used * 2 * abs(dy @ (As @ dx))
+            rhs = omega * dx @ dx + dy @ dy / omega
+            assert lhs <= rhs * (1 + 1e-9) + 1e-300, (k, lhs, rhs)
+            n_acc += 1
+    assert n_acc > 50
+
+
+ALL_PINS = [pin_spmv_transpose, pin_step_by_hand, pin_kkt_by_hand, pin_kkt_at_highs, pin_fixed_point,
+            pin_scaling, pin_box_only, pin_knapsack, pin_disjoint_cover, pin_bruteforce,
+            pin_highs_setcover, pin_highs_general, pin_energy_small, pin_duality_and_kkt,
+            pin_warm_start, pin_step_condition]
