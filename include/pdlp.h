@@ -1,0 +1,195 @@
+/*
+ * libpdlp -- PDLP (restarted, diagonally preconditioned primal-dual hybrid gradient) for the LP
+ * relaxation of a MIP, on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the LP of eq. (1) of the paper (Introduction):
+ *     min c'x  s.t.  a_i'x <= b_i,  l <= x <= u,  l, u in R u {+-inf},
+ * widened to per-row senses 'L' (<=), 'G' (>=) and 'E' (=) because the energy system models
+ * (section "Energy system optimization models") carry balance equalities. The solver returns the
+ * primal x, the duals y and the reduced costs r = c - A'y, which are what the LP-based variable and
+ * value strategies of section 2 consume ("LP-based variable strategies", "LP-based fixing"). The
+ * paper solves this relaxation with GPU PDLP to a low relative tolerance (1e-4, or 1e-6; section 4,
+ * "Numerical results" and Table 8); 1e-4 is the default here.
+ *
+ * Sign convention of the duals: Lagrangian c'x - y'(Ax - b), so y_i >= 0 on 'G' rows, y_i <= 0 on
+ * 'L' rows and y_i free on 'E' rows.
+ *
+ * Conventions for every entry point:
+ *   - Return value 0 = success, negative = error (PDLP_ERR_*). No C++ exception crosses the ABI.
+ *     pdlp_error_string() names a code; pdlp_last_error() gives detail for the calling thread.
+ *   - Ownership: pdlp_create deep-copies every input; no caller pointer is retained. The handle owns
+ *     all device memory it allocates and releases it in pdlp_destroy. Output buffers belong to the
+ *     caller and are written by pdlp_get.
+ *   - Pointers are host pointers unless pdlp_options.device_ptrs is set, in which case the CSR and
+ *     vector arguments of pdlp_create and the warm start of pdlp_solve are device pointers on the
+ *     handle's device (for example the data pointers of torch tensors).
+ *   - All work is ordered on pdlp_options.stream (a hipStream_t; NULL = the library creates one).
+ *     pdlp_solve and pdlp_get return after the stream has finished their work.
+ *   - Determinism: the same input and options on the same GPU give bitwise identical results.
+ *   - Calls on one handle must not overlap; different handles are independent.
+ */
+#ifndef PDLP_H_
+#define PDLP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes (negative) -------------------------------------------------------------- */
+#define PDLP_OK 0
+#define PDLP_ERR_ARG (-1)   /* bad argument: NULL pointer, negative size, NaN data, l > u, bad sense */
+#define PDLP_ERR_CSR (-2)   /* malformed CSR: row_ptr not monotone, column out of range, duplicate */
+#define PDLP_ERR_OOM (-3)   /* device allocation failed or exceeded pdlp_options.device_mem_limit */
+#define PDLP_ERR_HIP (-4)   /* a HIP runtime call failed */
+#define PDLP_ERR_STATE (-5) /* call out of order, e.g. pdlp_get before pdlp_solve */
+
+/* ---- solve status (pdlp_result.status) -------------------------------------------------- */
+#define PDLP_STATUS_NONE 0
+#define PDLP_STATUS_OPTIMAL 1    /* relative KKT error <= tol in the original space */
+#define PDLP_STATUS_ITER_LIMIT 2 /* iteration limit reached; the current iterate is returned */
+#define PDLP_STATUS_NUMERICAL 3  /* a step size or residual became NaN / Inf */
+
+/* ---- precision modes --------------------------------------------------------------------- */
+#define PDLP_FP32 0 /* matrix values and iterates FP32, int32 indices; norms, KKT, restart and
+                       primal-weight arithmetic FP64 */
+#define PDLP_FP64 1 /* everything FP64 */
+
+typedef struct pdlp_options {
+  int32_t precision;       /* PDLP_FP32 (default) or PDLP_FP64 */
+  int32_t eval_every;      /* attempts between KKT evaluations / restart tests (default 64) */
+  int32_t ruiz_iters;      /* Ruiz equilibration passes (default 10) */
+  int32_t pock_chambolle;  /* 1 = one Pock-Chambolle pass with alpha = 1 after Ruiz (default 1) */
+  int32_t use_graphs;      /* 1 = run each evaluation interval as one captured hipGraph (default 1) */
+  int32_t device_ptrs;     /* 1 = data pointers are device pointers (default 0) */
+  int32_t tile_nnz;        /* SpMV tile size in nonzeros; 0 = autotune (default 0) */
+  int32_t verbose;         /* 0 silent, 1 one line per solve, 2 one line per evaluation */
+  int64_t device_mem_limit;/* > 0: cap on the bytes this handle may allocate (default 0 = none) */
+  void *stream;            /* hipStream_t to order work on; NULL = library-owned stream */
+  int32_t warm_fallback;   /* 1 = replace a warm start whose relative KKT error is not below the
+                              cold start's by the cold start (default 1) */
+  int32_t reserved[7];
+} pdlp_options;
+
+typedef struct pdlp_result {
+  int32_t status;          /* PDLP_STATUS_* */
+  int32_t restarts;        /* number of restarts */
+  int64_t iterations;      /* PDHG attempts (accepted and rejected steps) */
+  double rel_primal;       /* |r_p| / (1 + |b|), original space, FP64 */
+  double rel_dual;         /* |r_d| / (1 + |c|) */
+  double rel_gap;          /* |pobj - dobj| / (1 + |pobj| + |dobj|) */
+  double primal_obj;       /* c'x */
+  double dual_obj;         /* b'y + sum_{l finite} l_j lambda_j^+ - sum_{u finite} u_j lambda_j^- */
+  double omega;            /* final primal weight (scaled space) */
+  double eta;              /* final step size (scaled space) */
+  double solve_seconds;    /* wall time of the last pdlp_solve */
+  int32_t used_average;    /* 1 = the returned point is the weighted average iterate */
+  int32_t warm_started;    /* 1 = a warm start was used, 0 = cold (including fallback) */
+  int32_t fallback_used;   /* 1 = the warm start was rejected in favour of the cold start */
+  int32_t final_checks;    /* how many times the FP64 re-check of the returned point ran */
+} pdlp_result;
+
+typedef struct pdlp_problem pdlp_problem;
+
+/* Fill *opt with the defaults listed above. */
+void pdlp_options_default(pdlp_options *opt);
+
+/*
+ * Create a solver handle for the LP (eq. (1) with row senses).
+ *   m, n        rows and columns (m >= 0, n >= 0; nnz < 2^31)
+ *   row_ptr     [m+1] int32 CSR row offsets, row_ptr[0] = 0, nondecreasing
+ *   col_idx     [nnz] int32 column indices, strictly increasing within a row (no duplicates)
+ *   val         [nnz] float64 values, finite
+ *   c           [n] objective, finite;  b [m] right-hand sides, finite
+ *   sense       [m] 'L', 'G' or 'E'
+ *   l, u        [n] bounds, -inf <= l <= u <= +inf (NaN rejected)
+ *   opt         NULL = defaults
+ * On success *out receives the handle. The matrix is copied to the device, its transpose is built
+ * there, both are equilibrated (10 Ruiz passes and one Pock-Chambolle pass) and the SpMV schedule
+ * is chosen.
+ */
+int pdlp_create(pdlp_problem **out, int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                const int32_t *col_idx, const double *val, const double *c, const double *b,
+                const char *sense, const double *l, const double *u, const pdlp_options *opt);
+
+/*
+ * Solve to relative KKT tolerance tol (<= 0 means run to iter_limit) within iter_limit attempts.
+ * x0 [n] / y0 [m] optional warm start in the original space (NULL = cold start at the projection
+ * of 0); omega0 > 0 sets the initial primal weight (otherwise |c~|/|b~|). A warm start is projected
+ * onto the bounds and sign sets; with warm_fallback set it is replaced by the cold start when its
+ * relative KKT error is not smaller. Each call starts a fresh solve from its own start point.
+ */
+int pdlp_solve(pdlp_problem *p, double tol, int64_t iter_limit, const double *x0, const double *y0,
+               double omega0);
+
+/*
+ * Copy the solution of the last pdlp_solve into caller buffers (each may be NULL):
+ *   x [n] primal, y [m] duals, red_cost [n] = c - A'y, all float64 in the original space;
+ *   res receives the status and FP64 residuals of the returned point.
+ */
+int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_result *res);
+
+/*
+ * y = A x (trans = 0, x [n], y [m]) or y = A' x (trans = 1, x [m], y [n]) with the ORIGINAL
+ * (unscaled) matrix, computed by the library's SpMV kernels in the handle's precision on the
+ * handle's stream. x and y are host pointers unless device_ptrs is set.
+ */
+int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y);
+
+/*
+ * Scaling diagnostics: Dr [m] and Dc [n] (A~ = diag(Dr) A diag(Dc)), and optionally the scaled
+ * matrix values in the CSR order of A (scaled_val [nnz], FP64) and the transpose's CSR
+ * (t_row_ptr [n+1], t_col [nnz], t_val [nnz] scaled). Any pointer may be NULL. Host pointers.
+ */
+int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val, int32_t *t_row_ptr,
+                     int32_t *t_col, double *t_val);
+
+/* SpMV schedule chosen for A and A': tile size in nonzeros and number of tiles of each. */
+int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at);
+
+/* Bytes of device memory held by the handle. */
+int64_t pdlp_device_bytes(const pdlp_problem *p);
+
+void pdlp_destroy(pdlp_problem *p);
+
+const char *pdlp_error_string(int code);
+const char *pdlp_last_error(void);
+
+/* ==========================================================================================
+ * Batched solve: many independent LPs of uneven sizes solved together, as the repeated LP
+ * solves the paper mentions (periodic re-solves, section 2) and as training data for the warm-start
+ * model need. Each instance follows exactly the single-instance method; instances share launches.
+ * ========================================================================================== */
+typedef struct pdlp_problem_desc {
+  int32_t m, n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *val;
+  const double *c, *b;
+  const char *sense;
+  const double *l, *u;
+} pdlp_problem_desc;
+
+typedef struct pdlp_batch pdlp_batch;
+
+/* Create a batch handle for k problems (host pointers). Validation as in pdlp_create. */
+int pdlp_batch_create(pdlp_batch **out, int32_t k, const pdlp_problem_desc *descs,
+                      const pdlp_options *opt);
+
+/* Solve every instance to tol within iter_limit attempts each. x0s/y0s: NULL or arrays of k
+ * pointers (entries may be NULL) to warm starts; omega0s: NULL or k values (<= 0 = default). */
+int pdlp_batch_solve(pdlp_batch *bt, double tol, int64_t iter_limit, const double *const *x0s,
+                     const double *const *y0s, const double *omega0s);
+
+/* Solution of instance i (0 <= i < k), as pdlp_get. */
+int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_cost,
+                   pdlp_result *res);
+
+void pdlp_batch_destroy(pdlp_batch *bt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDLP_H_ */

@@ -30,7 +30,7 @@ OPTIMAL, ITER_LIMIT, NUMERICAL = 1, 2, 3
 
 
 def build(openmp: bool = True, src: str = SRC, out: str = LIB) -> str:
-    cmd = ["gcc", "-O3", "-march=native", "-fPIC", "-shared", "-std=c99", src, "-o", out, "-lm"]
+    cmd = ["gcc", "-O3", "-fPIC", "-shared", "-std=c99", src, "-o", out, "-lm"]
     if openmp:
         cmd.insert(1, "-fopenmp")
     subprocess.run(cmd, check=True)

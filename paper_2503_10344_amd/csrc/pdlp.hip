@@ -1,0 +1,1080 @@
+// libpdlp host runtime: problem set-up on the device, the solve loop (one captured hipGraph per
+// evaluation interval), finalisation and the extern "C" boundary declared in include/pdlp.h.
+//
+// A handle holds K >= 1 LPs as one block-diagonal problem (pdlp_create: K = 1; pdlp_batch_create:
+// K = k). Set-up runs once over the concatenation (scaling and transposition of a block-diagonal
+// matrix act on each block independently); the per-instance scalars are segmented reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pdlp.h"
+#include "pdlp_kernels.h"
+
+namespace pdlp {
+
+// ----------------------------------------------------------------------------------------------
+// Errors
+// ----------------------------------------------------------------------------------------------
+thread_local std::string g_last_error;
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] static void raise(int code, const std::string &msg) { throw Error{code, msg}; }
+
+#define HIPCHK(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) {                                                                     \
+      (void)hipGetLastError();                                                                  \
+      raise(e_ == hipErrorOutOfMemory ? PDLP_ERR_OOM : PDLP_ERR_HIP,                            \
+            std::string(#expr) + ": " + hipGetErrorString(e_));                                 \
+    }                                                                                           \
+  } while (0)
+
+static int grid_for(int64_t n, int per_thread = 1, int cap = 4096) {
+  int64_t g = (n + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// ----------------------------------------------------------------------------------------------
+// Device memory owned by a handle, with an optional cap (forced out-of-memory tests use it).
+// ----------------------------------------------------------------------------------------------
+struct Arena {
+  int64_t limit = 0, used = 0;
+  std::vector<std::pair<void *, int64_t>> blocks;
+  template <typename U>
+  U *alloc(int64_t count) {
+    int64_t bytes = std::max<int64_t>(count, 1) * (int64_t)sizeof(U);
+    bytes = (bytes + 255) & ~int64_t(255);
+    if (limit > 0 && used + bytes > limit)
+      raise(PDLP_ERR_OOM, "device_mem_limit of " + std::to_string(limit) + " bytes exceeded");
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, (size_t)bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      raise(PDLP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    used += bytes;
+    blocks.push_back({p, bytes});
+    return static_cast<U *>(p);
+  }
+  void release(void *p) {
+    for (size_t i = 0; i < blocks.size(); ++i)
+      if (blocks[i].first == p) {
+        (void)hipFree(p);
+        used -= blocks[i].second;
+        blocks.erase(blocks.begin() + (long)i);
+        return;
+      }
+  }
+  ~Arena() {
+    for (auto &b : blocks) (void)hipFree(b.first);
+  }
+};
+
+// ----------------------------------------------------------------------------------------------
+// Host copy of one LP (eq. (1) with row senses) and its validation.
+// ----------------------------------------------------------------------------------------------
+struct HostProblem {
+  int32_t m = 0, n = 0;
+  int64_t nnz = 0;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> val, c, b, l, u;
+  std::vector<uint8_t> sense;
+};
+
+static void validate(const HostProblem &P) {
+  if (P.m < 0 || P.n < 0) raise(PDLP_ERR_ARG, "negative dimension");
+  if (P.nnz < 0 || P.nnz >= (int64_t)INT32_MAX) raise(PDLP_ERR_ARG, "nnz out of range");
+  if (P.rp[0] != 0 || P.rp[P.m] != P.nnz) raise(PDLP_ERR_CSR, "row_ptr[0] must be 0 and row_ptr[m] == nnz");
+  for (int32_t i = 0; i < P.m; ++i) {
+    const int32_t a = P.rp[i], e = P.rp[i + 1];
+    if (e < a) raise(PDLP_ERR_CSR, "row_ptr decreases at row " + std::to_string(i));
+    for (int32_t k = a; k < e; ++k) {
+      const int32_t j = P.ci[k];
+      if (j < 0 || j >= P.n) raise(PDLP_ERR_CSR, "column index out of range in row " + std::to_string(i));
+      if (k > a && j <= P.ci[k - 1])
+        raise(PDLP_ERR_CSR, "column indices not strictly increasing (duplicate or unsorted) in row " +
+                                std::to_string(i));
+    }
+    const uint8_t s = P.sense[i];
+    if (s != 'L' && s != 'G' && s != 'E') raise(PDLP_ERR_ARG, "row sense must be 'L', 'G' or 'E'");
+    if (!std::isfinite(P.b[i])) raise(PDLP_ERR_ARG, "b must be finite");
+  }
+  for (int64_t k = 0; k < P.nnz; ++k)
+    if (!std::isfinite(P.val[k])) raise(PDLP_ERR_ARG, "matrix values must be finite");
+  for (int32_t j = 0; j < P.n; ++j) {
+    if (!std::isfinite(P.c[j])) raise(PDLP_ERR_ARG, "c must be finite");
+    if (std::isnan(P.l[j]) || std::isnan(P.u[j])) raise(PDLP_ERR_ARG, "bounds must not be NaN");
+    if (P.l[j] > P.u[j]) raise(PDLP_ERR_ARG, "l > u at column " + std::to_string(j));
+    if (P.l[j] == INFINITY || P.u[j] == -INFINITY) raise(PDLP_ERR_ARG, "l = +inf or u = -inf");
+  }
+}
+
+// Tile schedule of rows [r0, r1) (see tile_spmv): runs of consecutive rows with <= tn nonzeros
+// and <= kBlock rows; a row longer than tn alone. An empty range yields one empty tile so that
+// every instance owns at least one block. Tile boundaries are appended to `t`.
+static void build_tiles(const int32_t *rp, int32_t r0, int32_t r1, int tn, std::vector<int32_t> &t) {
+  if (r1 == r0) {
+    t.push_back(r1);  // empty tile [r0, r0)
+    return;
+  }
+  int64_t acc = 0;
+  int cnt = 0;
+  for (int32_t i = r0; i < r1; ++i) {
+    const int64_t len = (int64_t)rp[i + 1] - rp[i];
+    if (len > tn) {
+      if (cnt > 0) t.push_back(i);
+      t.push_back(i + 1);
+      acc = 0, cnt = 0;
+      continue;
+    }
+    if (cnt > 0 && (acc + len > tn || cnt == kBlock)) {
+      t.push_back(i);
+      acc = 0, cnt = 0;
+    }
+    acc += len, cnt += 1;
+  }
+  if (cnt > 0) t.push_back(r1);
+}
+
+static const int kTileCandidates[] = {512, 1024, 2048, 4096};
+
+// Autotune cache: matrix signature -> chosen tile size.
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+
+// ----------------------------------------------------------------------------------------------
+// Solver for K instances
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+struct Solver {
+  pdlp_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Arena mem;
+  int32_t K = 1, m = 0, n = 0, nnz = 0;
+  // instance layout (host)
+  std::vector<int32_t> h_row0, h_col0, h_nnz0, h_a_tile0, h_t_tile0, h_ra0, h_ev0;
+  std::vector<int32_t> h_arp, h_trp;
+  std::string sig;
+  // instance layout (device)
+  int32_t *d_row0 = nullptr, *d_col0 = nullptr, *d_nnz0 = nullptr, *d_a_tile0 = nullptr, *d_t_tile0 = nullptr;
+  int32_t *d_a_tile_inst = nullptr, *d_t_tile_inst = nullptr, *d_ra0 = nullptr, *d_ra_inst = nullptr;
+  int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
+  int ra_blocks = 0, ev_blocks = 1;
+  // matrix
+  int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr, *perm = nullptr;
+  int32_t *a_tiles = nullptr, *t_tiles = nullptr;
+  double *a_v64 = nullptr, *t_v64 = nullptr;
+  T *a_v = nullptr, *t_v = nullptr;
+  int tile_nnz = 2048, a_ntiles = 0, t_ntiles = 0;
+  // data
+  uint8_t *sense = nullptr;
+  double *Dr = nullptr, *Dc = nullptr, *c64 = nullptr, *b64 = nullptr, *l64 = nullptr, *u64 = nullptr;
+  T *cT = nullptr, *bT = nullptr, *lT = nullptr, *uT = nullptr;
+  // iterates
+  T *xs[2] = {nullptr, nullptr}, *ys[2] = {nullptr, nullptr}, *axs[2] = {nullptr, nullptr};
+  T *aty = nullptr, *xbar = nullptr, *ybar = nullptr, *axbar = nullptr, *atybar = nullptr;
+  T *xa = nullptr, *ya = nullptr, *tmp_n = nullptr, *tmp_m = nullptr;
+  // finalize / staging
+  double *xd = nullptr, *yd = nullptr, *ax64 = nullptr, *aty64 = nullptr;
+  double *x_out = nullptr, *y_out = nullptr, *rc_out = nullptr, *stage_n = nullptr, *stage_m = nullptr;
+  // reductions, state
+  double *partials = nullptr, *d_red = nullptr;
+  State *st = nullptr;
+  int32_t *ndone = nullptr;
+  std::vector<State> h_st;  // host mirror
+  int32_t *h_flags = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<double> eta0, omega_default, nb, nc;
+  hipGraphExec_t graph = nullptr;
+  Iter<T> P{};
+  bool solved = false;
+  std::vector<pdlp_result> last;
+
+  ~Solver() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h_flags) (void)hipHostFree(h_flags);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  template <typename U>
+  void upload(U *dst, const U *src, int64_t count) {
+    if (count > 0) HIPCHK(hipMemcpyAsync(dst, src, (size_t)count * sizeof(U), hipMemcpyHostToDevice, stream));
+  }
+  template <typename U>
+  void download(U *dst, const U *src, int64_t count) {
+    if (count > 0) HIPCHK(hipMemcpyAsync(dst, src, (size_t)count * sizeof(U), hipMemcpyDeviceToHost, stream));
+  }
+  template <typename U>
+  U *alloc_upload(const std::vector<U> &v) {
+    U *d = mem.alloc<U>((int64_t)v.size());
+    upload(d, v.data(), (int64_t)v.size());
+    return d;
+  }
+  void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+
+  // per-instance segmented reduction (kind 0 sum of squares, 1 max |v|) over segments s0
+  std::vector<double> seg_reduce(int kind, const int32_t *d_s0, const double *v) {
+    hipLaunchKernelGGL(k_seg_reduce, dim3(K), dim3(kBlock), 0, stream, kind, d_s0, v, d_red);
+    HIPCHK(hipGetLastError());
+    std::vector<double> r((size_t)K);
+    download(r.data(), d_red, K);
+    sync();
+    return r;
+  }
+
+  // ---------------------------------------------------------------------------------------------
+  void create(const std::vector<const HostProblem *> &Hs, const pdlp_options &o) {
+    opt = o;
+    K = (int32_t)Hs.size();
+    mem.limit = o.device_mem_limit;
+    if (o.stream) {
+      stream = (hipStream_t)o.stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    HIPCHK(hipHostMalloc((void **)&h_flags, 2 * sizeof(int32_t), hipHostMallocDefault));
+    for (auto &e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+
+    // ---- concatenate ----
+    h_row0.assign(1, 0), h_col0.assign(1, 0), h_nnz0.assign(1, 0);
+    int64_t M = 0, N = 0, Z = 0;
+    for (const HostProblem *H : Hs) {
+      M += H->m, N += H->n, Z += H->nnz;
+      if (M >= INT32_MAX || N >= INT32_MAX || Z >= INT32_MAX) raise(PDLP_ERR_ARG, "total size exceeds int32 range");
+      h_row0.push_back((int32_t)M), h_col0.push_back((int32_t)N), h_nnz0.push_back((int32_t)Z);
+    }
+    m = (int32_t)M, n = (int32_t)N, nnz = (int32_t)Z;
+    h_arp.resize((size_t)m + 1);
+    std::vector<int32_t> ci((size_t)nnz);
+    std::vector<double> val((size_t)nnz), c((size_t)n), b((size_t)m), l((size_t)n), u((size_t)n);
+    std::vector<uint8_t> sn((size_t)m);
+    h_arp[0] = 0;
+    for (int q = 0; q < K; ++q) {
+      const HostProblem &H = *Hs[q];
+      const int32_t r0 = h_row0[q], c0 = h_col0[q], z0 = h_nnz0[q];
+      for (int32_t i = 0; i < H.m; ++i) h_arp[r0 + i + 1] = z0 + H.rp[i + 1];
+      for (int64_t k = 0; k < H.nnz; ++k) ci[z0 + k] = c0 + H.ci[k], val[z0 + k] = H.val[k];
+      std::copy(H.c.begin(), H.c.end(), c.begin() + c0);
+      std::copy(H.l.begin(), H.l.end(), l.begin() + c0);
+      std::copy(H.u.begin(), H.u.end(), u.begin() + c0);
+      std::copy(H.b.begin(), H.b.end(), b.begin() + r0);
+      std::copy(H.sense.begin(), H.sense.end(), sn.begin() + r0);
+    }
+    // signature of the sparsity pattern (autotune cache key)
+    {
+      uint64_t h = 1469598103934665603ull;
+      auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+      mix((uint64_t)K), mix((uint64_t)m), mix((uint64_t)n), mix((uint64_t)nnz);
+      const int32_t step = std::max<int32_t>(1, m / 4096);
+      for (int32_t i = 0; i <= m; i += step) mix((uint64_t)h_arp[i]);
+      char buf[96];
+      snprintf(buf, sizeof buf, "%d:%d:%d:%d:%016llx:%d", K, m, n, nnz, (unsigned long long)h, (int)sizeof(T));
+      sig = buf;
+    }
+
+    const int64_t mm = std::max(m, 1), nn = std::max(n, 1);
+    a_rp = alloc_upload(h_arp);
+    a_ci = alloc_upload(ci);
+    a_v64 = alloc_upload(val);
+    sense = alloc_upload(sn);
+    double *c0 = alloc_upload(c), *b0 = alloc_upload(b), *l0 = alloc_upload(l), *u0 = alloc_upload(u);
+    d_row0 = alloc_upload(h_row0), d_col0 = alloc_upload(h_col0), d_nnz0 = alloc_upload(h_nnz0);
+    t_rp = mem.alloc<int32_t>(n + 1);
+    t_ci = mem.alloc<int32_t>(nnz);
+    perm = mem.alloc<int32_t>(nnz);
+    Dr = mem.alloc<double>(mm), Dc = mem.alloc<double>(nn);
+    c64 = mem.alloc<double>(nn), l64 = mem.alloc<double>(nn), u64 = mem.alloc<double>(nn);
+    b64 = mem.alloc<double>(mm);
+    d_red = mem.alloc<double>(K);
+    st = mem.alloc<State>(K);
+    ndone = mem.alloc<int32_t>(1);
+    h_st.resize((size_t)K);
+    last.assign((size_t)K, pdlp_result{});
+    ci.clear(), ci.shrink_to_fit(), val.clear(), val.shrink_to_fit();
+
+    // ---- transpose (counting sort; the per-column sort of source positions makes it deterministic)
+    int32_t *row_of = mem.alloc<int32_t>(nnz);
+    int32_t *cnt = mem.alloc<int32_t>(nn);
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)nn, stream));
+    hipLaunchKernelGGL(k_expand_rows, dim3(grid_for((int64_t)m * kWave)), dim3(kBlock), 0, stream, m, a_rp, row_of);
+    hipLaunchKernelGGL(k_histogram, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, nnz, a_ci, cnt);
+    const int nsb = (int)std::max<int64_t>(1, ((int64_t)n + kScanItems - 1) / kScanItems);
+    int32_t *bsum = mem.alloc<int32_t>(nsb);
+    hipLaunchKernelGGL(k_scan_partial, dim3(nsb), dim3(kBlock), 0, stream, n, cnt, bsum);
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(kBlock), 0, stream, nsb, bsum);
+    hipLaunchKernelGGL(k_scan_final, dim3(nsb), dim3(kBlock), 0, stream, n, cnt, bsum, t_rp);
+    HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)nn, stream));
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, nnz, a_ci, t_rp, cnt, perm);
+    HIPCHK(hipGetLastError());
+    h_trp.resize((size_t)n + 1);
+    download(h_trp.data(), t_rp, n + 1);
+    sync();
+    std::vector<int32_t> big;
+    std::vector<int64_t> scr_off;
+    int64_t scr_total = 0;
+    for (int32_t j = 0; j < n; ++j) {
+      const int32_t len = h_trp[j + 1] - h_trp[j];
+      if (len > 32) {
+        big.push_back(j);
+        int64_t Np = 1;
+        while (Np < len) Np <<= 1;
+        scr_off.push_back(scr_total);
+        if (Np > kSortLds) scr_total += Np;
+      }
+    }
+    hipLaunchKernelGGL(k_segsort_small, dim3(grid_for(n)), dim3(kBlock), 0, stream, n, t_rp, perm);
+    if (!big.empty()) {
+      int32_t *d_big = alloc_upload(big);
+      int64_t *d_off = alloc_upload(scr_off);
+      int32_t *scr = mem.alloc<int32_t>(std::max<int64_t>(scr_total, 1));
+      for (size_t off = 0; off < big.size(); off += 65535) {
+        const int cntb = (int)std::min<size_t>(65535, big.size() - off);
+        hipLaunchKernelGGL(k_segsort_large, dim3(cntb), dim3(kBlock), 0, stream, d_big + off, t_rp, perm, scr,
+                           d_off + off);
+      }
+      HIPCHK(hipGetLastError());
+      sync();
+      mem.release(d_big), mem.release(d_off), mem.release(scr);
+    }
+
+    // ---- scaling: Ruiz passes then one Pock-Chambolle pass (FP64) ----
+    double *rho = mem.alloc<double>(mm), *kap = mem.alloc<double>(nn);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(m)), dim3(kBlock), 0, stream, (int64_t)m, Dr, 1.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kBlock), 0, stream, (int64_t)n, Dc, 1.0);
+    auto pass = [&](bool sum) {
+      auto rk = sum ? k_row_norm<true> : k_row_norm<false>;
+      hipLaunchKernelGGL(rk, dim3(grid_for((int64_t)m * kWave)), dim3(kBlock), 0, stream, m, (const int32_t *)a_rp,
+                         (const int32_t *)nullptr, (const double *)a_v64, rho);
+      hipLaunchKernelGGL(rk, dim3(grid_for((int64_t)n * kWave)), dim3(kBlock), 0, stream, n, (const int32_t *)t_rp,
+                         (const int32_t *)perm, (const double *)a_v64, kap);
+      hipLaunchKernelGGL(k_apply_scale, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, nnz, (const int32_t *)row_of,
+                         (const int32_t *)a_ci, a_v64, (const double *)rho, (const double *)kap);
+      hipLaunchKernelGGL(k_div_inplace, dim3(grid_for(m)), dim3(kBlock), 0, stream, m, Dr, (const double *)rho);
+      hipLaunchKernelGGL(k_div_inplace, dim3(grid_for(n)), dim3(kBlock), 0, stream, n, Dc, (const double *)kap);
+    };
+    for (int it = 0; it < o.ruiz_iters; ++it) pass(false);
+    if (o.pock_chambolle) pass(true);
+    HIPCHK(hipGetLastError());
+    t_v64 = mem.alloc<double>(nnz);
+    hipLaunchKernelGGL(k_gather_t<double>, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, nnz, (const int32_t *)perm,
+                       (const int32_t *)row_of, (const double *)a_v64, t_ci, t_v64);
+    cT = mem.alloc<T>(nn), lT = mem.alloc<T>(nn), uT = mem.alloc<T>(nn), bT = mem.alloc<T>(mm);
+    hipLaunchKernelGGL(k_scale_vectors<T>, dim3(grid_for(std::max(m, n))), dim3(kBlock), 0, stream, m, n,
+                       (const double *)c0, (const double *)l0, (const double *)u0, (const double *)b0,
+                       (const double *)Dr, (const double *)Dc, c64, l64, u64, b64, cT, lT, uT, bT);
+    HIPCHK(hipGetLastError());
+    // ---- per-instance scalars ----
+    nb = seg_reduce(0, d_row0, b0), nc = seg_reduce(0, d_col0, c0);
+    const std::vector<double> ncs = seg_reduce(0, d_col0, c64), nbs = seg_reduce(0, d_row0, b64);
+    const std::vector<double> amax = seg_reduce(1, d_nnz0, a_v64);
+    eta0.resize((size_t)K), omega_default.resize((size_t)K);
+    for (int q = 0; q < K; ++q) {
+      nb[q] = std::sqrt(nb[q]), nc[q] = std::sqrt(nc[q]);
+      const double a = std::sqrt(ncs[q]), bb = std::sqrt(nbs[q]);
+      omega_default[q] = (a > 1e-10 && bb > 1e-10) ? a / bb : 1.0;
+      eta0[q] = amax[q] > 0.0 ? 1.0 / amax[q] : 1.0;
+    }
+    mem.release(c0), mem.release(b0), mem.release(l0), mem.release(u0);
+    mem.release(rho), mem.release(kap), mem.release(cnt), mem.release(bsum), mem.release(row_of);
+
+    // iteration-precision copies of the matrix
+    if (sizeof(T) == sizeof(double)) {
+      a_v = reinterpret_cast<T *>(a_v64);
+      t_v = reinterpret_cast<T *>(t_v64);
+    } else {
+      a_v = mem.alloc<T>(nnz), t_v = mem.alloc<T>(nnz);
+      hipLaunchKernelGGL(k_convert<T>, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, (int64_t)nnz,
+                         (const double *)a_v64, a_v);
+      hipLaunchKernelGGL(k_convert<T>, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, (int64_t)nnz,
+                         (const double *)t_v64, t_v);
+    }
+
+    // iterates and staging
+    for (int q = 0; q < 2; ++q) xs[q] = mem.alloc<T>(nn), ys[q] = mem.alloc<T>(mm), axs[q] = mem.alloc<T>(mm);
+    aty = mem.alloc<T>(nn), xbar = mem.alloc<T>(nn), atybar = mem.alloc<T>(nn), xa = mem.alloc<T>(nn);
+    ybar = mem.alloc<T>(mm), axbar = mem.alloc<T>(mm), ya = mem.alloc<T>(mm);
+    tmp_n = mem.alloc<T>(nn), tmp_m = mem.alloc<T>(mm);
+    xd = mem.alloc<double>(nn), yd = mem.alloc<double>(mm), ax64 = mem.alloc<double>(mm), aty64 = mem.alloc<double>(nn);
+    x_out = mem.alloc<double>(nn), y_out = mem.alloc<double>(mm), rc_out = mem.alloc<double>(nn);
+    stage_n = mem.alloc<double>(nn), stage_m = mem.alloc<double>(mm);
+    for (int q = 0; q < 2; ++q) {
+      HIPCHK(hipMemsetAsync(xs[q], 0, sizeof(T) * (size_t)nn, stream));
+      HIPCHK(hipMemsetAsync(ys[q], 0, sizeof(T) * (size_t)mm, stream));
+      HIPCHK(hipMemsetAsync(axs[q], 0, sizeof(T) * (size_t)mm, stream));
+    }
+    for (T *p : {aty, xbar, atybar, xa, tmp_n}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)nn, stream));
+    for (T *p : {ybar, axbar, ya, tmp_m}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)mm, stream));
+    HIPCHK(hipMemsetAsync(st, 0, sizeof(State) * (size_t)K, stream));
+
+    // ---- SpMV schedule, row-average and evaluation blocks ----
+    choose_schedule();
+    std::vector<int32_t> ra_inst, ev_inst;
+    h_ra0.assign(1, 0), h_ev0.assign(1, 0);
+    for (int q = 0; q < K; ++q) {
+      const int32_t mq = h_row0[q + 1] - h_row0[q], nq = h_col0[q + 1] - h_col0[q];
+      const int ra = (mq + kRowAvgSpan - 1) / kRowAvgSpan;
+      for (int r = 0; r < ra; ++r) ra_inst.push_back(q);
+      h_ra0.push_back(h_ra0.back() + ra);
+      const int ev = grid_for(std::max(mq, nq), kEvalSpan / kBlock, 2048);
+      for (int r = 0; r < ev; ++r) ev_inst.push_back(q);
+      h_ev0.push_back(h_ev0.back() + ev);
+    }
+    ra_blocks = h_ra0.back(), ev_blocks = h_ev0.back();
+    if (!ra_inst.empty()) d_ra_inst = alloc_upload(ra_inst);
+    else d_ra_inst = mem.alloc<int32_t>(1);
+    d_ra0 = alloc_upload(h_ra0);
+    d_ev_inst = alloc_upload(ev_inst);
+    d_ev0 = alloc_upload(h_ev0);
+    const int64_t need = std::max<int64_t>({(int64_t)a_ntiles * 2, (int64_t)(t_ntiles + ra_blocks),
+                                            (int64_t)ev_blocks * kEvalNV, 16});
+    partials = mem.alloc<double>(need);
+    set_params();
+    sync();
+  }
+
+  void set_params() {
+    Layout &L = P.L;
+    L.K = K;
+    L.row0 = d_row0, L.col0 = d_col0, L.a_tile0 = d_a_tile0, L.t_tile0 = d_t_tile0;
+    L.a_tile_inst = d_a_tile_inst, L.t_tile_inst = d_t_tile_inst, L.ra_blk0 = d_ra0, L.ra_inst = d_ra_inst;
+    L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
+    L.a_ntiles = a_ntiles, L.t_ntiles = t_ntiles, L.ra_blocks = ra_blocks, L.ev_blocks = ev_blocks;
+    P.a_rp = a_rp, P.a_ci = a_ci, P.a_tiles = a_tiles, P.a_val = a_v;
+    P.t_rp = t_rp, P.t_ci = t_ci, P.t_tiles = t_tiles, P.t_val = t_v;
+    P.c = cT, P.l = lT, P.u = uT, P.b = bT, P.sense = sense, P.Dr = Dr, P.Dc = Dc;
+    for (int q = 0; q < 2; ++q) P.x[q] = xs[q], P.y[q] = ys[q], P.ax[q] = axs[q];
+    P.aty = aty, P.xbar = xbar, P.ybar = ybar, P.axbar = axbar, P.atybar = atybar, P.xa = xa, P.ya = ya;
+    P.partials = partials, P.st = st, P.ndone = ndone;
+  }
+
+  // ---------------------------------------------------------------------------------------------
+  // SpMV schedule
+  // ---------------------------------------------------------------------------------------------
+  void make_tiles(int tn) {
+    std::vector<int32_t> ta(1, 0), tt(1, 0), ta_inst, tt_inst;
+    h_a_tile0.assign(1, 0), h_t_tile0.assign(1, 0);
+    for (int q = 0; q < K; ++q) {
+      size_t before = ta.size();
+      build_tiles(h_arp.data(), h_row0[q], h_row0[q + 1], tn, ta);
+      for (size_t s = before; s < ta.size(); ++s) ta_inst.push_back(q);
+      h_a_tile0.push_back((int32_t)ta.size() - 1);
+      before = tt.size();
+      build_tiles(h_trp.data(), h_col0[q], h_col0[q + 1], tn, tt);
+      for (size_t s = before; s < tt.size(); ++s) tt_inst.push_back(q);
+      h_t_tile0.push_back((int32_t)tt.size() - 1);
+    }
+    for (int32_t *p : {a_tiles, t_tiles, d_a_tile_inst, d_t_tile_inst, d_a_tile0, d_t_tile0})
+      if (p) mem.release(p);
+    a_tiles = alloc_upload(ta), t_tiles = alloc_upload(tt);
+    d_a_tile_inst = alloc_upload(ta_inst), d_t_tile_inst = alloc_upload(tt_inst);
+    d_a_tile0 = alloc_upload(h_a_tile0), d_t_tile0 = alloc_upload(h_t_tile0);
+    a_ntiles = (int)ta.size() - 1, t_ntiles = (int)tt.size() - 1;
+    tile_nnz = tn;
+  }
+
+  template <typename V, typename X, typename Acc, typename Y>
+  void spmv_tiles(int trans, int tile_begin, int tile_end, const X *x, Y *y) {
+    const int32_t *rp = trans ? t_rp : a_rp;
+    const int32_t *ci = trans ? t_ci : a_ci;
+    const V *v;
+    if constexpr (sizeof(V) == sizeof(double)) v = (const V *)(trans ? t_v64 : a_v64);
+    else v = (const V *)(trans ? t_v : a_v);
+    const int32_t *tl = (trans ? t_tiles : a_tiles) + tile_begin;
+    const int nt = tile_end - tile_begin;
+    if (nt <= 0) return;
+    switch (tile_nnz) {
+#define CASE(TN)                                                                                           \
+  case TN:                                                                                                  \
+    hipLaunchKernelGGL((k_spmv<V, X, Acc, Y, TN>), dim3(nt), dim3(kBlock), 0, stream, rp, ci, v, tl, nt, x, y); \
+    break;
+      CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+      default:
+        raise(PDLP_ERR_ARG, "unsupported tile size");
+    }
+  }
+  void spmv_T(int trans, const T *x, T *y) { spmv_tiles<T, T, T, T>(trans, 0, trans ? t_ntiles : a_ntiles, x, y); }
+
+  // Autotuner: time A x and A'y for each candidate tile size and keep the fastest (the smallest
+  // size within 3 % of the best). The choice is cached per sparsity signature.
+  void choose_schedule() {
+    if (opt.tile_nnz > 0) {
+      bool ok = false;
+      for (int c : kTileCandidates) ok |= (c == opt.tile_nnz);
+      if (!ok) raise(PDLP_ERR_ARG, "tile_nnz must be one of 512, 1024, 2048, 4096 (or 0 = autotune)");
+      make_tiles(opt.tile_nnz);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune_cache.find(sig);
+      if (it != g_tune_cache.end()) {
+        make_tiles(it->second);
+        return;
+      }
+    }
+    int pick = 2048;
+    if (nnz >= 200000) {
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      float best = 1e30f;
+      std::vector<std::pair<int, float>> times;
+      for (int cand : kTileCandidates) {
+        make_tiles(cand);
+        spmv_T(0, xs[0], axs[0]);
+        spmv_T(1, ys[0], aty);
+        HIPCHK(hipEventRecord(e0, stream));
+        for (int r = 0; r < 5; ++r) {
+          spmv_T(0, xs[0], axs[0]);
+          spmv_T(1, ys[0], aty);
+        }
+        HIPCHK(hipEventRecord(e1, stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        times.push_back({cand, ms});
+        best = std::min(best, ms);
+      }
+      for (auto &t : times)
+        if (t.second <= best * 1.03f) {
+          pick = t.first;
+          break;
+        }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    make_tiles(pick);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[sig] = pick;
+  }
+
+  // ---------------------------------------------------------------------------------------------
+  // Iteration launches
+  // ---------------------------------------------------------------------------------------------
+  void launch_attempt() {
+    switch (tile_nnz) {
+#define CASE(TN)                                                                                       \
+  case TN:                                                                                              \
+    hipLaunchKernelGGL((k_dual<T, TN>), dim3(a_ntiles), dim3(kBlock), 0, stream, P);                    \
+    hipLaunchKernelGGL((k_primal<T, TN>), dim3(t_ntiles + ra_blocks), dim3(kBlock), 0, stream, P);      \
+    break;
+      CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+    }
+  }
+  void launch_eval(int mode) {
+    hipLaunchKernelGGL(k_eval<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, mode);
+  }
+  void launch_restart() { hipLaunchKernelGGL(k_restart<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P); }
+  void launch_chunk_body() {
+    for (int r = 0; r < opt.eval_every; ++r) launch_attempt();
+    launch_eval(kEvalChunk);
+    launch_restart();
+  }
+  void run_chunk() {
+    if (!opt.use_graphs) {
+      launch_chunk_body();
+      HIPCHK(hipGetLastError());
+      return;
+    }
+    if (!graph) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      launch_chunk_body();
+      HIPCHK(hipStreamEndCapture(stream, &g));
+      HIPCHK(hipGraphInstantiate(&graph, g, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(g));
+    }
+    HIPCHK(hipGraphLaunch(graph, stream));
+  }
+
+  // ---------------------------------------------------------------------------------------------
+  // Solve
+  // ---------------------------------------------------------------------------------------------
+  // Stage warm starts (original space; NULL entries = cold) and write the start point.
+  bool stage_start(const double *const *x0s, const double *const *y0s) {
+    bool any = false;
+    for (int q = 0; q < K; ++q) any |= (x0s && x0s[q]) || (y0s && y0s[q]);
+    if (!any) {
+      start_point(nullptr, nullptr, xs[0], ys[0]);
+      return false;
+    }
+    const hipMemcpyKind kind = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemsetAsync(stage_n, 0, sizeof(double) * (size_t)std::max(n, 1), stream));
+    HIPCHK(hipMemsetAsync(stage_m, 0, sizeof(double) * (size_t)std::max(m, 1), stream));
+    for (int q = 0; q < K; ++q) {
+      const int32_t nq = h_col0[q + 1] - h_col0[q], mq = h_row0[q + 1] - h_row0[q];
+      if (x0s && x0s[q] && nq)
+        HIPCHK(hipMemcpyAsync(stage_n + h_col0[q], x0s[q], sizeof(double) * (size_t)nq, kind, stream));
+      if (y0s && y0s[q] && mq)
+        HIPCHK(hipMemcpyAsync(stage_m + h_row0[q], y0s[q], sizeof(double) * (size_t)mq, kind, stream));
+    }
+    start_point(stage_n, stage_m, xs[0], ys[0]);
+    return true;
+  }
+  void start_point(const double *dx, const double *dy, T *x, T *y) {
+    hipLaunchKernelGGL(k_init_point<T>, dim3(grid_for(std::max(m, n))), dim3(kBlock), 0, stream, m, n, dx, dy,
+                       (const double *)Dr, (const double *)Dc, (const double *)l64, (const double *)u64,
+                       (const uint8_t *)sense, x, y);
+    HIPCHK(hipGetLastError());
+  }
+
+  void upload_state() { upload(st, h_st.data(), K); }
+  void read_state() {
+    download(h_st.data(), st, K);
+    sync();
+  }
+  int32_t count_done() {
+    int32_t c = 0;
+    for (auto &s : h_st) c += s.done;
+    return c;
+  }
+
+  void solve(double tol, int64_t iter_limit, const double *const *x0s, const double *const *y0s,
+             const double *omega0s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    iter_limit = std::max<int64_t>(iter_limit, 1);
+    for (int q = 0; q < K; ++q) {
+      State &s = h_st[q];
+      std::memset(&s, 0, sizeof(State));
+      s.eta = eta0[q];
+      s.omega = (omega0s && omega0s[q] > 0.0) ? omega0s[q] : omega_default[q];
+      s.tol = tol > 0.0 ? tol : -1.0;
+      s.nb = nb[q], s.nc = nc[q];
+      s.kkt_prev = INFINITY;
+      s.iter_limit = iter_limit;
+      s.eval_every = opt.eval_every;
+      s.restart_mode = kToCurrent;
+    }
+    upload_state();
+    HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));
+    const bool warm = stage_start(x0s, y0s);
+    std::vector<int> fallback((size_t)K, 0), warm_q((size_t)K, 0);
+    for (int q = 0; q < K; ++q) warm_q[q] = (x0s && x0s[q]) || (y0s && y0s[q]);
+    spmv_T(0, xs[0], axs[0]);
+    spmv_T(1, ys[0], aty);
+    if (warm && opt.warm_fallback) {
+      // cold start in the average slots; compare the relative KKT errors of both points
+      start_point(nullptr, nullptr, xbar, ybar);
+      spmv_T(0, xbar, axbar);
+      spmv_T(1, ybar, atybar);
+      launch_eval(kEvalPoint);
+      HIPCHK(hipGetLastError());
+      read_state();
+      bool any = false;
+      for (int q = 0; q < K; ++q)
+        if (warm_q[q] && !(h_st[q].cand_rel[0] < h_st[q].cand_rel[1])) {
+          fallback[q] = 1, any = true;
+          const int32_t nq = h_col0[q + 1] - h_col0[q], mq = h_row0[q + 1] - h_row0[q];
+          if (nq) HIPCHK(hipMemsetAsync(stage_n + h_col0[q], 0, sizeof(double) * (size_t)nq, stream));
+          if (mq) HIPCHK(hipMemsetAsync(stage_m + h_row0[q], 0, sizeof(double) * (size_t)mq, stream));
+          if (omega0s && omega0s[q] > 0.0) h_st[q].omega = omega_default[q];
+        }
+      if (any) {
+        start_point(stage_n, stage_m, xs[0], ys[0]);
+        spmv_T(0, xs[0], axs[0]);
+        spmv_T(1, ys[0], aty);
+        for (int q = 0; q < K; ++q) h_st[q].cnt[2] = 0;
+        upload_state();
+      }
+    }
+    launch_eval(kEvalInit);
+    launch_restart();
+    HIPCHK(hipGetLastError());
+
+    std::vector<int> checks((size_t)K, 0);
+    std::vector<double> tol_int((size_t)K, tol);
+    while (true) {
+      run_loop(iter_limit);
+      read_state();
+      finalize();
+      read_state();
+      bool resume = false;
+      for (int q = 0; q < K; ++q) {
+        State &s = h_st[q];
+        if (s.done != 1) continue;
+        const double rk = std::max(s.rel_p, std::max(s.rel_d, s.rel_gap));
+        if (checks[q] == 0 || s.status == PDLP_STATUS_OPTIMAL) checks[q] += (s.status != 0);
+        if (s.status == PDLP_STATUS_OPTIMAL && tol > 0.0 && !(rk <= tol)) {
+          if (checks[q] < 4 && s.k < iter_limit) {
+            // the FP64 recomputation from the FP64 matrix disagrees with the in-loop evaluation:
+            // continue this instance from the same state with a tighter internal tolerance
+            tol_int[q] *= 0.5;
+            s.done = 0, s.status = 0, s.stop = 0, s.tol = tol_int[q];
+            resume = true;
+          } else {
+            s.status = PDLP_STATUS_ITER_LIMIT;
+          }
+        }
+      }
+      if (!resume) break;
+      int32_t nd = count_done();
+      upload_state();
+      upload(ndone, &nd, 1);
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    const double secs = std::chrono::duration<double>(t1 - t0).count();
+    for (int q = 0; q < K; ++q) {
+      const State &s = h_st[q];
+      pdlp_result &r = last[q];
+      r = pdlp_result{};
+      r.status = s.status;
+      r.restarts = s.restarts;
+      r.iterations = s.k;
+      r.rel_primal = s.rel_p;
+      r.rel_dual = s.rel_d;
+      r.rel_gap = s.rel_gap;
+      r.primal_obj = s.pobj;
+      r.dual_obj = s.dobj;
+      r.omega = s.omega;
+      r.eta = s.eta;
+      r.solve_seconds = secs;
+      r.used_average = s.which;
+      r.warm_started = warm_q[q] && !fallback[q];
+      r.fallback_used = fallback[q];
+      r.final_checks = checks[q];
+    }
+    solved = true;
+    if (opt.verbose)
+      for (int q = 0; q < std::min(K, 8); ++q)
+        fprintf(stderr, "[pdlp] inst %d status %d iters %lld restarts %d rel_p %.3e rel_d %.3e gap %.3e obj %.10g (%.3f s)\n",
+                q, last[q].status, (long long)last[q].iterations, last[q].restarts, last[q].rel_primal,
+                last[q].rel_dual, last[q].rel_gap, last[q].primal_obj, secs);
+  }
+
+  // Launch evaluation intervals until every instance is done. Two intervals are kept in flight:
+  // the host waits for the done counter of interval c-1 while interval c runs; an interval launched
+  // after all instances finished does no work.
+  void run_loop(int64_t iter_limit) {
+    const int64_t max_chunks = iter_limit / opt.eval_every + 3;
+    for (int64_t ch = 0; ch < max_chunks; ++ch) {
+      run_chunk();
+      HIPCHK(hipMemcpyAsync(&h_flags[ch & 1], ndone, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipEventRecord(ev[ch & 1], stream));
+      if (ch >= 1) {
+        HIPCHK(hipEventSynchronize(ev[(ch - 1) & 1]));
+        if (h_flags[(ch - 1) & 1] >= K) break;
+      }
+    }
+    sync();
+  }
+
+  void finalize() {
+    hipLaunchKernelGGL(k_unscale<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, xd, yd, x_out, y_out);
+    spmv_tiles<double, double, double, double>(0, 0, a_ntiles, xd, ax64);
+    spmv_tiles<double, double, double, double>(1, 0, t_ntiles, yd, aty64);
+    Final64 F{xd, yd, ax64, aty64, c64, b64, l64, u64, rc_out};
+    hipLaunchKernelGGL(k_final_residuals<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, F);
+    HIPCHK(hipGetLastError());
+  }
+
+  void get(int q, double *x, double *y, double *rc, pdlp_result *res) {
+    if (!solved) raise(PDLP_ERR_STATE, "get before solve");
+    if (q < 0 || q >= K) raise(PDLP_ERR_ARG, "instance index out of range");
+    const hipMemcpyKind kind = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int32_t c0 = h_col0[q], nq = h_col0[q + 1] - c0, r0 = h_row0[q], mq = h_row0[q + 1] - r0;
+    if (x && nq) HIPCHK(hipMemcpyAsync(x, x_out + c0, sizeof(double) * (size_t)nq, kind, stream));
+    if (y && mq) HIPCHK(hipMemcpyAsync(y, y_out + r0, sizeof(double) * (size_t)mq, kind, stream));
+    if (rc && nq) HIPCHK(hipMemcpyAsync(rc, rc_out + c0, sizeof(double) * (size_t)nq, kind, stream));
+    sync();
+    if (res) *res = last[q];
+  }
+
+  // Original-space product y = A x = Dr^-1 A~ Dc^-1 x (trans = 0) or y = A'x (trans = 1).
+  void spmv(int trans, const double *x, double *y) {
+    const int in = trans ? m : n, out = trans ? n : m;
+    double *sin = trans ? stage_m : stage_n;
+    double *sout = trans ? stage_n : stage_m;
+    T *tin = trans ? tmp_m : tmp_n;
+    T *tout = trans ? tmp_n : tmp_m;
+    const hipMemcpyKind k_in = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind k_out = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (in) HIPCHK(hipMemcpyAsync(sin, x, sizeof(double) * (size_t)in, k_in, stream));
+    hipLaunchKernelGGL(k_div_to<T>, dim3(grid_for(in)), dim3(kBlock), 0, stream, in, (const double *)sin,
+                       (const double *)(trans ? Dr : Dc), tin);
+    spmv_T(trans, tin, tout);
+    hipLaunchKernelGGL(k_div_from<T>, dim3(grid_for(out)), dim3(kBlock), 0, stream, out, (const T *)tout,
+                       (const double *)(trans ? Dc : Dr), sout);
+    HIPCHK(hipGetLastError());
+    if (out) HIPCHK(hipMemcpyAsync(y, sout, sizeof(double) * (size_t)out, k_out, stream));
+    sync();
+  }
+
+  void get_scaling(double *dr, double *dc, double *sv, int32_t *trp, int32_t *tci, double *tv) {
+    if (dr) download(dr, Dr, m);
+    if (dc) download(dc, Dc, n);
+    if (sv) download(sv, a_v64, nnz);
+    if (trp) download(trp, t_rp, n + 1);
+    if (tci) download(tci, t_ci, nnz);
+    if (tv) download(tv, t_v64, nnz);
+    sync();
+  }
+};
+
+// Precision-erased handle.
+struct AnySolver {
+  std::unique_ptr<Solver<float>> f;
+  std::unique_ptr<Solver<double>> d;
+  template <typename F>
+  void visit(F &&fn) {
+    if (f) fn(*f);
+    else fn(*d);
+  }
+  void create(const std::vector<const HostProblem *> &H, const pdlp_options &o) {
+    if (o.precision == PDLP_FP64) {
+      d = std::make_unique<Solver<double>>();
+      d->create(H, o);
+    } else {
+      f = std::make_unique<Solver<float>>();
+      f->create(H, o);
+    }
+  }
+};
+
+}  // namespace pdlp
+
+// ================================================================================================
+// extern "C" boundary
+// ================================================================================================
+struct pdlp_problem {
+  pdlp::AnySolver s;
+};
+struct pdlp_batch {
+  pdlp::AnySolver s;
+  int32_t k = 0;
+};
+
+using pdlp::Error;
+
+template <typename F>
+static int guarded(F &&f) {
+  try {
+    f();
+    return PDLP_OK;
+  } catch (const Error &e) {
+    pdlp::g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    pdlp::g_last_error = "host allocation failed";
+    return PDLP_ERR_OOM;
+  } catch (...) {
+    pdlp::g_last_error = "unexpected C++ exception";
+    return PDLP_ERR_HIP;
+  }
+}
+
+static pdlp_options resolve_options(const pdlp_options *opt) {
+  pdlp_options o;
+  pdlp_options_default(&o);
+  if (opt) o = *opt;
+  if (o.eval_every <= 0) o.eval_every = 64;
+  if (o.ruiz_iters < 0) pdlp::raise(PDLP_ERR_ARG, "ruiz_iters < 0");
+  if (o.precision != PDLP_FP32 && o.precision != PDLP_FP64) pdlp::raise(PDLP_ERR_ARG, "unknown precision");
+  return o;
+}
+
+static void fetch_host_problem(pdlp::HostProblem &H, int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, const double *val, const double *c, const double *b,
+                               const char *sense, const double *l, const double *u, bool device) {
+  using pdlp::raise;
+  if (m < 0 || n < 0 || nnz < 0) raise(PDLP_ERR_ARG, "negative size");
+  if (!row_ptr || (nnz > 0 && (!col_idx || !val)) || (n > 0 && (!c || !l || !u)) || (m > 0 && (!b || !sense)))
+    raise(PDLP_ERR_ARG, "NULL data pointer");
+  if (nnz >= (int64_t)INT32_MAX) raise(PDLP_ERR_ARG, "nnz must be below 2^31");
+  H.m = m, H.n = n, H.nnz = nnz;
+  H.rp.resize((size_t)m + 1), H.ci.resize((size_t)nnz), H.val.resize((size_t)nnz);
+  H.c.resize((size_t)n), H.l.resize((size_t)n), H.u.resize((size_t)n), H.b.resize((size_t)m), H.sense.resize((size_t)m);
+  auto cp = [&](void *dst, const void *src, size_t bytes) {
+    if (!bytes) return;
+    if (device) {
+      hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) raise(PDLP_ERR_HIP, std::string("reading device input: ") + hipGetErrorString(e));
+    } else {
+      std::memcpy(dst, src, bytes);
+    }
+  };
+  cp(H.rp.data(), row_ptr, sizeof(int32_t) * ((size_t)m + 1));
+  cp(H.ci.data(), col_idx, sizeof(int32_t) * (size_t)nnz);
+  cp(H.val.data(), val, sizeof(double) * (size_t)nnz);
+  cp(H.c.data(), c, sizeof(double) * (size_t)n);
+  cp(H.l.data(), l, sizeof(double) * (size_t)n);
+  cp(H.u.data(), u, sizeof(double) * (size_t)n);
+  cp(H.b.data(), b, sizeof(double) * (size_t)m);
+  cp(H.sense.data(), sense, (size_t)m);
+  pdlp::validate(H);
+}
+
+extern "C" {
+
+void pdlp_options_default(pdlp_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = PDLP_FP32;
+  o->eval_every = 64;
+  o->ruiz_iters = 10;
+  o->pock_chambolle = 1;
+  o->use_graphs = 1;
+  o->device_ptrs = 0;
+  o->tile_nnz = 0;
+  o->verbose = 0;
+  o->device_mem_limit = 0;
+  o->stream = nullptr;
+  o->warm_fallback = 1;
+}
+
+const char *pdlp_error_string(int code) {
+  switch (code) {
+    case PDLP_OK: return "ok";
+    case PDLP_ERR_ARG: return "invalid argument";
+    case PDLP_ERR_CSR: return "malformed CSR matrix";
+    case PDLP_ERR_OOM: return "out of device memory";
+    case PDLP_ERR_HIP: return "HIP runtime error";
+    case PDLP_ERR_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+const char *pdlp_last_error(void) { return pdlp::g_last_error.c_str(); }
+
+int pdlp_create(pdlp_problem **out, int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                const int32_t *col_idx, const double *val, const double *c, const double *b, const char *sense,
+                const double *l, const double *u, const pdlp_options *opt) {
+  if (!out) {
+    pdlp::g_last_error = "out is NULL";
+    return PDLP_ERR_ARG;
+  }
+  *out = nullptr;
+  return guarded([&] {
+    const pdlp_options o = resolve_options(opt);
+    pdlp::HostProblem H;
+    fetch_host_problem(H, m, n, nnz, row_ptr, col_idx, val, c, b, sense, l, u, o.device_ptrs != 0);
+    auto p = std::make_unique<pdlp_problem>();
+    p->s.create({&H}, o);
+    *out = p.release();
+  });
+}
+
+int pdlp_solve(pdlp_problem *p, double tol, int64_t iter_limit, const double *x0, const double *y0, double omega0) {
+  if (!p || iter_limit <= 0 || std::isnan(tol) || std::isnan(omega0)) {
+    pdlp::g_last_error = !p ? "NULL handle" : "iter_limit must be positive; tol / omega0 not NaN";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    const double *xs[1] = {x0}, *ys[1] = {y0};
+    const double om[1] = {omega0};
+    p->s.visit([&](auto &s) { s.solve(tol, iter_limit, xs, ys, om); });
+  });
+}
+
+int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_result *res) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { s.get(0, x, y, red_cost, res); }); });
+}
+
+int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y) {
+  if (!p || !x || !y || (trans != 0 && trans != 1)) {
+    pdlp::g_last_error = "bad argument to pdlp_spmv";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { s.spmv(trans, x, y); }); });
+}
+
+int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val, int32_t *t_row_ptr,
+                     int32_t *t_col, double *t_val) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { s.get_scaling(Dr, Dc, scaled_val, t_row_ptr, t_col, t_val); }); });
+}
+
+int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    p->s.visit([&](auto &s) {
+      if (tile_nnz) *tile_nnz = s.tile_nnz;
+      if (tiles_a) *tiles_a = s.a_ntiles;
+      if (tiles_at) *tiles_at = s.t_ntiles;
+    });
+  });
+}
+
+int64_t pdlp_device_bytes(const pdlp_problem *p) {
+  if (!p) return 0;
+  int64_t r = 0;
+  const_cast<pdlp_problem *>(p)->s.visit([&](auto &s) { r = s.mem.used; });
+  return r;
+}
+
+void pdlp_destroy(pdlp_problem *p) { delete p; }
+
+int pdlp_batch_create(pdlp_batch **out, int32_t k, const pdlp_problem_desc *descs, const pdlp_options *opt) {
+  if (!out || k <= 0 || !descs) {
+    pdlp::g_last_error = "bad argument to pdlp_batch_create";
+    return PDLP_ERR_ARG;
+  }
+  *out = nullptr;
+  return guarded([&] {
+    const pdlp_options o = resolve_options(opt);
+    std::vector<pdlp::HostProblem> H((size_t)k);
+    std::vector<const pdlp::HostProblem *> ptrs;
+    for (int32_t q = 0; q < k; ++q) {
+      const pdlp_problem_desc &d = descs[q];
+      fetch_host_problem(H[q], d.m, d.n, d.nnz, d.row_ptr, d.col_idx, d.val, d.c, d.b, d.sense, d.l, d.u,
+                         o.device_ptrs != 0);
+      ptrs.push_back(&H[q]);
+    }
+    auto p = std::make_unique<pdlp_batch>();
+    p->k = k;
+    p->s.create(ptrs, o);
+    *out = p.release();
+  });
+}
+
+int pdlp_batch_solve(pdlp_batch *bt, double tol, int64_t iter_limit, const double *const *x0s,
+                     const double *const *y0s, const double *omega0s) {
+  if (!bt || iter_limit <= 0 || std::isnan(tol)) {
+    pdlp::g_last_error = "bad argument to pdlp_batch_solve";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { bt->s.visit([&](auto &s) { s.solve(tol, iter_limit, x0s, y0s, omega0s); }); });
+}
+
+int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_cost, pdlp_result *res) {
+  if (!bt) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { bt->s.visit([&](auto &s) { s.get(i, x, y, red_cost, res); }); });
+}
+
+void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libpdlp.
+//
+// One handle solves K >= 1 independent LPs. Their matrices are stored as one block-diagonal CSR
+// (and its transpose) with global row/column indices; every launch covers all instances, and each
+// block looks up the instance it works for. A single-LP handle is the case K = 1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdlp {
+
+constexpr int kBlock = 256;   // threads per block for every kernel
+constexpr int kWave = 64;     // CDNA wavefront
+constexpr int kWaves = kBlock / kWave;
+constexpr int kEvalNV = 18;   // per-block partial sums of the evaluation kernel
+constexpr int kRowAvgSpan = 2048;  // rows per row-average block in the primal kernel
+constexpr int kEvalSpan = 2048;    // elements per evaluation block (target)
+
+enum RestartMode : int32_t { kNoRestart = 0, kToCurrent = 1, kToAverage = 2 };
+enum EvalMode : int32_t { kEvalInit = 0, kEvalChunk = 1, kEvalPoint = 2 };
+
+// Per-instance solver state on the device. Written only by the last block of an instance in a
+// kernel (or by the host between solves); read by every block of that instance at kernel start.
+struct State {
+  double eta;         // step size of the next attempt (scaled space)
+  double omega;       // primal weight
+  double wsum;        // sum of accepted step sizes since the last restart
+  double avg_w;       // weight eta/wsum of the pending average update
+  double dx2;         // |x' - x|^2 of the pending primal candidate
+  double kkt_anchor;  // weighted KKT error of the last restart point
+  double kkt_prev;    // weighted KKT error of the previous restart candidate
+  double tol;         // relative KKT tolerance (<= 0: never met)
+  double rel_p, rel_d, rel_gap, pobj, dobj;  // last evaluated point (original space)
+  double cand_rel[2]; // relative KKT error of current [0] / average [1] at the last evaluation
+  double nb, nc;      // |b|, |c| of the original data
+  int64_t k;          // attempts so far
+  int64_t last_restart;
+  int64_t iter_limit;
+  int32_t cur;        // which buffer of x/y/ax holds the committed iterate
+  int32_t commit;     // 1: the last attempt was accepted and awaits the transposed product
+  int32_t stop;       // 1: finish after the pending commit / restart
+  int32_t done;       // 1: no further work
+  int32_t status;     // PDLP_STATUS_*
+  int32_t which;      // returned point: 0 current, 1 average
+  int32_t restarts;
+  int32_t restart_mode;
+  int32_t eval_every;
+  int32_t pad_;
+  uint32_t cnt[8];    // arrival counters of the last-block reductions, one per kernel
+};
+
+// Instance layout tables (device arrays).
+struct Layout {
+  int32_t K;
+  const int32_t *row0, *col0;       // [K+1] row / column offsets
+  const int32_t *a_tile0, *t_tile0; // [K+1] tile ranges of A and A'
+  const int32_t *a_tile_inst;       // [a_ntiles] instance of each tile of A
+  const int32_t *t_tile_inst;       // [t_ntiles]
+  const int32_t *ra_blk0;           // [K+1] row-average block ranges (primal kernel)
+  const int32_t *ra_inst;           // [ra_blocks]
+  const int32_t *ev_blk0;           // [K+1] evaluation block ranges
+  const int32_t *ev_inst;           // [ev_blocks]
+  int32_t a_ntiles, t_ntiles, ra_blocks, ev_blocks;
+};
+
+// Everything an iteration kernel reads or writes. Passed by value.
+template <typename T>
+struct Iter {
+  Layout L;
+  // A (row view) and A' (column view), scaled, in the iteration precision
+  const int32_t *a_rp, *a_ci, *a_tiles;
+  const T *a_val;
+  const int32_t *t_rp, *t_ci, *t_tiles;
+  const T *t_val;
+  // problem data, scaled
+  const T *c, *l, *u, *b;
+  const uint8_t *sense;
+  const double *Dr, *Dc;
+  // iterates
+  T *x[2], *y[2], *ax[2];
+  T *aty;
+  T *xbar, *ybar, *axbar, *atybar;
+  T *xa, *ya;
+  // reductions and state
+  double *partials;
+  State *st;
+  int32_t *ndone;  // number of instances with done == 1
+};
+
+}  // namespace pdlp

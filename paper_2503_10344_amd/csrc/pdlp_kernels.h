@@ -1,0 +1,945 @@
+// HIP kernels of libpdlp for gfx950 (CDNA4, wave64).
+//
+// Iteration kernels (one PDHG attempt = k_dual then k_primal; every eval_every attempts k_eval then
+// k_restart), setup kernels (transpose, scan, scaling) and finalize kernels. All reductions are
+// deterministic: fixed per-thread order, fixed wave/block trees, block partials summed in block
+// order by the last block to arrive.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pdlp_internal.h"
+
+namespace pdlp {
+
+// ----------------------------------------------------------------------------------------------
+// Small device helpers
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T clipv(T x, T lo, T hi) {
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
+// Projection onto the dual sign set of a row: 'G' -> [0, inf), 'L' -> (-inf, 0], 'E' -> R.
+template <typename T>
+__device__ __forceinline__ T proj_dual(T y, uint8_t s) {
+  if (s == 'G') return y > T(0) ? y : T(0);
+  if (s == 'L') return y < T(0) ? y : T(0);
+  return y;
+}
+
+// Primal residual of a row given b - a'x.
+__device__ __forceinline__ double row_violation(double t, uint8_t s) {
+  if (s == 'G') return t > 0.0 ? t : 0.0;
+  if (s == 'L') return t < 0.0 ? t : 0.0;
+  return t;
+}
+
+// Projection of g onto the reduced-cost set fixed by which bounds are finite.
+__device__ __forceinline__ double proj_reduced(double g, double lo, double hi) {
+  const bool lf = isfinite(lo), uf = isfinite(hi);
+  if (lf && uf) return g;
+  if (lf) return g > 0.0 ? g : 0.0;
+  if (uf) return g < 0.0 ? g : 0.0;
+  return 0.0;
+}
+
+// Contribution of one column to the dual objective: l lambda^+ - u lambda^-.
+__device__ __forceinline__ double bound_term(double lo, double hi, double lam) {
+  double t = 0.0;
+  if (isfinite(lo) && lam > 0.0) t += lo * lam;
+  if (isfinite(hi) && lam < 0.0) t += hi * lam;
+  return t;
+}
+
+template <typename A>
+__device__ __forceinline__ A wave_sum(A v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block-wide sum of NV doubles; the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double red[NV * kWaves];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q * kWaves + wid] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = red[q * kWaves];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) s += red[q * kWaves + w];
+      v[q] = s;
+    }
+  }
+}
+
+template <typename A>
+__device__ __forceinline__ A block_sum_scalar(A v) {
+  __shared__ A red1[kWaves];
+  v = wave_sum(v);
+  const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  __syncthreads();
+  if (lane == 0) red1[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A s = red1[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s += red1[w];
+    v = s;
+  }
+  return v;
+}
+
+// Returns true in every thread of the last of `expected` blocks to arrive; that block then sees all
+// partials written by the others. The counter is reset for the next launch.
+__device__ __forceinline__ bool last_block(uint32_t *counter, uint32_t expected) {
+  __shared__ int am_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = atomicAdd(counter, 1u);
+    am_last = (prev == expected - 1) ? 1 : 0;
+    if (am_last) *counter = 0u;
+  }
+  __syncthreads();
+  const bool r = am_last != 0;
+  if (r) __threadfence();
+  return r;
+}
+
+// Sum of per-block partials [b0, b1) x [NV] in a fixed order; valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void final_sum(const double *partials, int b0, int b1, double (&out)[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) out[q] = 0.0;
+  for (int bidx = b0 + (int)threadIdx.x; bidx < b1; bidx += kBlock) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] += partials[(size_t)bidx * NV + q];
+  }
+  block_sum<NV>(out);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs. Give every XCD a contiguous range of
+// tiles so that neighbouring tiles (which gather neighbouring parts of x in structured matrices)
+// share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  constexpr int kXcd = 8;
+  if (nb < kXcd) return bid;
+  const int xcd = bid % kXcd, local = bid / kXcd;
+  const int base = nb / kXcd, extra = nb % kXcd;
+  return xcd * base + (xcd < extra ? xcd : extra) + local;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Tile SpMV engine.
+//
+// A tile is either a run of consecutive rows holding at most TN nonzeros and at most kBlock rows
+// (stream tile) or one row longer than TN (long tile). Stream tiles stage the products
+// val[e] * x[col[e]] in LDS with coalesced loads of val/col, then G = largest power of two with
+// G * rows <= kBlock (G <= 64) lanes reduce each row from LDS and a G-lane shuffle tree finishes
+// it. A long row is split over the whole block with a wave-shuffle + LDS reduction. The epilogue
+// epi(row, sum) runs in exactly one thread per row.
+// ----------------------------------------------------------------------------------------------
+template <typename V, typename X, typename Acc, int TN, typename Epi>
+__device__ __forceinline__ void tile_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                          const V *__restrict__ val, const X *__restrict__ x, int r0,
+                                          int r1, Acc *lds, Epi &&epi) {
+  const int tid = threadIdx.x;
+  const int k0 = rp[r0], k1 = rp[r1];
+  const int nt = k1 - k0;
+  if (nt > TN) {  // long row (r1 == r0 + 1)
+    Acc s = Acc(0);
+    for (int e = k0 + tid; e < k1; e += kBlock) s += Acc(val[e]) * Acc(x[ci[e]]);
+    s = block_sum_scalar(s);
+    if (tid == 0) epi(r0, s);
+    return;
+  }
+#pragma unroll
+  for (int it = 0; it < TN / kBlock; ++it) {
+    const int e = it * kBlock + tid;
+    if (e < nt) lds[e] = Acc(val[k0 + e]) * Acc(x[ci[k0 + e]]);
+  }
+  __syncthreads();
+  const int R = r1 - r0;
+  int G = kWave;
+  while (G > 1 && G * R > kBlock) G >>= 1;
+  const int row = tid / G, lane = tid & (G - 1);
+  Acc s = Acc(0);
+  if (row < R) {
+    const int rs = rp[r0 + row] - k0, re = rp[r0 + row + 1] - k0;
+    for (int e = rs + lane; e < re; e += G) s += lds[e];
+  }
+  for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+  if (row < R && lane == 0) epi(r0 + row, s);
+}
+
+// y = A x on a tile schedule (plain store epilogue).
+template <typename V, typename X, typename Acc, typename Y, int TN>
+__global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const V *__restrict__ val, const int32_t *__restrict__ tiles,
+                                                 int ntiles, const X *__restrict__ x, Y *__restrict__ y) {
+  __shared__ Acc lds[TN];
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  if (tile >= ntiles) return;
+  tile_spmv<V, X, Acc, TN>(rp, ci, val, x, tiles[tile], tiles[tile + 1], lds,
+                           [&](int i, Acc s) { y[i] = Y(s); });
+}
+
+__device__ __forceinline__ void mark_done(State *st, int32_t *ndone) {
+  if (!st->done) {
+    st->done = 1;
+    atomicAdd(ndone, 1);
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// One PDHG attempt, part 1: A x' fused with the dual update and the step-size decision.
+//   ax'_i = (A x')_i ;  y'_i = proj_Y(y_i + sigma (b_i - 2 ax'_i + ax_i)), sigma = eta * omega
+//   partial sums of |dy|^2 and dy'(ax' - ax); the instance's last block applies the adaptive step
+//   rule: eta_bar = (omega |dx|^2 + |dy|^2 / omega) / (2 |dy'(A dx)|), accept iff eta <= eta_bar,
+//   eta <- min((1 - (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta).
+// Grid: one block per tile of A (every instance owns at least one, possibly empty, tile).
+// ----------------------------------------------------------------------------------------------
+__device__ inline void step_size_rule(State *st, int32_t *ndone, double dy2, double inter) {
+  const double eta = st->eta, omega = st->omega;
+  const double denom = 2.0 * fabs(inter);
+  const double eta_bar = denom > 0.0 ? (omega * st->dx2 + dy2 / omega) / denom : INFINITY;
+  const int64_t k = st->k + 1;
+  st->k = k;
+  const double kk = (double)(k + 1);
+  const double eta_new = fmin((1.0 - pow(kk, -0.3)) * eta_bar, (1.0 + pow(kk, -0.6)) * eta);
+  if (eta <= eta_bar) {
+    st->cur ^= 1;
+    st->wsum += eta;
+    st->avg_w = eta / st->wsum;
+    st->commit = 1;
+  } else {
+    st->commit = 0;
+  }
+  st->eta = eta_new;
+  if (!isfinite(eta_new) || !(eta_new > 0.0)) {
+    st->status = 3;  // PDLP_STATUS_NUMERICAL
+    mark_done(st, ndone);
+  } else if (k >= st->iter_limit && (k % st->eval_every) != 0) {
+    st->status = 2;  // PDLP_STATUS_ITER_LIMIT
+    st->stop = 1;
+  }
+}
+
+template <typename T, int TN>
+__global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
+  __shared__ T lds[TN];
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = P.L.a_tile_inst[tile];
+  State *st = P.st + inst;
+  if (st->done | st->stop) return;
+  const int cur = st->cur;
+  const T sigma = T(st->eta * st->omega);
+  const T *__restrict__ xn = P.x[cur ^ 1];
+  const T *__restrict__ yc = P.y[cur];
+  const T *__restrict__ axc = P.ax[cur];
+  T *__restrict__ yn = P.y[cur ^ 1];
+  T *__restrict__ axn = P.ax[cur ^ 1];
+  const T *__restrict__ b = P.b;
+  const uint8_t *__restrict__ sense = P.sense;
+  double acc[2] = {0.0, 0.0};
+  tile_spmv<T, T, T, TN>(P.a_rp, P.a_ci, P.a_val, xn, P.a_tiles[tile], P.a_tiles[tile + 1], lds,
+                         [&](int i, T s) {
+                           const T yi = yc[i], axi = axc[i];
+                           const T ynew = proj_dual(yi + sigma * (b[i] - T(2) * s + axi), sense[i]);
+                           yn[i] = ynew;
+                           axn[i] = s;
+                           const double dy = double(ynew) - double(yi);
+                           acc[0] += dy * dy;
+                           acc[1] += dy * (double(s) - double(axi));
+                         });
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    P.partials[2 * tile] = acc[0];
+    P.partials[2 * tile + 1] = acc[1];
+  }
+  const int t0 = P.L.a_tile0[inst], t1 = P.L.a_tile0[inst + 1];
+  if (!last_block(&st->cnt[0], (uint32_t)(t1 - t0))) return;
+  double tot[2] = {0.0, 0.0};
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
+    tot[0] += P.partials[2 * t];
+    tot[1] += P.partials[2 * t + 1];
+  }
+  block_sum<2>(tot);
+  if (threadIdx.x == 0) step_size_rule(st, P.ndone, tot[0], tot[1]);
+}
+
+// ----------------------------------------------------------------------------------------------
+// One PDHG attempt, part 2: if the attempt was accepted, A'y' (committing it) and the weighted
+// averages (x_bar, A'y_bar here; y_bar, A x_bar in the row-average blocks); then the primal
+// candidate of the next attempt x' = proj_[l,u](x - tau (c - A'y)), tau = eta / omega, and
+// |x' - x|^2. Grid: one block per tile of A', then the row-average blocks.
+// ----------------------------------------------------------------------------------------------
+template <typename T, int TN>
+__global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
+  __shared__ T lds[TN];
+  const int nt = P.L.t_ntiles;
+  const bool is_tile = (int)blockIdx.x < nt;
+  const int tile = is_tile ? xcd_remap(blockIdx.x, nt) : 0;
+  const int rblk = is_tile ? 0 : (int)blockIdx.x - nt;
+  const int inst = is_tile ? P.L.t_tile_inst[tile] : P.L.ra_inst[rblk];
+  State *st = P.st + inst;
+  if (st->done) return;
+  const int cur = st->cur, commit = st->commit, stop = st->stop;
+  const T tau = T(st->eta / st->omega);
+  const T w = T(st->avg_w);
+  const T *__restrict__ xc = P.x[cur];
+  T *__restrict__ xnx = P.x[cur ^ 1];
+  const T *__restrict__ yc = P.y[cur];
+  const T *__restrict__ c = P.c;
+  const T *__restrict__ lo = P.l;
+  const T *__restrict__ hi = P.u;
+  T *__restrict__ aty = P.aty;
+  T *__restrict__ xbar = P.xbar;
+  T *__restrict__ atybar = P.atybar;
+  double acc[1] = {0.0};
+  int pidx;
+  if (is_tile) {
+    pidx = tile;
+    const int r0 = P.t_tiles[tile], r1 = P.t_tiles[tile + 1];
+    auto primal = [&](int j, T atyj) {
+      const T xj = xc[j];
+      if (commit) {
+        xbar[j] += w * (xj - xbar[j]);
+        atybar[j] += w * (atyj - atybar[j]);
+      }
+      if (!stop) {
+        const T xnew = clipv(xj - tau * (c[j] - atyj), lo[j], hi[j]);
+        xnx[j] = xnew;
+        const double d = double(xnew) - double(xj);
+        acc[0] += d * d;
+      }
+    };
+    if (commit) {
+      tile_spmv<T, T, T, TN>(P.t_rp, P.t_ci, P.t_val, yc, r0, r1, lds, [&](int j, T s) {
+        aty[j] = s;
+        primal(j, s);
+      });
+    } else if (!stop) {
+      for (int j = r0 + (int)threadIdx.x; j < r1; j += kBlock) primal(j, aty[j]);
+    }
+  } else {
+    pidx = nt + rblk;
+    if (commit) {
+      const T *__restrict__ axc = P.ax[cur];
+      T *__restrict__ ybar = P.ybar;
+      T *__restrict__ axbar = P.axbar;
+      const int i0 = P.L.row0[inst] + (rblk - P.L.ra_blk0[inst]) * kRowAvgSpan;
+      const int i1 = min(P.L.row0[inst + 1], i0 + kRowAvgSpan);
+      for (int i = i0 + (int)threadIdx.x; i < i1; i += kBlock) {
+        ybar[i] += w * (yc[i] - ybar[i]);
+        axbar[i] += w * (axc[i] - axbar[i]);
+      }
+    }
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) P.partials[pidx] = acc[0];
+  const int t0 = P.L.t_tile0[inst], t1 = P.L.t_tile0[inst + 1];
+  const int q0 = nt + P.L.ra_blk0[inst], q1 = nt + P.L.ra_blk0[inst + 1];
+  if (!last_block(&st->cnt[1], (uint32_t)((t1 - t0) + (q1 - q0)))) return;
+  double tot[1] = {0.0};
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) tot[0] += P.partials[t];
+  for (int t = q0 + (int)threadIdx.x; t < q1; t += kBlock) tot[0] += P.partials[t];
+  block_sum<1>(tot);
+  if (threadIdx.x == 0) {
+    st->dx2 = tot[0];
+    st->commit = 0;
+    if (st->stop) mark_done(st, P.ndone);
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Evaluation every eval_every attempts, on the committed current iterate and the average:
+// residuals in scaled and original space, objectives, distances to the restart anchor (FP64).
+// The instance's last block applies termination, the restart test and the primal weight update.
+// Grid: the evaluation blocks of all instances (ev_blk0 / ev_inst).
+// ----------------------------------------------------------------------------------------------
+struct Cand {
+  double rp2, rp2o, by, dya2, rd2, rd2o, bt, cx, dxa2;
+};
+
+__device__ __forceinline__ void cand_errors(const Cand &q, double omega, double nb, double nc,
+                                            double &rel_p, double &rel_d, double &rel_gap,
+                                            double &pobj, double &dobj, double &kkt_w) {
+  pobj = q.cx;
+  dobj = q.by + q.bt;
+  const double gap = pobj - dobj;
+  rel_p = sqrt(q.rp2o) / (1.0 + nb);
+  rel_d = sqrt(q.rd2o) / (1.0 + nc);
+  rel_gap = fabs(gap) / (1.0 + fabs(pobj) + fabs(dobj));
+  kkt_w = sqrt(omega * omega * q.rp2 + q.rd2 / (omega * omega) + gap * gap);
+}
+
+__device__ inline void eval_logic(State *st, int32_t *ndone, const double *tot, int mode) {
+  Cand qc{tot[0], tot[1], tot[2], tot[3], tot[4], tot[5], tot[6], tot[7], tot[8]};
+  Cand qa{tot[9], tot[10], tot[11], tot[12], tot[13], tot[14], tot[15], tot[16], tot[17]};
+  double omega = st->omega;
+  double rc[5], ra[5], kwc, kwa;
+  cand_errors(qc, omega, st->nb, st->nc, rc[0], rc[1], rc[2], rc[3], rc[4], kwc);
+  cand_errors(qa, omega, st->nb, st->nc, ra[0], ra[1], ra[2], ra[3], ra[4], kwa);
+  const double kc = fmax(rc[0], fmax(rc[1], rc[2]));
+  const double ka = fmax(ra[0], fmax(ra[1], ra[2]));
+  st->cand_rel[0] = kc;
+  st->cand_rel[1] = ka;
+  if (mode != kEvalChunk) {
+    st->rel_p = rc[0], st->rel_d = rc[1], st->rel_gap = rc[2], st->pobj = rc[3], st->dobj = rc[4];
+    if (mode == kEvalInit) {
+      st->kkt_anchor = kwc;
+      st->kkt_prev = INFINITY;
+    }
+    return;
+  }
+  if (!isfinite(kc) && !isfinite(ka)) {
+    st->status = 3;
+    mark_done(st, ndone);
+    return;
+  }
+  const bool pass_c = kc <= st->tol, pass_a = ka <= st->tol;
+  if (pass_c || pass_a) {
+    const int which = (pass_a && (!pass_c || ka < kc)) ? 1 : 0;
+    const double *r = which ? ra : rc;
+    st->rel_p = r[0], st->rel_d = r[1], st->rel_gap = r[2], st->pobj = r[3], st->dobj = r[4];
+    st->which = which;
+    st->status = 1;
+    mark_done(st, ndone);
+    return;
+  }
+  const bool use_avg = kwa < kwc;
+  const double kkt_c = use_avg ? kwa : kwc;
+  const int64_t k = st->k;
+  const int64_t t_since = k - st->last_restart;
+  const bool restart = (kkt_c <= 0.2 * st->kkt_anchor) ||
+                       (kkt_c <= 0.8 * st->kkt_anchor && kkt_c > st->kkt_prev) ||
+                       ((double)t_since >= 0.36 * (double)k);
+  if (!restart) {
+    st->kkt_prev = kkt_c;
+    st->restart_mode = kNoRestart;
+  } else {
+    const Cand &q = use_avg ? qa : qc;
+    const double ddx = sqrt(q.dxa2), ddy = sqrt(q.dya2);
+    if (ddx > 1e-10 && ddy > 1e-10) omega = exp(0.5 * log(ddy / ddx) + 0.5 * log(omega));
+    st->omega = omega;
+    double t0, t1, t2, t3, t4, kw;
+    cand_errors(q, omega, st->nb, st->nc, t0, t1, t2, t3, t4, kw);
+    st->kkt_anchor = kw;
+    st->kkt_prev = INFINITY;
+    st->wsum = 0.0;
+    st->last_restart = k;
+    st->restarts += 1;
+    st->restart_mode = use_avg ? kToAverage : kToCurrent;
+  }
+  if (k >= st->iter_limit) {
+    st->status = 2;
+    st->rel_p = rc[0], st->rel_d = rc[1], st->rel_gap = rc[2], st->pobj = rc[3], st->dobj = rc[4];
+    st->which = 0;
+    if (st->restart_mode == kNoRestart) mark_done(st, ndone);
+    else st->stop = 1;
+  }
+}
+
+// Instance of an evaluation-type block and its local block index / count.
+struct EvBlock {
+  int inst, lb, nlb;
+};
+__device__ __forceinline__ EvBlock ev_block(const Layout &L) {
+  EvBlock e;
+  e.inst = L.ev_inst[blockIdx.x];
+  const int b0 = L.ev_blk0[e.inst];
+  e.lb = (int)blockIdx.x - b0;
+  e.nlb = L.ev_blk0[e.inst + 1] - b0;
+  return e;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eval(Iter<T> P, int mode) {
+  const EvBlock E = ev_block(P.L);
+  State *st = P.st + E.inst;
+  if (st->done) return;
+  const int cur = st->cur;
+  double a[kEvalNV];
+#pragma unroll
+  for (int q = 0; q < kEvalNV; ++q) a[q] = 0.0;
+  const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
+  const T *__restrict__ yc = P.y[cur];
+  const T *__restrict__ axc = P.ax[cur];
+  const int r1 = P.L.row0[E.inst + 1];
+  for (int i = P.L.row0[E.inst] + off; i < r1; i += gs) {
+    const double b = double(P.b[i]), dr = P.Dr[i], ya = double(P.ya[i]);
+    const uint8_t s = P.sense[i];
+    {
+      const double y = double(yc[i]);
+      const double t = row_violation(b - double(axc[i]), s);
+      const double to = t / dr, d = y - ya;
+      a[0] += t * t, a[1] += to * to, a[2] += b * y, a[3] += d * d;
+    }
+    {
+      const double y = double(P.ybar[i]);
+      const double t = row_violation(b - double(P.axbar[i]), s);
+      const double to = t / dr, d = y - ya;
+      a[9] += t * t, a[10] += to * to, a[11] += b * y, a[12] += d * d;
+    }
+  }
+  const T *__restrict__ xc = P.x[cur];
+  const int c1 = P.L.col0[E.inst + 1];
+  for (int j = P.L.col0[E.inst] + off; j < c1; j += gs) {
+    const double c = double(P.c[j]), lo = double(P.l[j]), hi = double(P.u[j]);
+    const double dc = P.Dc[j], xa = double(P.xa[j]);
+    {
+      const double x = double(xc[j]), g = c - double(P.aty[j]);
+      const double lam = proj_reduced(g, lo, hi), rd = g - lam, rdo = rd / dc, d = x - xa;
+      a[4] += rd * rd, a[5] += rdo * rdo, a[6] += bound_term(lo, hi, lam), a[7] += c * x, a[8] += d * d;
+    }
+    {
+      const double x = double(P.xbar[j]), g = c - double(P.atybar[j]);
+      const double lam = proj_reduced(g, lo, hi), rd = g - lam, rdo = rd / dc, d = x - xa;
+      a[13] += rd * rd, a[14] += rdo * rdo, a[15] += bound_term(lo, hi, lam), a[16] += c * x, a[17] += d * d;
+    }
+  }
+  block_sum<kEvalNV>(a);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < kEvalNV; ++q) P.partials[(size_t)blockIdx.x * kEvalNV + q] = a[q];
+  }
+  if (!last_block(&st->cnt[2], (uint32_t)E.nlb)) return;
+  double tot[kEvalNV];
+  final_sum<kEvalNV>(P.partials, (int)blockIdx.x - E.lb, (int)blockIdx.x - E.lb + E.nlb, tot);
+  if (threadIdx.x == 0) eval_logic(st, P.ndone, tot, mode);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Restart (also used once at start-up with kToCurrent): move the chosen candidate into the current
+// iterate, make it the anchor and the new average, then recompute the primal candidate with the
+// possibly new primal weight. Grid: the evaluation blocks.
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
+  const EvBlock E = ev_block(P.L);
+  State *st = P.st + E.inst;
+  if (st->done) return;
+  const int mode = st->restart_mode;
+  if (mode == kNoRestart) return;
+  const int cur = st->cur, stop = st->stop;
+  const T tau = T(st->eta / st->omega);
+  T *__restrict__ xc = P.x[cur];
+  T *__restrict__ xnx = P.x[cur ^ 1];
+  T *__restrict__ yc = P.y[cur];
+  T *__restrict__ axc = P.ax[cur];
+  double acc[1] = {0.0};
+  const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
+  const int c1 = P.L.col0[E.inst + 1];
+  for (int j = P.L.col0[E.inst] + off; j < c1; j += gs) {
+    T xj, atyj;
+    if (mode == kToAverage) {
+      xj = P.xbar[j], atyj = P.atybar[j];
+      xc[j] = xj, P.aty[j] = atyj;
+    } else {
+      xj = xc[j], atyj = P.aty[j];
+      P.xbar[j] = xj, P.atybar[j] = atyj;
+    }
+    P.xa[j] = xj;
+    if (!stop) {
+      const T xnew = clipv(xj - tau * (P.c[j] - atyj), P.l[j], P.u[j]);
+      xnx[j] = xnew;
+      const double d = double(xnew) - double(xj);
+      acc[0] += d * d;
+    }
+  }
+  const int r1 = P.L.row0[E.inst + 1];
+  for (int i = P.L.row0[E.inst] + off; i < r1; i += gs) {
+    T yi;
+    if (mode == kToAverage) {
+      yi = P.ybar[i];
+      yc[i] = yi, axc[i] = P.axbar[i];
+    } else {
+      yi = yc[i];
+      P.ybar[i] = yi, P.axbar[i] = axc[i];
+    }
+    P.ya[i] = yi;
+  }
+  block_sum<1>(acc);
+  if (threadIdx.x == 0) P.partials[blockIdx.x] = acc[0];
+  if (!last_block(&st->cnt[3], (uint32_t)E.nlb)) return;
+  double tot[1];
+  final_sum<1>(P.partials, (int)blockIdx.x - E.lb, (int)blockIdx.x - E.lb + E.nlb, tot);
+  if (threadIdx.x == 0) {
+    st->dx2 = tot[0];
+    st->restart_mode = kNoRestart;
+    if (st->stop) mark_done(st, P.ndone);
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Start point: x = proj_[l~,u~](x0 / Dc or 0), y = proj_Y(y0 / Dr or 0), rounded once to T.
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_point(int m, int n, const double *__restrict__ x0,
+                                                       const double *__restrict__ y0, const double *__restrict__ Dr,
+                                                       const double *__restrict__ Dc, const double *__restrict__ l64,
+                                                       const double *__restrict__ u64,
+                                                       const uint8_t *__restrict__ sense, T *__restrict__ x,
+                                                       T *__restrict__ y) {
+  const int gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+  for (int j = gt; j < n; j += gs) x[j] = T(clipv(x0 ? x0[j] / Dc[j] : 0.0, l64[j], u64[j]));
+  for (int i = gt; i < m; i += gs) y[i] = T(proj_dual(y0 ? y0[i] / Dr[i] : 0.0, sense[i]));
+}
+
+// ----------------------------------------------------------------------------------------------
+// Finalize: select each instance's returned point (current or average), unscale it, and recompute
+// its residuals in FP64 from the FP64 scaled matrix (ax64 = A~ x~, aty64 = A~' y~ computed by
+// k_spmv in FP64 in between). Grid: the evaluation blocks.
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_unscale(Iter<T> P, double *__restrict__ xd, double *__restrict__ yd,
+                                                    double *__restrict__ x_out, double *__restrict__ y_out) {
+  const EvBlock E = ev_block(P.L);
+  const State *st = P.st + E.inst;
+  const int cur = st->cur, which = st->which;
+  const T *__restrict__ x = which ? P.xbar : P.x[cur];
+  const T *__restrict__ y = which ? P.ybar : P.y[cur];
+  const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
+  for (int j = P.L.col0[E.inst] + off; j < P.L.col0[E.inst + 1]; j += gs) {
+    const double v = double(x[j]);
+    xd[j] = v;
+    x_out[j] = P.Dc[j] * v;
+  }
+  for (int i = P.L.row0[E.inst] + off; i < P.L.row0[E.inst + 1]; i += gs) {
+    const double v = double(y[i]);
+    yd[i] = v;
+    y_out[i] = P.Dr[i] * v;
+  }
+}
+
+// rc_out [n]: original-space reduced cost; the instance's last block stores the relative errors.
+struct Final64 {
+  const double *xd, *yd, *ax64, *aty64, *c64, *b64, *l64, *u64;
+  double *rc_out;
+};
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_final_residuals(Iter<T> P, Final64 F) {
+  const EvBlock E = ev_block(P.L);
+  State *st = P.st + E.inst;
+  double a[5] = {0, 0, 0, 0, 0};  // rp2o, rd2o, by, bt, cx
+  const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
+  for (int i = P.L.row0[E.inst] + off; i < P.L.row0[E.inst + 1]; i += gs) {
+    const double t = row_violation(F.b64[i] - F.ax64[i], P.sense[i]) / P.Dr[i];
+    a[0] += t * t;
+    a[2] += F.b64[i] * F.yd[i];
+  }
+  for (int j = P.L.col0[E.inst] + off; j < P.L.col0[E.inst + 1]; j += gs) {
+    const double g = F.c64[j] - F.aty64[j];
+    const double lam = proj_reduced(g, F.l64[j], F.u64[j]);
+    const double rdo = (g - lam) / P.Dc[j];
+    a[1] += rdo * rdo;
+    a[3] += bound_term(F.l64[j], F.u64[j], lam);
+    a[4] += F.c64[j] * F.xd[j];
+    F.rc_out[j] = g / P.Dc[j];
+  }
+  block_sum<5>(a);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) P.partials[(size_t)blockIdx.x * 5 + q] = a[q];
+  }
+  if (!last_block(&st->cnt[4], (uint32_t)E.nlb)) return;
+  double tot[5];
+  final_sum<5>(P.partials, (int)blockIdx.x - E.lb, (int)blockIdx.x - E.lb + E.nlb, tot);
+  if (threadIdx.x == 0) {
+    const double pobj = tot[4], dobj = tot[2] + tot[3];
+    st->rel_p = sqrt(tot[0]) / (1.0 + st->nb);
+    st->rel_d = sqrt(tot[1]) / (1.0 + st->nc);
+    st->rel_gap = fabs(pobj - dobj) / (1.0 + fabs(pobj) + fabs(dobj));
+    st->pobj = pobj;
+    st->dobj = dobj;
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Per-instance FP64 reductions used during set-up, one block per instance segment [s0[k], s0[k+1]):
+// kind 0 = sum of squares, kind 1 = max |v|.
+// ----------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_seg_reduce(int kind, const int32_t *__restrict__ s0,
+                                                       const double *__restrict__ v, double *__restrict__ out) {
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int i = s0[k] + (int)threadIdx.x; i < s0[k + 1]; i += kBlock) {
+    const double t = v[i];
+    acc = kind == 0 ? acc + t * t : fmax(acc, fabs(t));
+  }
+  __shared__ double red[kWaves];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const double o = __shfl_xor(acc, off, kWave);
+    acc = kind == 0 ? acc + o : fmax(acc, o);
+  }
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < kWaves; ++w) r = kind == 0 ? r + red[w] : fmax(r, red[w]);
+    out[k] = r;
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Set-up: transpose by counting sort (histogram, exclusive scan, scatter, per-column sort of the
+// scattered source positions so the result is deterministic, gather).
+// ----------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_expand_rows(int m, const int32_t *__restrict__ rp, int32_t *__restrict__ row_of) {
+  // one wave per row
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int nwaves = gridDim.x * kWaves;
+  for (int i = wave; i < m; i += nwaves)
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += kWave) row_of[e] = i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_histogram(int nnz, const int32_t *__restrict__ ci, int32_t *__restrict__ cnt) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < nnz; e += gridDim.x * kBlock) atomicAdd(&cnt[ci[e]], 1);
+}
+
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total. Blocks of kScanItems items.
+constexpr int kScanPer = 8;
+constexpr int kScanItems = kBlock * kScanPer;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *total) {
+  __shared__ int wsum[kWaves];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  int inc = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int t = __shfl_up(inc, off, kWave);
+    if (lane >= off) inc += t;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) wsum[wid] = inc;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    if (w < wid) base += wsum[w];
+    tot += wsum[w];
+  }
+  *total = tot;
+  return base + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_partial(int n, const int32_t *__restrict__ in, int32_t *__restrict__ bsum) {
+  const int base = blockIdx.x * kScanItems + threadIdx.x * kScanPer;
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q)
+    if (base + q < n) s += in[base + q];
+  int tot;
+  block_exclusive_scan(s, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_bsums(int nb, int32_t *__restrict__ bsum) {
+  int carry = 0;
+  for (int off = 0; off < nb; off += kBlock) {
+    const int i = off + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    int tot;
+    const int ex = block_exclusive_scan(v, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final(int n, const int32_t *__restrict__ in, const int32_t *__restrict__ bsum,
+                                                       int32_t *__restrict__ out) {
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+    return;
+  }
+  const int base = blockIdx.x * kScanItems + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    v[q] = base + q < n ? in[base + q] : 0;
+    s += v[q];
+  }
+  int tot;
+  int run = block_exclusive_scan(s, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kScanPer; ++q) {
+    if (base + q < n) out[base + q] = run;
+    run += v[q];
+  }
+  if (base <= n - 1 && n - 1 < base + kScanPer) out[n] = run;  // thread holding the last item
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(int nnz, const int32_t *__restrict__ ci, const int32_t *__restrict__ t_rp,
+                                                    int32_t *__restrict__ fill, int32_t *__restrict__ perm) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < nnz; e += gridDim.x * kBlock) {
+    const int j = ci[e];
+    const int p = t_rp[j] + atomicAdd(&fill[j], 1);
+    perm[p] = e;
+  }
+}
+
+// Sort every segment of length <= 32 in place (one thread per segment, insertion sort).
+__global__ __launch_bounds__(kBlock) void k_segsort_small(int nseg, const int32_t *__restrict__ sp, int32_t *__restrict__ d) {
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < nseg; s += gridDim.x * kBlock) {
+    const int a = sp[s], b = sp[s + 1];
+    if (b - a > 32 || b - a < 2) continue;
+    for (int i = a + 1; i < b; ++i) {
+      const int key = d[i];
+      int j = i - 1;
+      while (j >= a && d[j] > key) {
+        d[j + 1] = d[j];
+        --j;
+      }
+      d[j + 1] = key;
+    }
+  }
+}
+
+// Bitonic sort of the listed long segments, one block per segment. Segments whose padded length
+// fits kSortLds are sorted in LDS, longer ones in their slice of `scratch` (offset scr_off[q]).
+constexpr int kSortLds = 4096;
+__device__ void bitonic(int32_t *buf, int N) {
+  for (int k = 2; k <= N; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += kBlock) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const bool up = (i & k) == 0;
+          const int a = buf[i], b = buf[ixj];
+          if ((a > b) == up) {
+            buf[i] = b;
+            buf[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_segsort_large(const int32_t *__restrict__ seg_list, const int32_t *__restrict__ sp,
+                                                          int32_t *__restrict__ d, int32_t *__restrict__ scratch,
+                                                          const int64_t *__restrict__ scr_off) {
+  __shared__ int32_t lbuf[kSortLds];
+  const int s = seg_list[blockIdx.x];
+  const int a = sp[s], len = sp[s + 1] - a;
+  int N = 1;
+  while (N < len) N <<= 1;
+  int32_t *buf = N <= kSortLds ? lbuf : scratch + scr_off[blockIdx.x];
+  for (int i = threadIdx.x; i < N; i += kBlock) buf[i] = i < len ? d[a + i] : INT32_MAX;
+  __syncthreads();
+  bitonic(buf, N);
+  for (int i = threadIdx.x; i < len; i += kBlock) d[a + i] = buf[i];
+}
+
+// t_ci[p] = row of source entry perm[p]; t_val[p] = val[perm[p]]
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_gather_t(int nnz, const int32_t *__restrict__ perm, const int32_t *__restrict__ row_of,
+                                                     const V *__restrict__ val, int32_t *__restrict__ t_ci, V *__restrict__ t_val) {
+  for (int p = blockIdx.x * kBlock + threadIdx.x; p < nnz; p += gridDim.x * kBlock) {
+    const int e = perm[p];
+    if (t_ci) t_ci[p] = row_of[e];
+    t_val[p] = val[e];
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Set-up: equilibration. One wave per row reduces |a| (max or sum) over a row of A (direct) or a
+// row of A' (values gathered through perm).
+// ----------------------------------------------------------------------------------------------
+template <bool kSum>
+__global__ __launch_bounds__(kBlock) void k_row_norm(int rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ perm,
+                                                     const double *__restrict__ val, double *__restrict__ out) {
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int nwaves = gridDim.x * kWaves;
+  for (int r = wave; r < rows; r += nwaves) {
+    double acc = 0.0;
+    for (int e = rp[r] + lane; e < rp[r + 1]; e += kWave) {
+      const double v = fabs(val[perm ? perm[e] : e]);
+      acc = kSum ? acc + v : fmax(acc, v);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const double o = __shfl_xor(acc, off, kWave);
+      acc = kSum ? acc + o : fmax(acc, o);
+    }
+    if (lane == 0) out[r] = acc > 0.0 ? sqrt(acc) : 1.0;
+  }
+}
+
+// a_ij <- a_ij / (rho_i * kap_j); Dr /= rho; Dc /= kap
+__global__ __launch_bounds__(kBlock) void k_apply_scale(int nnz, const int32_t *__restrict__ row_of, const int32_t *__restrict__ ci,
+                                                        double *__restrict__ val, const double *__restrict__ rho,
+                                                        const double *__restrict__ kap) {
+  for (int e = blockIdx.x * kBlock + threadIdx.x; e < nnz; e += gridDim.x * kBlock)
+    val[e] = val[e] / (rho[row_of[e]] * kap[ci[e]]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_inplace(int n, double *__restrict__ d, const double *__restrict__ s) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = d[i] / s[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(int64_t n, double *__restrict__ d, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) d[i] = v;
+}
+
+// c~ = Dc c, l~ = l / Dc, u~ = u / Dc (infinite bounds stay infinite); b~ = Dr b. FP64 copies kept,
+// T copies rounded once.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_vectors(int m, int n, const double *__restrict__ c, const double *__restrict__ l,
+                                                          const double *__restrict__ u, const double *__restrict__ b,
+                                                          const double *__restrict__ Dr, const double *__restrict__ Dc,
+                                                          double *__restrict__ c64, double *__restrict__ l64,
+                                                          double *__restrict__ u64, double *__restrict__ b64, T *__restrict__ cT,
+                                                          T *__restrict__ lT, T *__restrict__ uT, T *__restrict__ bT) {
+  const int gt = blockIdx.x * kBlock + threadIdx.x, gs = gridDim.x * kBlock;
+  for (int j = gt; j < n; j += gs) {
+    const double cs = Dc[j] * c[j];
+    const double ls = isfinite(l[j]) ? l[j] / Dc[j] : l[j];
+    const double us = isfinite(u[j]) ? u[j] / Dc[j] : u[j];
+    c64[j] = cs, l64[j] = ls, u64[j] = us;
+    cT[j] = T(cs), lT[j] = T(ls), uT[j] = T(us);
+  }
+  for (int i = gt; i < m; i += gs) {
+    const double bs = Dr[i] * b[i];
+    b64[i] = bs;
+    bT[i] = T(bs);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_convert(int64_t n, const double *__restrict__ s, T *__restrict__ d) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) d[i] = T(s[i]);
+}
+
+// Original-space product helper: xs = x / D (scaled input, rounded to T) and y = ys / D.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_div_to(int n, const double *__restrict__ x, const double *__restrict__ D,
+                                                   T *__restrict__ out) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = T(x[i] / D[i]);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_div_from(int n, const T *__restrict__ y, const double *__restrict__ D,
+                                                     double *__restrict__ out) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) out[i] = double(y[i]) / D[i];
+}
+
+}  // namespace pdlp

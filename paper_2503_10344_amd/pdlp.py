@@ -1,0 +1,343 @@
+"""Thin Python binding of libpdlp (ctypes). Argument marshalling only: every step of the solve runs
+in the library's HIP kernels.
+
+The functions keep the C names (pdlp_create, pdlp_solve, pdlp_get, ...). `Problem` wraps a handle
+for convenience. PyTorch supplies streams and, optionally, device memory: tensors on the GPU may be
+passed directly (their data pointers are handed over with device_ptrs set).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdlp.so")
+
+FP32, FP64 = 0, 1
+STATUS = {0: "none", 1: "optimal", 2: "iteration_limit", 3: "numerical"}
+OPTIMAL, ITER_LIMIT, NUMERICAL = 1, 2, 3
+ERR = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_CSR", -3: "PDLP_ERR_OOM", -4: "PDLP_ERR_HIP", -5: "PDLP_ERR_STATE"}
+
+
+class PDLPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("eval_every", C.c_int32), ("ruiz_iters", C.c_int32),
+                ("pock_chambolle", C.c_int32), ("use_graphs", C.c_int32), ("device_ptrs", C.c_int32),
+                ("tile_nnz", C.c_int32), ("verbose", C.c_int32), ("device_mem_limit", C.c_int64),
+                ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
+                ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
+                ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("omega", C.c_double),
+                ("eta", C.c_double), ("solve_seconds", C.c_double), ("used_average", C.c_int32),
+                ("warm_started", C.c_int32), ("fallback_used", C.c_int32), ("final_checks", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["rel_kkt"] = max(self.rel_primal, self.rel_dual, self.rel_gap)
+        d["status_name"] = STATUS.get(self.status, str(self.status))
+        return d
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("val", C.c_void_p), ("c", C.c_void_p), ("b", C.c_void_p),
+                ("sense", C.c_void_p), ("l", C.c_void_p), ("u", C.c_void_p)]
+
+
+EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_spmv",
+           "pdlp_get_scaling", "pdlp_get_schedule", "pdlp_device_bytes", "pdlp_destroy",
+           "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
+           "pdlp_batch_get", "pdlp_batch_destroy"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpdlp.so. Raises if it has not been built: there is no fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpdlp.so not found at {path}; build it with "
+                           "`python -m paper_2503_10344_amd.build` (hipcc, gfx950)")
+    try:  # share torch's HIP runtime when torch is present (one runtime per process)
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    lib = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.pdlp_options_default.argtypes = [C.POINTER(Options)]
+    lib.pdlp_options_default.restype = None
+    lib.pdlp_create.argtypes = [C.POINTER(vp), i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options)]
+    lib.pdlp_create.restype = C.c_int
+    lib.pdlp_solve.argtypes = [vp, dp, i64, vp, vp, dp]
+    lib.pdlp_solve.restype = C.c_int
+    lib.pdlp_get.argtypes = [vp, vp, vp, vp, C.POINTER(Result)]
+    lib.pdlp_get.restype = C.c_int
+    lib.pdlp_spmv.argtypes = [vp, i32, vp, vp]
+    lib.pdlp_spmv.restype = C.c_int
+    lib.pdlp_get_scaling.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.pdlp_get_scaling.restype = C.c_int
+    lib.pdlp_get_schedule.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.pdlp_get_schedule.restype = C.c_int
+    lib.pdlp_device_bytes.argtypes = [vp]
+    lib.pdlp_device_bytes.restype = i64
+    lib.pdlp_destroy.argtypes = [vp]
+    lib.pdlp_destroy.restype = None
+    lib.pdlp_error_string.argtypes = [C.c_int]
+    lib.pdlp_error_string.restype = C.c_char_p
+    lib.pdlp_last_error.argtypes = []
+    lib.pdlp_last_error.restype = C.c_char_p
+    lib.pdlp_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(ProblemDesc), C.POINTER(Options)]
+    lib.pdlp_batch_create.restype = C.c_int
+    lib.pdlp_batch_solve.argtypes = [vp, dp, i64, C.POINTER(vp), C.POINTER(vp), vp]
+    lib.pdlp_batch_solve.restype = C.c_int
+    lib.pdlp_batch_get.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Result)]
+    lib.pdlp_batch_get.restype = C.c_int
+    lib.pdlp_batch_destroy.argtypes = [vp]
+    lib.pdlp_batch_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        lib = load()
+        raise PDLPError(rc, lib.pdlp_last_error().decode())
+
+
+def _ptr(a):
+    """Pointer of a numpy array or a torch tensor (None stays None)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
+            device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
+            warm_fallback=True) -> Options:
+    o = Options()
+    load().pdlp_options_default(C.byref(o))
+    o.precision = FP64 if str(precision).lower() in ("fp64", "f64", "double", "1") else FP32
+    o.eval_every = eval_every
+    o.ruiz_iters = ruiz_iters
+    o.pock_chambolle = 1 if pock_chambolle else 0
+    o.use_graphs = 1 if use_graphs else 0
+    o.device_ptrs = 1 if device_ptrs else 0
+    o.tile_nnz = tile_nnz
+    o.verbose = verbose
+    o.device_mem_limit = device_mem_limit
+    o.warm_fallback = 1 if warm_fallback else 0
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                stream = torch.cuda.current_stream().cuda_stream
+        except Exception:
+            stream = None
+    o.stream = stream
+    return o
+
+
+# ---- functions with the C names ---------------------------------------------------------------
+def pdlp_create(m, n, nnz, row_ptr, col_idx, val, c, b, sense, l, u, opt: Options | None = None):
+    lib = load()
+    h = C.c_void_p()
+    _check(lib.pdlp_create(C.byref(h), m, n, nnz, _ptr(row_ptr), _ptr(col_idx), _ptr(val), _ptr(c),
+                           _ptr(b), _ptr(sense), _ptr(l), _ptr(u), C.byref(opt) if opt else None))
+    return h
+
+
+def pdlp_solve(h, tol=1e-4, iter_limit=1_000_000, x0=None, y0=None, omega0=0.0):
+    _check(load().pdlp_solve(h, tol, iter_limit, _ptr(x0), _ptr(y0), omega0))
+
+
+def pdlp_get(h, x=None, y=None, red_cost=None) -> Result:
+    r = Result()
+    _check(load().pdlp_get(h, _ptr(x), _ptr(y), _ptr(red_cost), C.byref(r)))
+    return r
+
+
+def pdlp_spmv(h, trans, x, y):
+    _check(load().pdlp_spmv(h, int(trans), _ptr(x), _ptr(y)))
+
+
+def pdlp_destroy(h):
+    load().pdlp_destroy(h)
+
+
+# ---- convenience wrapper ----------------------------------------------------------------------
+def _lp_arrays(lp):
+    return dict(row_ptr=np.ascontiguousarray(lp.row_ptr, np.int32), col=np.ascontiguousarray(lp.col, np.int32),
+                val=np.ascontiguousarray(lp.val, np.float64), c=np.ascontiguousarray(lp.c, np.float64),
+                b=np.ascontiguousarray(lp.b, np.float64), sense=np.ascontiguousarray(lp.sense, np.uint8),
+                l=np.ascontiguousarray(lp.l, np.float64), u=np.ascontiguousarray(lp.u, np.float64))
+
+
+@dataclass
+class Solution:
+    x: np.ndarray
+    y: np.ndarray
+    rc: np.ndarray
+    info: dict
+
+
+class Problem:
+    """A solver handle for one LP (generators.LP or any object with the same fields)."""
+
+    def __init__(self, lp, precision="fp32", **opts):
+        self.m, self.n = int(lp.m), int(lp.n)
+        self.arr = _lp_arrays(lp)
+        self.nnz = int(self.arr["row_ptr"][-1])
+        self.opt = options(precision=precision, **opts)
+        a = self.arr
+        self.h = pdlp_create(self.m, self.n, self.nnz, a["row_ptr"], a["col"], a["val"], a["c"], a["b"],
+                             a["sense"], a["l"], a["u"], self.opt)
+
+    def solve(self, tol=1e-4, iter_limit=1_000_000, x0=None, y0=None, omega0=0.0) -> dict:
+        x0a = None if x0 is None else np.ascontiguousarray(x0, np.float64)
+        y0a = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+        pdlp_solve(self.h, tol, iter_limit, x0a, y0a, omega0)
+        return pdlp_get(self.h).as_dict()
+
+    def get(self) -> Solution:
+        x, y, rc = np.zeros(self.n), np.zeros(self.m), np.zeros(self.n)
+        r = pdlp_get(self.h, x, y, rc)
+        return Solution(x, y, rc, r.as_dict())
+
+    def spmv(self, x, trans=False) -> np.ndarray:
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.zeros(self.n if trans else self.m)
+        pdlp_spmv(self.h, 1 if trans else 0, x, y)
+        return y
+
+    def scaling(self):
+        Dr, Dc, sv = np.zeros(self.m), np.zeros(self.n), np.zeros(self.nnz)
+        trp, tci, tv = np.zeros(self.n + 1, np.int32), np.zeros(self.nnz, np.int32), np.zeros(self.nnz)
+        _check(load().pdlp_get_scaling(self.h, _ptr(Dr), _ptr(Dc), _ptr(sv), _ptr(trp), _ptr(tci), _ptr(tv)))
+        return dict(Dr=Dr, Dc=Dc, scaled_val=sv, t_row_ptr=trp, t_col=tci, t_val=tv)
+
+    def schedule(self) -> dict:
+        tn, ta, tt = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().pdlp_get_schedule(self.h, C.byref(tn), C.byref(ta), C.byref(tt)))
+        return dict(tile_nnz=tn.value, tiles_a=ta.value, tiles_at=tt.value)
+
+    def device_bytes(self) -> int:
+        return int(load().pdlp_device_bytes(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            pdlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def pdlp_batch_create(descs, opt: Options | None = None):
+    lib = load()
+    h = C.c_void_p()
+    arr = (ProblemDesc * len(descs))(*descs)
+    _check(lib.pdlp_batch_create(C.byref(h), len(descs), arr, C.byref(opt) if opt else None))
+    return h
+
+
+def pdlp_batch_solve(h, tol=1e-4, iter_limit=1_000_000, x0s=None, y0s=None, omega0s=None):
+    _check(load().pdlp_batch_solve(h, tol, iter_limit, x0s, y0s, omega0s))
+
+
+def pdlp_batch_get(h, i, x=None, y=None, red_cost=None) -> Result:
+    r = Result()
+    _check(load().pdlp_batch_get(h, i, _ptr(x), _ptr(y), _ptr(red_cost), C.byref(r)))
+    return r
+
+
+def pdlp_batch_destroy(h):
+    load().pdlp_batch_destroy(h)
+
+
+class Batch:
+    """A handle solving many LPs together (one launch per kernel covers every instance)."""
+
+    def __init__(self, lps, precision="fp32", **opts):
+        self.arrs = [_lp_arrays(lp) for lp in lps]
+        self.dims = [(int(lp.m), int(lp.n)) for lp in lps]
+        descs = []
+        for (m, n), a in zip(self.dims, self.arrs):
+            descs.append(ProblemDesc(m, n, int(a["row_ptr"][-1]), _ptr(a["row_ptr"]), _ptr(a["col"]),
+                                     _ptr(a["val"]), _ptr(a["c"]), _ptr(a["b"]), _ptr(a["sense"]),
+                                     _ptr(a["l"]), _ptr(a["u"])))
+        self.opt = options(precision=precision, **opts)
+        self.h = pdlp_batch_create(descs, self.opt)
+
+    def __len__(self):
+        return len(self.dims)
+
+    def solve(self, tol=1e-4, iter_limit=1_000_000, x0s=None, y0s=None, omega0s=None):
+        k = len(self.dims)
+        keep = []
+
+        def ptr_array(vs):
+            if vs is None:
+                return None
+            arr = (C.c_void_p * k)()
+            for i, v in enumerate(vs):
+                if v is not None:
+                    a = np.ascontiguousarray(v, np.float64)
+                    keep.append(a)
+                    arr[i] = a.ctypes.data
+            return arr
+
+        xa, ya = ptr_array(x0s), ptr_array(y0s)
+        om = None
+        if omega0s is not None:
+            oa = np.ascontiguousarray(omega0s, np.float64)
+            keep.append(oa)
+            om = oa.ctypes.data_as(C.c_void_p)
+        pdlp_batch_solve(self.h, tol, iter_limit, xa, ya, om)
+        return [pdlp_batch_get(self.h, i).as_dict() for i in range(k)]
+
+    def get(self, i) -> Solution:
+        m, n = self.dims[i]
+        x, y, rc = np.zeros(n), np.zeros(m), np.zeros(n)
+        r = pdlp_batch_get(self.h, i, x, y, rc)
+        return Solution(x, y, rc, r.as_dict())
+
+    def close(self):
+        if getattr(self, "h", None):
+            pdlp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

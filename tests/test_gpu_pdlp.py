@@ -1,0 +1,245 @@
+"""GPU parity tests: the HIP path through the C-ABI against the FP64 oracle (and HiGHS / scipy).
+
+Tolerances:
+  * SpMV, FP64: |y - y_ref| <= 1e-12 (|A||x|)_i ; FP32: <= 2e-6 (|A||x|)_i + 1e-30 (the inputs are
+    rounded to FP32 once, each product and sum adds one rounding; sqrt(5000) * 2^-24 < 5e-6 for the
+    longest rows, far below what accumulates in practice).
+  * Scaling (FP64 on the GPU): Dr, Dc and the scaled values within 1e-12 relative of the oracle; the
+    sums of the Pock-Chambolle pass are taken in a different order, so bitwise equality is not
+    expected.
+  * Transpose: bit-exact (integer work; the values are gathered, not computed).
+  * Iterate tracking (FP64): |x_k^gpu - x_k^orc| <= 1e-9 |x_k^orc| (likewise y, eta, omega) for
+    k = 1..100, unless the oracle logged a discrete decision with relative margin < 1e-12 at or
+    before k.
+  * End to end: relative KKT <= tol as re-evaluated by the oracle from the returned point, and the
+    objective within 1e-4 relative (max(1, |f*|)) of HiGHS.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle_pins as P
+
+try:  # import at collection time: the first import on a fresh machine can take a minute
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+from paper_2503_10344_amd import generators as g
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pdlp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2503_10344_amd import pdlp as mod
+    mod.load()
+    return mod
+
+
+def _absprod(lp, x):
+    A = lp.to_scipy()
+    return abs(A) @ np.abs(x)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spmv_parity(pdlp, prec):
+    lp = g.general_sparse(1, m=20000, n=40000)  # rows up to 5000 long: stream and long tiles
+    say("spmv", prec, lp.m, lp.n, lp.nnz)
+    A = lp.to_scipy()
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(lp.n)
+    y = rng.standard_normal(lp.m)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    for tn in (512, 2048, 4096):
+        with pdlp.Problem(lp, precision=prec, tile_nnz=tn) as p:
+            ax = p.spmv(x)
+            aty = p.spmv(y, trans=True)
+        ref = oracle.spmv(lp.row_ptr, lp.col, lp.val, x)
+        assert np.all(np.abs(ax - ref) <= tol * _absprod(lp, x) + 1e-30), (tn, np.abs(ax - ref).max())
+        refT = A.T @ y
+        bound = abs(A).T @ np.abs(y)
+        assert np.all(np.abs(aty - refT) <= tol * bound + 1e-30), (tn, np.abs(aty - refT).max())
+
+
+def test_spmv_edge_shapes(pdlp):
+    # empty rows, empty columns, a single dense row, and a ragged tail
+    rng = np.random.default_rng(5)
+    m, n = 1500, 3000
+    rows, cols, vals = [], [], []
+    for i in range(m):
+        if i % 7 == 0:
+            continue  # empty row
+        L = 4100 if i == 700 else int(rng.integers(1, 40))
+        cs = np.sort(rng.choice(n - 50, size=min(L, n - 50), replace=False))  # last 50 columns empty
+        rows += [i] * cs.size
+        cols += cs.tolist()
+        vals += rng.standard_normal(cs.size).tolist()
+    rp, ci, v = g._csr_from_triplets(m, n, rows, cols, vals)
+    lp = g.LP(m, n, rp, ci, v, np.zeros(n), np.zeros(m), np.full(m, ord("E"), np.uint8),
+              np.full(n, -np.inf), np.full(n, np.inf))
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    A = lp.to_scipy()
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-6)):
+        with pdlp.Problem(lp, precision=prec, tile_nnz=1024) as p:
+            ax, aty = p.spmv(x), p.spmv(y, trans=True)
+        assert np.all(np.abs(ax - A @ x) <= tol * (abs(A) @ np.abs(x)) + 1e-30)
+        assert np.all(np.abs(aty - A.T @ y) <= tol * (abs(A).T @ np.abs(y)) + 1e-30)
+        assert np.all(ax[::7] == 0.0) and np.all(aty[-50:] == 0.0)
+
+
+def test_transpose_and_scaling(pdlp):
+    lp = g.general_sparse(3, m=4000, n=9000, cap=2000)
+    say("scaling", lp.m, lp.n, lp.nnz)
+    with pdlp.Problem(lp, precision="fp64") as p:
+        s = p.scaling()
+    Dr, Dc, sv = oracle.scale(lp)
+    assert np.allclose(s["Dr"], Dr, rtol=1e-12, atol=0) and np.allclose(s["Dc"], Dc, rtol=1e-12, atol=0)
+    assert np.allclose(s["scaled_val"], sv, rtol=1e-12, atol=0)
+    trp, tci, tv = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col, s["scaled_val"])
+    assert np.array_equal(s["t_row_ptr"], trp) and np.array_equal(s["t_col"], tci)
+    assert np.array_equal(s["t_val"], tv)  # gathered, so bitwise equal to the row copy
+
+
+def _tracking(pdlp, lp, K=100, label=""):
+    orc = oracle.solve(lp, tol=0.0, iter_limit=K, trace_len=K)
+    tr = orc.trace
+    cut = K
+    bad = np.nonzero(tr["margin"] < 1e-12)[0]
+    if bad.size:
+        cut = int(bad[0])  # compare only before the first near-tie
+        say(label, "near-tie at attempt", cut + 1, "- comparing attempts 1 ..", cut)
+    ks = list(range(1, cut + 1))
+    with pdlp.Problem(lp, precision="fp64", tile_nnz=1024, warm_fallback=False) as p:
+        for k in ks:
+            p.solve(tol=0.0, iter_limit=k)
+            sol = p.get()
+            xo, yo = tr["x"][k - 1], tr["y"][k - 1]
+            ex = np.linalg.norm(sol.x - xo) / max(np.linalg.norm(xo), 1e-30)
+            ey = np.linalg.norm(sol.y - yo) / max(np.linalg.norm(yo), 1e-30)
+            eeta = abs(sol.info["eta"] - tr["eta"][k - 1]) / tr["eta"][k - 1]
+            eom = abs(sol.info["omega"] - tr["omega"][k - 1]) / tr["omega"][k - 1]
+            assert sol.info["iterations"] == k
+            assert max(ex, ey, eeta, eom) <= 1e-9, (label, k, ex, ey, eeta, eom)
+    flags = tr["flags"][:cut]
+    say(label, "tracked", cut, "attempts; accepted", int((flags & 1).sum()), "restarts", int(((flags & 4) > 0).sum()))
+
+
+def test_tracking_fp64_setcover(pdlp):
+    _tracking(pdlp, g.set_cover(0, m=300, n=700), label="setcover")
+
+
+def test_tracking_fp64_general(pdlp):
+    _tracking(pdlp, g.general_sparse(2, m=400, n=800, cap=200), label="general")
+
+
+def test_tracking_fp64_energy(pdlp):
+    _tracking(pdlp, g.energy(1, T=24, N=5, K=3, E=8), label="energy")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_end_to_end_setcover(pdlp, prec):
+    lp = g.set_cover(0)  # 2000 x 5000, the correctness / latency workload
+    f, _, _ = P.highs(lp)
+    with pdlp.Problem(lp, precision=prec) as p:
+        info = p.solve(tol=1e-4)
+        sol = p.get()
+    say("setcover", prec, info["status_name"], info["iterations"], info["primal_obj"], f)
+    assert info["status"] == pdlp.OPTIMAL
+    k = oracle.kkt(lp, sol.x, sol.y)
+    assert k["rel_kkt"] <= 1e-4, k
+    assert abs(info["primal_obj"] - f) <= 1e-4 * max(1.0, abs(f))
+    assert abs(k["pobj"] - info["primal_obj"]) <= 1e-9 * max(1.0, abs(f))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_end_to_end_general(pdlp, prec):
+    lp = g.general_sparse(5, m=3000, n=6000, cap=1000)
+    f, _, _ = P.highs(lp)
+    with pdlp.Problem(lp, precision=prec) as p:
+        info = p.solve(tol=1e-4, iter_limit=200_000)
+        sol = p.get()
+    say("general", prec, info["status_name"], info["iterations"], info["primal_obj"], f)
+    assert info["status"] == pdlp.OPTIMAL
+    assert oracle.kkt(lp, sol.x, sol.y)["rel_kkt"] <= 1e-4
+    assert abs(info["primal_obj"] - f) <= 1e-4 * max(1.0, abs(f))
+
+
+def test_fp64_matches_oracle_iterations(pdlp):
+    """In FP64 the GPU solve to 1e-6 stops at the same evaluation as the oracle (or one adjacent),
+    with the same objective to 1e-8."""
+    lp = g.set_cover(4, m=500, n=1200)
+    orc = oracle.solve(lp, tol=1e-6)
+    with pdlp.Problem(lp, precision="fp64") as p:
+        info = p.solve(tol=1e-6)
+    say("fp64 vs oracle", info["iterations"], orc.iterations)
+    assert abs(info["iterations"] - orc.iterations) <= 64
+    assert abs(info["primal_obj"] - orc.pobj) <= 1e-6 * max(1.0, abs(orc.pobj))
+
+
+def test_determinism(pdlp):
+    lp = g.general_sparse(7, m=2000, n=4000, cap=800)
+    with pdlp.Problem(lp, precision="fp32") as p:
+        p.solve(tol=1e-4)
+        a = p.get()
+        p.solve(tol=1e-4)
+        b = p.get()
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y)
+    assert a.info["iterations"] == b.info["iterations"]
+
+
+def test_graphs_match_direct_launches(pdlp):
+    lp = g.set_cover(2, m=800, n=2000)
+    out = []
+    for graphs in (True, False):
+        with pdlp.Problem(lp, precision="fp32", use_graphs=graphs, tile_nnz=1024) as p:
+            p.solve(tol=1e-4)
+            out.append(p.get())
+    assert np.array_equal(out[0].x, out[1].x) and out[0].info["iterations"] == out[1].info["iterations"]
+
+
+def test_iteration_limit_and_warm_start(pdlp):
+    lp = g.general_sparse(30, m=300, n=600, cap=100)
+    f, xs, ys = P.highs(lp)
+    with pdlp.Problem(lp, precision="fp64") as p:
+        info = p.solve(tol=1e-8, iter_limit=50)
+        assert info["status"] == pdlp.ITER_LIMIT and info["iterations"] == 50
+        # warm start at the optimum: terminates at the first evaluation
+        info = p.solve(tol=1e-7, x0=xs, y0=ys)
+        assert info["status"] == pdlp.OPTIMAL and info["iterations"] == 64 and info["warm_started"] == 1
+        # a garbage warm start is replaced by the cold start
+        info = p.solve(tol=1e-4, x0=np.full(lp.n, 1e6), y0=np.full(lp.m, -1e6))
+        assert info["fallback_used"] == 1 and info["status"] == pdlp.OPTIMAL
+
+
+def test_device_memory_cap(pdlp):
+    lp = g.set_cover(1, m=500, n=1000)
+    with pytest.raises(pdlp.PDLPError) as e:
+        pdlp.Problem(lp, device_mem_limit=4096)
+    assert e.value.code == -3
+
+
+def test_batch_matches_single(pdlp):
+    lps = [g.set_cover(10, m=300, n=700), g.general_sparse(11, m=200, n=500, cap=60),
+           g.multi_knapsack(12, m=150, n=400)]
+    singles = []
+    for lp in lps:
+        with pdlp.Problem(lp, precision="fp32", tile_nnz=1024) as p:
+            p.solve(tol=1e-4)
+            singles.append(p.get())
+    with pdlp.Batch(lps, precision="fp32", tile_nnz=1024) as bt:
+        bt.solve(tol=1e-4)
+        for i, lp in enumerate(lps):
+            s = bt.get(i)
+            say("batch", i, s.info["iterations"], singles[i].info["iterations"])
+            assert s.info["iterations"] == singles[i].info["iterations"]
+            assert np.array_equal(s.x, singles[i].x) and np.array_equal(s.y, singles[i].y)
