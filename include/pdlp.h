@@ -69,7 +69,10 @@ typedef struct pdlp_options {
   void *stream;            /* hipStream_t to order work on; NULL = library-owned stream */
   int32_t warm_fallback;   /* 1 = replace a warm start whose relative KKT error is not below the
                               cold start's by the cold start (default 1) */
-  int32_t reserved[7];
+  int32_t kernel_timing;   /* 1 = bracket every launch of the two iteration kernels with HIP events
+                              on the handle's stream (graphs are not used then); read the totals with
+                              pdlp_kernel_stats (default 0) */
+  int32_t reserved[6];
 } pdlp_options;
 
 typedef struct pdlp_result {
@@ -147,6 +150,14 @@ int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val
 
 /* SpMV schedule chosen for A and A': tile size in nonzeros and number of tiles of each. */
 int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at);
+
+/*
+ * Kernel timing of the last pdlp_solve with pdlp_options.kernel_timing = 1.
+ *   kernel 0: A x' fused with the dual update and the step-size decision
+ *   kernel 1: A'y' fused with the primal update and the iterate averages
+ * *launches receives the number of launches, *total_ms their summed HIP-event durations.
+ */
+int pdlp_kernel_stats(pdlp_problem *p, int32_t kernel, int64_t *launches, double *total_ms);
 
 /* Bytes of device memory held by the handle. */
 int64_t pdlp_device_bytes(const pdlp_problem *p);

@@ -49,7 +49,8 @@ class _Opts(C.Structure):
                 ("pock_chambolle", C.c_int32), ("eval_every", C.c_int32), ("trace_len", C.c_int32),
                 ("x0", C.c_void_p), ("y0", C.c_void_p), ("omega0", C.c_double),
                 ("trace_x", C.c_void_p), ("trace_y", C.c_void_p), ("trace_eta", C.c_void_p),
-                ("trace_omega", C.c_void_p), ("trace_flags", C.c_void_p), ("trace_margin", C.c_void_p)]
+                ("trace_omega", C.c_void_p), ("trace_flags", C.c_void_p), ("trace_margin", C.c_void_p),
+                ("trace_cond", C.c_void_p)]
 
 
 class _Res(C.Structure):
@@ -128,10 +129,11 @@ def solve(lp, tol: float = 1e-4, iter_limit: int = 1_000_000, ruiz_iters: int = 
     if trace_len > 0:
         tr = dict(x=np.zeros((trace_len, lp.n)), y=np.zeros((trace_len, lp.m)),
                   eta=np.zeros(trace_len), omega=np.zeros(trace_len),
-                  flags=np.zeros(trace_len, np.int32), margin=np.full(trace_len, np.inf))
+                  flags=np.zeros(trace_len, np.int32), margin=np.full(trace_len, np.inf),
+                  cond=np.ones(trace_len))
     o = _Opts(tol, iter_limit, ruiz_iters, 1 if pock_chambolle else 0, eval_every, trace_len,
               _p(x0a), _p(y0a), omega0,
-              *([_p(tr[k]) for k in ("x", "y", "eta", "omega", "flags", "margin")] if tr else [None] * 6))
+              *([_p(tr[k]) for k in ("x", "y", "eta", "omega", "flags", "margin", "cond")] if tr else [None] * 7))
     r = _Res()
     rc_ = lib.orc_solve(C.byref(s), C.byref(o), _p(x), _p(y), _p(rc), C.byref(r))
     if rc_ != 0:

@@ -67,6 +67,8 @@ typedef struct {
   double *trace_omega;  /* [trace_len] primal weight after attempt k */
   int32_t *trace_flags; /* [trace_len] bit0 accepted, bit1 evaluated, bit2 restarted, bit3 average */
   double *trace_margin; /* [trace_len] smallest relative margin of a discrete decision at attempt k */
+  double *trace_cond;   /* [trace_len] 1 + |x|/|dx| + |y|/|dy| of attempt k (scaled space): the factor
+                           by which relative errors of the iterates enter the step-size ratio */
 } orc_opts;
 
 typedef struct {
@@ -433,6 +435,14 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     double eta_new = fmin((1.0 - pow(kk, -0.3)) * eta_bar, (1.0 + pow(kk, -0.6)) * eta);
     int accepted = eta <= eta_bar;
     double margin = rel_margin(eta, eta_bar);
+    double cond = 1.0;
+    {
+      double xx = 0.0, yy = 0.0;
+      for (int32_t j = 0; j < n; ++j) xx += cur.x[j] * cur.x[j];
+      for (int32_t i = 0; i < m; ++i) yy += cur.y[i] * cur.y[i];
+      if (dx2 > 0.0) cond += sqrt(xx / dx2);
+      if (dy2 > 0.0) cond += sqrt(yy / dy2);
+    }
     if (accepted) {
       memcpy(cur.x, xn, sizeof(double) * (size_t)n);
       memcpy(cur.y, yn, sizeof(double) * (size_t)m);
@@ -530,6 +540,7 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
       if (o->trace_omega) o->trace_omega[t] = omega;
       if (o->trace_flags) o->trace_flags[t] = flags;
       if (o->trace_margin) o->trace_margin[t] = margin;
+      if (o->trace_cond) o->trace_cond[t] = cond;
     }
 
     if (k >= o->iter_limit) {

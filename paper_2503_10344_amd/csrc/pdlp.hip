@@ -202,12 +202,18 @@ struct Solver {
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::vector<double> eta0, omega_default, nb, nc;
   hipGraphExec_t graph = nullptr;
+  // kernel timing (opt.kernel_timing): two pools of start/stop events per attempt and kernel
+  std::vector<hipEvent_t> tev[2];
+  int64_t t_launches[2] = {0, 0};
+  double t_ms[2] = {0.0, 0.0};
   Iter<T> P{};
   bool solved = false;
   std::vector<pdlp_result> last;
 
   ~Solver() {
     if (stream) (void)hipStreamSynchronize(stream);
+    for (auto &pool : tev)
+      for (auto e : pool) (void)hipEventDestroy(e);
     if (graph) (void)hipGraphExecDestroy(graph);
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -592,7 +598,50 @@ struct Solver {
     launch_eval(kEvalChunk);
     launch_restart();
   }
-  void run_chunk() {
+  // Direct launches bracketed by events (pool `slot`): [attempt][kernel][start, stop].
+  void launch_chunk_timed(int slot) {
+    auto &pool = tev[slot];
+    if (pool.empty()) {
+      pool.resize((size_t)opt.eval_every * 4);
+      for (auto &e : pool) HIPCHK(hipEventCreate(&e));
+    }
+    for (int r = 0; r < opt.eval_every; ++r) {
+      hipEvent_t *e = &pool[(size_t)r * 4];
+      switch (tile_nnz) {
+#define CASE(TN)                                                                                    \
+  case TN:                                                                                           \
+    HIPCHK(hipEventRecord(e[0], stream));                                                            \
+    hipLaunchKernelGGL((k_dual<T, TN>), dim3(a_ntiles), dim3(kBlock), 0, stream, P);                 \
+    HIPCHK(hipEventRecord(e[1], stream));                                                            \
+    HIPCHK(hipEventRecord(e[2], stream));                                                            \
+    hipLaunchKernelGGL((k_primal<T, TN>), dim3(t_ntiles + ra_blocks), dim3(kBlock), 0, stream, P);   \
+    HIPCHK(hipEventRecord(e[3], stream));                                                            \
+    break;
+        CASE(512) CASE(1024) CASE(2048) CASE(4096)
+#undef CASE
+      }
+    }
+    launch_eval(kEvalChunk);
+    launch_restart();
+    HIPCHK(hipGetLastError());
+  }
+  // Add the durations recorded in pool `slot` (its chunk has completed).
+  void collect_times(int slot) {
+    auto &pool = tev[slot];
+    for (int r = 0; r < opt.eval_every && !pool.empty(); ++r)
+      for (int k = 0; k < 2; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 4 + 2 * k], pool[(size_t)r * 4 + 2 * k + 1]));
+        t_ms[k] += ms;
+        t_launches[k] += 1;
+      }
+  }
+
+  void run_chunk(int64_t ch) {
+    if (opt.kernel_timing) {
+      launch_chunk_timed((int)(ch & 1));
+      return;
+    }
     if (!opt.use_graphs) {
       launch_chunk_body();
       HIPCHK(hipGetLastError());
@@ -669,6 +718,8 @@ struct Solver {
     }
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));
+    t_launches[0] = t_launches[1] = 0;
+    t_ms[0] = t_ms[1] = 0.0;
     const bool warm = stage_start(x0s, y0s);
     std::vector<int> fallback((size_t)K, 0), warm_q((size_t)K, 0);
     for (int q = 0; q < K; ++q) warm_q[q] = (x0s && x0s[q]) || (y0s && y0s[q]);
@@ -768,16 +819,19 @@ struct Solver {
   // after all instances finished does no work.
   void run_loop(int64_t iter_limit) {
     const int64_t max_chunks = iter_limit / opt.eval_every + 3;
-    for (int64_t ch = 0; ch < max_chunks; ++ch) {
-      run_chunk();
+    int64_t ch = 0;
+    for (; ch < max_chunks; ++ch) {
+      run_chunk(ch);
       HIPCHK(hipMemcpyAsync(&h_flags[ch & 1], ndone, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipEventRecord(ev[ch & 1], stream));
       if (ch >= 1) {
         HIPCHK(hipEventSynchronize(ev[(ch - 1) & 1]));
+        if (opt.kernel_timing) collect_times((int)((ch - 1) & 1));
         if (h_flags[(ch - 1) & 1] >= K) break;
       }
     }
     sync();
+    if (opt.kernel_timing) collect_times((int)((ch < max_chunks ? ch : ch - 1) & 1));
   }
 
   void finalize() {
@@ -941,6 +995,7 @@ void pdlp_options_default(pdlp_options *o) {
   o->device_mem_limit = 0;
   o->stream = nullptr;
   o->warm_fallback = 1;
+  o->kernel_timing = 0;
 }
 
 const char *pdlp_error_string(int code) {
@@ -1022,6 +1077,19 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
       if (tile_nnz) *tile_nnz = s.tile_nnz;
       if (tiles_a) *tiles_a = s.a_ntiles;
       if (tiles_at) *tiles_at = s.t_ntiles;
+    });
+  });
+}
+
+int pdlp_kernel_stats(pdlp_problem *p, int32_t kernel, int64_t *launches, double *total_ms) {
+  if (!p || kernel < 0 || kernel > 1) {
+    pdlp::g_last_error = "bad argument to pdlp_kernel_stats";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    p->s.visit([&](auto &s) {
+      if (launches) *launches = s.t_launches[kernel];
+      if (total_ms) *total_ms = s.t_ms[kernel];
     });
   });
 }

@@ -32,7 +32,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("eval_every", C.c_int32), ("ruiz_iters", C.c_int32),
                 ("pock_chambolle", C.c_int32), ("use_graphs", C.c_int32), ("device_ptrs", C.c_int32),
                 ("tile_nnz", C.c_int32), ("verbose", C.c_int32), ("device_mem_limit", C.c_int64),
-                ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("kernel_timing", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class Result(C.Structure):
@@ -56,7 +57,7 @@ class ProblemDesc(C.Structure):
 
 
 EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_spmv",
-           "pdlp_get_scaling", "pdlp_get_schedule", "pdlp_device_bytes", "pdlp_destroy",
+           "pdlp_get_scaling", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
            "pdlp_batch_get", "pdlp_batch_destroy"]
 
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.pdlp_get_scaling.restype = C.c_int
     lib.pdlp_get_schedule.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.pdlp_get_schedule.restype = C.c_int
+    lib.pdlp_kernel_stats.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(dp)]
+    lib.pdlp_kernel_stats.restype = C.c_int
     lib.pdlp_device_bytes.argtypes = [vp]
     lib.pdlp_device_bytes.restype = i64
     lib.pdlp_destroy.argtypes = [vp]
@@ -128,7 +131,7 @@ def _ptr(a):
 
 def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
             device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
-            warm_fallback=True) -> Options:
+            warm_fallback=True, kernel_timing=False) -> Options:
     o = Options()
     load().pdlp_options_default(C.byref(o))
     o.precision = FP64 if str(precision).lower() in ("fp64", "f64", "double", "1") else FP32
@@ -141,6 +144,7 @@ def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True,
     o.verbose = verbose
     o.device_mem_limit = device_mem_limit
     o.warm_fallback = 1 if warm_fallback else 0
+    o.kernel_timing = 1 if kernel_timing else 0
     if stream is None:
         try:
             import torch
@@ -234,6 +238,15 @@ class Problem:
         tn, ta, tt = C.c_int32(), C.c_int32(), C.c_int32()
         _check(load().pdlp_get_schedule(self.h, C.byref(tn), C.byref(ta), C.byref(tt)))
         return dict(tile_nnz=tn.value, tiles_a=ta.value, tiles_at=tt.value)
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for k, name in ((0, "dual"), (1, "primal")):
+            n, ms = C.c_int64(), C.c_double()
+            _check(load().pdlp_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
+            out[name] = dict(launches=n.value, total_ms=ms.value,
+                             avg_ms=(ms.value / n.value) if n.value else float("nan"))
+        return out
 
     def device_bytes(self) -> int:
         return int(load().pdlp_device_bytes(self.h))
