@@ -168,14 +168,15 @@ struct Solver {
   Arena mem;
   int32_t K = 1, m = 0, n = 0, nnz = 0;
   // instance layout (host)
-  std::vector<int32_t> h_row0, h_col0, h_nnz0, h_a_tile0, h_t_tile0, h_ra0, h_ev0;
+  std::vector<int32_t> h_row0, h_col0, h_nnz0, h_a_tile0, h_t_tile0, h_ab0, h_tb0, h_ev0;
   std::vector<int32_t> h_arp, h_trp;
   std::string sig;
   // instance layout (device)
   int32_t *d_row0 = nullptr, *d_col0 = nullptr, *d_nnz0 = nullptr, *d_a_tile0 = nullptr, *d_t_tile0 = nullptr;
-  int32_t *d_a_tile_inst = nullptr, *d_t_tile_inst = nullptr, *d_ra0 = nullptr, *d_ra_inst = nullptr;
+  int32_t *d_ab0 = nullptr, *d_ab_inst = nullptr, *d_tb0 = nullptr, *d_tb_inst = nullptr;
   int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
-  int ra_blocks = 0, ev_blocks = 1;
+  int ab_blocks = 1, tb_blocks = 1, ev_blocks = 1;
+  int work_blocks = 2048;  // target number of work blocks per side for the whole handle
   // matrix
   int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr, *perm = nullptr;
   int32_t *a_tiles = nullptr, *t_tiles = nullptr;
@@ -194,7 +195,8 @@ struct Solver {
   double *xd = nullptr, *yd = nullptr, *ax64 = nullptr, *aty64 = nullptr;
   double *x_out = nullptr, *y_out = nullptr, *rc_out = nullptr, *stage_n = nullptr, *stage_m = nullptr;
   // reductions, state
-  double *partials = nullptr, *d_red = nullptr;
+  double *p_dual = nullptr, *p_primal = nullptr, *p_restart = nullptr, *p_eval = nullptr, *p_final = nullptr;
+  double *d_red = nullptr;
   State *st = nullptr;
   int32_t *ndone = nullptr;
   std::vector<State> h_st;  // host mirror
@@ -432,28 +434,24 @@ struct Solver {
     for (T *p : {ybar, axbar, ya, tmp_m}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)mm, stream));
     HIPCHK(hipMemsetAsync(st, 0, sizeof(State) * (size_t)K, stream));
 
-    // ---- SpMV schedule, row-average and evaluation blocks ----
+    // ---- SpMV schedule, work blocks and evaluation blocks ----
     choose_schedule();
-    std::vector<int32_t> ra_inst, ev_inst;
-    h_ra0.assign(1, 0), h_ev0.assign(1, 0);
+    std::vector<int32_t> ev_inst;
+    h_ev0.assign(1, 0);
     for (int q = 0; q < K; ++q) {
       const int32_t mq = h_row0[q + 1] - h_row0[q], nq = h_col0[q + 1] - h_col0[q];
-      const int ra = (mq + kRowAvgSpan - 1) / kRowAvgSpan;
-      for (int r = 0; r < ra; ++r) ra_inst.push_back(q);
-      h_ra0.push_back(h_ra0.back() + ra);
       const int ev = grid_for(std::max(mq, nq), kEvalSpan / kBlock, 2048);
       for (int r = 0; r < ev; ++r) ev_inst.push_back(q);
       h_ev0.push_back(h_ev0.back() + ev);
     }
-    ra_blocks = h_ra0.back(), ev_blocks = h_ev0.back();
-    if (!ra_inst.empty()) d_ra_inst = alloc_upload(ra_inst);
-    else d_ra_inst = mem.alloc<int32_t>(1);
-    d_ra0 = alloc_upload(h_ra0);
+    ev_blocks = h_ev0.back();
     d_ev_inst = alloc_upload(ev_inst);
     d_ev0 = alloc_upload(h_ev0);
-    const int64_t need = std::max<int64_t>({(int64_t)a_ntiles * 2, (int64_t)(t_ntiles + ra_blocks),
-                                            (int64_t)ev_blocks * kEvalNV, 16});
-    partials = mem.alloc<double>(need);
+    p_dual = mem.alloc<double>((int64_t)ab_blocks * 2);
+    p_primal = mem.alloc<double>(tb_blocks);
+    p_restart = mem.alloc<double>(ev_blocks);
+    p_eval = mem.alloc<double>((int64_t)ev_blocks * kEvalNV);
+    p_final = mem.alloc<double>((int64_t)ev_blocks * 5);
     set_params();
     sync();
   }
@@ -462,40 +460,56 @@ struct Solver {
     Layout &L = P.L;
     L.K = K;
     L.row0 = d_row0, L.col0 = d_col0, L.a_tile0 = d_a_tile0, L.t_tile0 = d_t_tile0;
-    L.a_tile_inst = d_a_tile_inst, L.t_tile_inst = d_t_tile_inst, L.ra_blk0 = d_ra0, L.ra_inst = d_ra_inst;
+    L.ab0 = d_ab0, L.ab_inst = d_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
-    L.a_ntiles = a_ntiles, L.t_ntiles = t_ntiles, L.ra_blocks = ra_blocks, L.ev_blocks = ev_blocks;
+    L.a_ntiles = a_ntiles, L.t_ntiles = t_ntiles, L.ab_blocks = ab_blocks, L.tb_blocks = tb_blocks;
+    L.ev_blocks = ev_blocks;
     P.a_rp = a_rp, P.a_ci = a_ci, P.a_tiles = a_tiles, P.a_val = a_v;
     P.t_rp = t_rp, P.t_ci = t_ci, P.t_tiles = t_tiles, P.t_val = t_v;
     P.c = cT, P.l = lT, P.u = uT, P.b = bT, P.sense = sense, P.Dr = Dr, P.Dc = Dc;
     for (int q = 0; q < 2; ++q) P.x[q] = xs[q], P.y[q] = ys[q], P.ax[q] = axs[q];
     P.aty = aty, P.xbar = xbar, P.ybar = ybar, P.axbar = axbar, P.atybar = atybar, P.xa = xa, P.ya = ya;
-    P.partials = partials, P.st = st, P.ndone = ndone;
+    P.p_dual = p_dual, P.p_primal = p_primal, P.p_restart = p_restart, P.p_eval = p_eval;
+    P.st = st, P.ndone = ndone;
   }
 
   // ---------------------------------------------------------------------------------------------
   // SpMV schedule
   // ---------------------------------------------------------------------------------------------
   void make_tiles(int tn) {
-    std::vector<int32_t> ta(1, 0), tt(1, 0), ta_inst, tt_inst;
+    std::vector<int32_t> ta(1, 0), tt(1, 0);
     h_a_tile0.assign(1, 0), h_t_tile0.assign(1, 0);
     for (int q = 0; q < K; ++q) {
-      size_t before = ta.size();
       build_tiles(h_arp.data(), h_row0[q], h_row0[q + 1], tn, ta);
-      for (size_t s = before; s < ta.size(); ++s) ta_inst.push_back(q);
       h_a_tile0.push_back((int32_t)ta.size() - 1);
-      before = tt.size();
       build_tiles(h_trp.data(), h_col0[q], h_col0[q + 1], tn, tt);
-      for (size_t s = before; s < tt.size(); ++s) tt_inst.push_back(q);
       h_t_tile0.push_back((int32_t)tt.size() - 1);
     }
-    for (int32_t *p : {a_tiles, t_tiles, d_a_tile_inst, d_t_tile_inst, d_a_tile0, d_t_tile0})
+    for (int32_t *p : {a_tiles, t_tiles, d_a_tile0, d_t_tile0, d_ab0, d_ab_inst, d_tb0, d_tb_inst})
       if (p) mem.release(p);
     a_tiles = alloc_upload(ta), t_tiles = alloc_upload(tt);
-    d_a_tile_inst = alloc_upload(ta_inst), d_t_tile_inst = alloc_upload(tt_inst);
     d_a_tile0 = alloc_upload(h_a_tile0), d_t_tile0 = alloc_upload(h_t_tile0);
     a_ntiles = (int)ta.size() - 1, t_ntiles = (int)tt.size() - 1;
     tile_nnz = tn;
+    // work blocks: about work_blocks per side in total, shared out by tile count, >= 1 per instance
+    std::vector<int32_t> ab_inst, tb_inst;
+    auto blocks_for = [&](const std::vector<int32_t> &tile0, std::vector<int32_t> &b0, std::vector<int32_t> &binst) {
+      const int64_t total = tile0.back();
+      b0.assign(1, 0);
+      binst.clear();
+      for (int q = 0; q < K; ++q) {
+        const int64_t nt = tile0[q + 1] - tile0[q];
+        int64_t nbq = (nt * work_blocks + total - 1) / std::max<int64_t>(total, 1);
+        nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, nt));
+        for (int64_t r = 0; r < nbq; ++r) binst.push_back(q);
+        b0.push_back(b0.back() + (int32_t)nbq);
+      }
+    };
+    blocks_for(h_a_tile0, h_ab0, ab_inst);
+    blocks_for(h_t_tile0, h_tb0, tb_inst);
+    ab_blocks = h_ab0.back(), tb_blocks = h_tb0.back();
+    d_ab0 = alloc_upload(h_ab0), d_ab_inst = alloc_upload(ab_inst);
+    d_tb0 = alloc_upload(h_tb0), d_tb_inst = alloc_upload(tb_inst);
   }
 
   template <typename V, typename X, typename Acc, typename Y>
@@ -582,15 +596,21 @@ struct Solver {
     switch (tile_nnz) {
 #define CASE(TN)                                                                                       \
   case TN:                                                                                              \
-    hipLaunchKernelGGL((k_dual<T, TN>), dim3(a_ntiles), dim3(kBlock), 0, stream, P);                    \
-    hipLaunchKernelGGL((k_primal<T, TN>), dim3(t_ntiles + ra_blocks), dim3(kBlock), 0, stream, P);      \
+    hipLaunchKernelGGL((k_dual<T, TN>), dim3(ab_blocks), dim3(kBlock), 0, stream, P);                   \
+    launch_step();                                                                                      \
+    hipLaunchKernelGGL((k_primal<T, TN>), dim3(tb_blocks), dim3(kBlock), 0, stream, P);                 \
     break;
       CASE(512) CASE(1024) CASE(2048) CASE(4096)
 #undef CASE
     }
   }
+  void launch_step() {
+    hipLaunchKernelGGL(k_step, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_dual,
+                       (const double *)p_primal, (const double *)p_restart, st, ndone);
+  }
   void launch_eval(int mode) {
-    hipLaunchKernelGGL(k_eval<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, mode);
+    hipLaunchKernelGGL(k_eval<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P);
+    hipLaunchKernelGGL(k_eval_fin, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_eval, st, ndone, mode);
   }
   void launch_restart() { hipLaunchKernelGGL(k_restart<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P); }
   void launch_chunk_body() {
@@ -611,10 +631,11 @@ struct Solver {
 #define CASE(TN)                                                                                    \
   case TN:                                                                                           \
     HIPCHK(hipEventRecord(e[0], stream));                                                            \
-    hipLaunchKernelGGL((k_dual<T, TN>), dim3(a_ntiles), dim3(kBlock), 0, stream, P);                 \
+    hipLaunchKernelGGL((k_dual<T, TN>), dim3(ab_blocks), dim3(kBlock), 0, stream, P);                \
     HIPCHK(hipEventRecord(e[1], stream));                                                            \
+    launch_step();                                                                                   \
     HIPCHK(hipEventRecord(e[2], stream));                                                            \
-    hipLaunchKernelGGL((k_primal<T, TN>), dim3(t_ntiles + ra_blocks), dim3(kBlock), 0, stream, P);   \
+    hipLaunchKernelGGL((k_primal<T, TN>), dim3(tb_blocks), dim3(kBlock), 0, stream, P);              \
     HIPCHK(hipEventRecord(e[3], stream));                                                            \
     break;
         CASE(512) CASE(1024) CASE(2048) CASE(4096)
@@ -746,7 +767,6 @@ struct Solver {
         start_point(stage_n, stage_m, xs[0], ys[0]);
         spmv_T(0, xs[0], axs[0]);
         spmv_T(1, ys[0], aty);
-        for (int q = 0; q < K; ++q) h_st[q].cnt[2] = 0;
         upload_state();
       }
     }
@@ -838,8 +858,9 @@ struct Solver {
     hipLaunchKernelGGL(k_unscale<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, xd, yd, x_out, y_out);
     spmv_tiles<double, double, double, double>(0, 0, a_ntiles, xd, ax64);
     spmv_tiles<double, double, double, double>(1, 0, t_ntiles, yd, aty64);
-    Final64 F{xd, yd, ax64, aty64, c64, b64, l64, u64, rc_out};
+    Final64 F{xd, yd, ax64, aty64, c64, b64, l64, u64, rc_out, p_final};
     hipLaunchKernelGGL(k_final_residuals<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, F);
+    hipLaunchKernelGGL(k_final_fin, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_final, st);
     HIPCHK(hipGetLastError());
   }
 

@@ -14,7 +14,6 @@ constexpr int kBlock = 256;   // threads per block for every kernel
 constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kWaves = kBlock / kWave;
 constexpr int kEvalNV = 18;   // per-block partial sums of the evaluation kernel
-constexpr int kRowAvgSpan = 2048;  // rows per row-average block in the primal kernel
 constexpr int kEvalSpan = 2048;    // elements per evaluation block (target)
 
 enum RestartMode : int32_t { kNoRestart = 0, kToCurrent = 1, kToAverage = 2 };
@@ -47,7 +46,6 @@ struct State {
   int32_t restart_mode;
   int32_t eval_every;
   int32_t pad_;
-  uint32_t cnt[8];    // arrival counters of the last-block reductions, one per kernel
 };
 
 // Instance layout tables (device arrays).
@@ -55,13 +53,10 @@ struct Layout {
   int32_t K;
   const int32_t *row0, *col0;       // [K+1] row / column offsets
   const int32_t *a_tile0, *t_tile0; // [K+1] tile ranges of A and A'
-  const int32_t *a_tile_inst;       // [a_ntiles] instance of each tile of A
-  const int32_t *t_tile_inst;       // [t_ntiles]
-  const int32_t *ra_blk0;           // [K+1] row-average block ranges (primal kernel)
-  const int32_t *ra_inst;           // [ra_blocks]
-  const int32_t *ev_blk0;           // [K+1] evaluation block ranges
-  const int32_t *ev_inst;           // [ev_blocks]
-  int32_t a_ntiles, t_ntiles, ra_blocks, ev_blocks;
+  const int32_t *ab0, *ab_inst;     // [K+1], [ab_blocks] A-side work blocks (k_dual)
+  const int32_t *tb0, *tb_inst;     // [K+1], [tb_blocks] A'-side work blocks (k_primal)
+  const int32_t *ev_blk0, *ev_inst; // [K+1], [ev_blocks] evaluation blocks
+  int32_t a_ntiles, t_ntiles, ab_blocks, tb_blocks, ev_blocks;
 };
 
 // Everything an iteration kernel reads or writes. Passed by value.
@@ -82,8 +77,11 @@ struct Iter {
   T *aty;
   T *xbar, *ybar, *axbar, *atybar;
   T *xa, *ya;
-  // reductions and state
-  double *partials;
+  // block partial sums (one slot per block of the producing kernel) and state
+  double *p_dual;     // [ab_blocks][2]  |dy|^2, dy'(A dx)
+  double *p_primal;   // [tb_blocks]     |dx|^2 of the primal candidate
+  double *p_restart;  // [ev_blocks]     |dx|^2 after a restart
+  double *p_eval;     // [ev_blocks][kEvalNV]
   State *st;
   int32_t *ndone;  // number of instances with done == 1
 };

@@ -1,9 +1,10 @@
 // HIP kernels of libpdlp for gfx950 (CDNA4, wave64).
 //
-// Iteration kernels (one PDHG attempt = k_dual then k_primal; every eval_every attempts k_eval then
-// k_restart), setup kernels (transpose, scan, scaling) and finalize kernels. All reductions are
-// deterministic: fixed per-thread order, fixed wave/block trees, block partials summed in block
-// order by the last block to arrive.
+// Iteration kernels (one PDHG attempt = k_dual, k_step, k_primal; every eval_every attempts k_eval,
+// k_eval_fin, k_restart), set-up kernels (transpose, scan, scaling) and finalize kernels. All
+// reductions are deterministic: fixed per-thread order, fixed wave/block trees, block partials
+// summed in block order by a one-block-per-instance kernel launched after the producer (the kernel
+// boundary orders the partial sums; no block issues a device-scope fence).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -102,35 +103,6 @@ __device__ __forceinline__ A block_sum_scalar(A v) {
   return v;
 }
 
-// Returns true in every thread of the last of `expected` blocks to arrive; that block then sees all
-// partials written by the others. The counter is reset for the next launch.
-__device__ __forceinline__ bool last_block(uint32_t *counter, uint32_t expected) {
-  __shared__ int am_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = atomicAdd(counter, 1u);
-    am_last = (prev == expected - 1) ? 1 : 0;
-    if (am_last) *counter = 0u;
-  }
-  __syncthreads();
-  const bool r = am_last != 0;
-  if (r) __threadfence();
-  return r;
-}
-
-// Sum of per-block partials [b0, b1) x [NV] in a fixed order; valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void final_sum(const double *partials, int b0, int b1, double (&out)[NV]) {
-#pragma unroll
-  for (int q = 0; q < NV; ++q) out[q] = 0.0;
-  for (int bidx = b0 + (int)threadIdx.x; bidx < b1; bidx += kBlock) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) out[q] += partials[(size_t)bidx * NV + q];
-  }
-  block_sum<NV>(out);
-}
-
 // Workgroups are dispatched round-robin over the 8 XCDs. Give every XCD a contiguous range of
 // tiles so that neighbouring tiles (which gather neighbouring parts of x in structured matrices)
 // share that XCD's L2.
@@ -166,6 +138,7 @@ __device__ __forceinline__ void tile_spmv(const int32_t *__restrict__ rp, const 
     if (tid == 0) epi(r0, s);
     return;
   }
+  __syncthreads();  // the previous tile of this block may still be reading lds
 #pragma unroll
   for (int it = 0; it < TN / kBlock; ++it) {
     const int e = it * kBlock + tid;
@@ -197,6 +170,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ rp,
                            [&](int i, Acc s) { y[i] = Y(s); });
 }
 
+// Sum of per-block partials [b0, b1) x [NV] in a fixed order; valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void final_sum(const double *partials, int b0, int b1, double (&out)[NV]) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) out[q] = 0.0;
+  for (int bidx = b0 + (int)threadIdx.x; bidx < b1; bidx += kBlock) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] += partials[(size_t)bidx * NV + q];
+  }
+  block_sum<NV>(out);
+}
+
 __device__ __forceinline__ void mark_done(State *st, int32_t *ndone) {
   if (!st->done) {
     st->done = 1;
@@ -204,18 +189,82 @@ __device__ __forceinline__ void mark_done(State *st, int32_t *ndone) {
   }
 }
 
+// A work block of an instance: which instance, its index among the instance's blocks (remapped
+// so that each XCD owns a contiguous range) and how many blocks the instance has.
+struct WBlock {
+  int inst, lb, nb;
+};
+__device__ __forceinline__ WBlock work_block(const int32_t *__restrict__ b0, const int32_t *__restrict__ binst) {
+  WBlock w;
+  w.inst = binst[blockIdx.x];
+  const int s = b0[w.inst];
+  w.nb = b0[w.inst + 1] - s;
+  w.lb = xcd_remap((int)blockIdx.x - s, w.nb);
+  return w;
+}
+// Balanced contiguous share [*lo, *hi) of `count` items for block lb of nb.
+__device__ __forceinline__ void share(int base, int count, int lb, int nb, int *lo, int *hi) {
+  *lo = base + (int)(((int64_t)lb * count) / nb);
+  *hi = base + (int)(((int64_t)(lb + 1) * count) / nb);
+}
+
 // ----------------------------------------------------------------------------------------------
-// One PDHG attempt, part 1: A x' fused with the dual update and the step-size decision.
+// One PDHG attempt is three launches: k_dual, k_step, k_primal. Block partial sums are finished
+// by the per-instance k_step in the next launch, so no block ever needs a device-wide fence.
+//
+// k_dual: A x' fused with the dual update.
 //   ax'_i = (A x')_i ;  y'_i = proj_Y(y_i + sigma (b_i - 2 ax'_i + ax_i)), sigma = eta * omega
-//   partial sums of |dy|^2 and dy'(ax' - ax); the instance's last block applies the adaptive step
-//   rule: eta_bar = (omega |dx|^2 + |dy|^2 / omega) / (2 |dy'(A dx)|), accept iff eta <= eta_bar,
-//   eta <- min((1 - (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta).
-// Grid: one block per tile of A (every instance owns at least one, possibly empty, tile).
+//   per-block partial sums of |dy|^2 and dy'(ax' - ax).
+// Grid: the A-side work blocks of all instances; each owns a contiguous run of tiles.
 // ----------------------------------------------------------------------------------------------
-__device__ inline void step_size_rule(State *st, int32_t *ndone, double dy2, double inter) {
+template <typename T, int TN>
+__global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
+  __shared__ T lds[TN];
+  const WBlock w = work_block(P.L.ab0, P.L.ab_inst);
+  const State *st = P.st + w.inst;
+  if (st->done | st->stop) return;
+  const int cur = st->cur;
+  const T sigma = T(st->eta * st->omega);
+  const T *__restrict__ xn = P.x[cur ^ 1];
+  const T *__restrict__ yc = P.y[cur];
+  const T *__restrict__ axc = P.ax[cur];
+  T *__restrict__ yn = P.y[cur ^ 1];
+  T *__restrict__ axn = P.ax[cur ^ 1];
+  const T *__restrict__ b = P.b;
+  const uint8_t *__restrict__ sense = P.sense;
+  double acc[2] = {0.0, 0.0};
+  int tb, te;
+  share(P.L.a_tile0[w.inst], P.L.a_tile0[w.inst + 1] - P.L.a_tile0[w.inst], w.lb, w.nb, &tb, &te);
+  for (int tile = tb; tile < te; ++tile) {
+    tile_spmv<T, T, T, TN>(P.a_rp, P.a_ci, P.a_val, xn, P.a_tiles[tile], P.a_tiles[tile + 1], lds,
+                           [&](int i, T s) {
+                             const T yi = yc[i], axi = axc[i];
+                             const T ynew = proj_dual(yi + sigma * (b[i] - T(2) * s + axi), sense[i]);
+                             yn[i] = ynew;
+                             axn[i] = s;
+                             const double dy = double(ynew) - double(yi);
+                             acc[0] += dy * dy;
+                             acc[1] += dy * (double(s) - double(axi));
+                           });
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    P.p_dual[2 * blockIdx.x] = acc[0];
+    P.p_dual[2 * blockIdx.x + 1] = acc[1];
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// k_step (one block per instance): the adaptive step-size rule.
+//   eta_bar = (omega |dx|^2 + |dy|^2 / omega) / (2 |dy'(A dx)|), accept iff eta <= eta_bar,
+//   eta <- min((1 - (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta).
+// |dx|^2 comes from the kernel that produced the primal candidate (k_primal, or k_restart after a
+// restart or at start-up).
+// ----------------------------------------------------------------------------------------------
+__device__ inline void step_size_rule(State *st, int32_t *ndone, double dx2, double dy2, double inter) {
   const double eta = st->eta, omega = st->omega;
   const double denom = 2.0 * fabs(inter);
-  const double eta_bar = denom > 0.0 ? (omega * st->dx2 + dy2 / omega) / denom : INFINITY;
+  const double eta_bar = denom > 0.0 ? (omega * dx2 + dy2 / omega) / denom : INFINITY;
   const int64_t k = st->k + 1;
   st->k = k;
   const double kk = (double)(k + 1);
@@ -238,68 +287,49 @@ __device__ inline void step_size_rule(State *st, int32_t *ndone, double dy2, dou
   }
 }
 
-template <typename T, int TN>
-__global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
-  __shared__ T lds[TN];
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int inst = P.L.a_tile_inst[tile];
-  State *st = P.st + inst;
-  if (st->done | st->stop) return;
-  const int cur = st->cur;
-  const T sigma = T(st->eta * st->omega);
-  const T *__restrict__ xn = P.x[cur ^ 1];
-  const T *__restrict__ yc = P.y[cur];
-  const T *__restrict__ axc = P.ax[cur];
-  T *__restrict__ yn = P.y[cur ^ 1];
-  T *__restrict__ axn = P.ax[cur ^ 1];
-  const T *__restrict__ b = P.b;
-  const uint8_t *__restrict__ sense = P.sense;
-  double acc[2] = {0.0, 0.0};
-  tile_spmv<T, T, T, TN>(P.a_rp, P.a_ci, P.a_val, xn, P.a_tiles[tile], P.a_tiles[tile + 1], lds,
-                         [&](int i, T s) {
-                           const T yi = yc[i], axi = axc[i];
-                           const T ynew = proj_dual(yi + sigma * (b[i] - T(2) * s + axi), sense[i]);
-                           yn[i] = ynew;
-                           axn[i] = s;
-                           const double dy = double(ynew) - double(yi);
-                           acc[0] += dy * dy;
-                           acc[1] += dy * (double(s) - double(axi));
-                         });
-  block_sum<2>(acc);
+__global__ __launch_bounds__(kBlock) void k_step(Layout L, const double *__restrict__ p_dual,
+                                                 const double *__restrict__ p_primal,
+                                                 const double *__restrict__ p_restart, State *sts,
+                                                 int32_t *ndone) {
+  const int inst = blockIdx.x;
+  State *st = sts + inst;
+  if (st->done) return;
+  if (st->stop) {  // the pending commit was applied by k_primal / k_restart: finish
+    if (threadIdx.x == 0) mark_done(st, ndone);
+    return;
+  }
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int q = L.ab0[inst] + (int)threadIdx.x; q < L.ab0[inst + 1]; q += kBlock) {
+    a[0] += p_dual[2 * q];
+    a[1] += p_dual[2 * q + 1];
+  }
+  if (st->restart_mode != kNoRestart) {
+    for (int q = L.ev_blk0[inst] + (int)threadIdx.x; q < L.ev_blk0[inst + 1]; q += kBlock) a[2] += p_restart[q];
+  } else {
+    for (int q = L.tb0[inst] + (int)threadIdx.x; q < L.tb0[inst + 1]; q += kBlock) a[2] += p_primal[q];
+  }
+  block_sum<3>(a);
   if (threadIdx.x == 0) {
-    P.partials[2 * tile] = acc[0];
-    P.partials[2 * tile + 1] = acc[1];
+    st->restart_mode = kNoRestart;
+    step_size_rule(st, ndone, a[2], a[0], a[1]);
   }
-  const int t0 = P.L.a_tile0[inst], t1 = P.L.a_tile0[inst + 1];
-  if (!last_block(&st->cnt[0], (uint32_t)(t1 - t0))) return;
-  double tot[2] = {0.0, 0.0};
-  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
-    tot[0] += P.partials[2 * t];
-    tot[1] += P.partials[2 * t + 1];
-  }
-  block_sum<2>(tot);
-  if (threadIdx.x == 0) step_size_rule(st, P.ndone, tot[0], tot[1]);
 }
 
 // ----------------------------------------------------------------------------------------------
-// One PDHG attempt, part 2: if the attempt was accepted, A'y' (committing it) and the weighted
-// averages (x_bar, A'y_bar here; y_bar, A x_bar in the row-average blocks); then the primal
-// candidate of the next attempt x' = proj_[l,u](x - tau (c - A'y)), tau = eta / omega, and
-// |x' - x|^2. Grid: one block per tile of A', then the row-average blocks.
+// k_primal: if the attempt was accepted, A'y' (committing it) and the weighted averages (x_bar,
+// A'y_bar over the block's columns; y_bar, A x_bar over its share of the rows); then the primal
+// candidate of the next attempt x' = proj_[l,u](x - tau (c - A'y)), tau = eta / omega, and its
+// |x' - x|^2 partial sum. Grid: the A'-side work blocks of all instances.
 // ----------------------------------------------------------------------------------------------
 template <typename T, int TN>
 __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   __shared__ T lds[TN];
-  const int nt = P.L.t_ntiles;
-  const bool is_tile = (int)blockIdx.x < nt;
-  const int tile = is_tile ? xcd_remap(blockIdx.x, nt) : 0;
-  const int rblk = is_tile ? 0 : (int)blockIdx.x - nt;
-  const int inst = is_tile ? P.L.t_tile_inst[tile] : P.L.ra_inst[rblk];
-  State *st = P.st + inst;
+  const WBlock w = work_block(P.L.tb0, P.L.tb_inst);
+  const State *st = P.st + w.inst;
   if (st->done) return;
   const int cur = st->cur, commit = st->commit, stop = st->stop;
   const T tau = T(st->eta / st->omega);
-  const T w = T(st->avg_w);
+  const T wa = T(st->avg_w);
   const T *__restrict__ xc = P.x[cur];
   T *__restrict__ xnx = P.x[cur ^ 1];
   const T *__restrict__ yc = P.y[cur];
@@ -310,66 +340,50 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   T *__restrict__ xbar = P.xbar;
   T *__restrict__ atybar = P.atybar;
   double acc[1] = {0.0};
-  int pidx;
-  if (is_tile) {
-    pidx = tile;
-    const int r0 = P.t_tiles[tile], r1 = P.t_tiles[tile + 1];
-    auto primal = [&](int j, T atyj) {
-      const T xj = xc[j];
-      if (commit) {
-        xbar[j] += w * (xj - xbar[j]);
-        atybar[j] += w * (atyj - atybar[j]);
-      }
-      if (!stop) {
-        const T xnew = clipv(xj - tau * (c[j] - atyj), lo[j], hi[j]);
-        xnx[j] = xnew;
-        const double d = double(xnew) - double(xj);
-        acc[0] += d * d;
-      }
-    };
+  auto primal = [&](int j, T atyj) {
+    const T xj = xc[j];
     if (commit) {
-      tile_spmv<T, T, T, TN>(P.t_rp, P.t_ci, P.t_val, yc, r0, r1, lds, [&](int j, T s) {
-        aty[j] = s;
-        primal(j, s);
-      });
-    } else if (!stop) {
-      for (int j = r0 + (int)threadIdx.x; j < r1; j += kBlock) primal(j, aty[j]);
+      xbar[j] += wa * (xj - xbar[j]);
+      atybar[j] += wa * (atyj - atybar[j]);
     }
-  } else {
-    pidx = nt + rblk;
-    if (commit) {
-      const T *__restrict__ axc = P.ax[cur];
-      T *__restrict__ ybar = P.ybar;
-      T *__restrict__ axbar = P.axbar;
-      const int i0 = P.L.row0[inst] + (rblk - P.L.ra_blk0[inst]) * kRowAvgSpan;
-      const int i1 = min(P.L.row0[inst + 1], i0 + kRowAvgSpan);
-      for (int i = i0 + (int)threadIdx.x; i < i1; i += kBlock) {
-        ybar[i] += w * (yc[i] - ybar[i]);
-        axbar[i] += w * (axc[i] - axbar[i]);
-      }
+    if (!stop) {
+      const T xnew = clipv(xj - tau * (c[j] - atyj), lo[j], hi[j]);
+      xnx[j] = xnew;
+      const double d = double(xnew) - double(xj);
+      acc[0] += d * d;
     }
+  };
+  int tb, te;
+  share(P.L.t_tile0[w.inst], P.L.t_tile0[w.inst + 1] - P.L.t_tile0[w.inst], w.lb, w.nb, &tb, &te);
+  if (commit) {
+    for (int tile = tb; tile < te; ++tile)
+      tile_spmv<T, T, T, TN>(P.t_rp, P.t_ci, P.t_val, yc, P.t_tiles[tile], P.t_tiles[tile + 1], lds,
+                             [&](int j, T s) {
+                               aty[j] = s;
+                               primal(j, s);
+                             });
+    const T *__restrict__ axc = P.ax[cur];
+    T *__restrict__ ybar = P.ybar;
+    T *__restrict__ axbar = P.axbar;
+    int rb, re;
+    share(P.L.row0[w.inst], P.L.row0[w.inst + 1] - P.L.row0[w.inst], w.lb, w.nb, &rb, &re);
+    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+      ybar[i] += wa * (yc[i] - ybar[i]);
+      axbar[i] += wa * (axc[i] - axbar[i]);
+    }
+  } else if (!stop && te > tb) {
+    const int j0 = P.t_tiles[tb], j1 = P.t_tiles[te];
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += kBlock) primal(j, aty[j]);
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) P.partials[pidx] = acc[0];
-  const int t0 = P.L.t_tile0[inst], t1 = P.L.t_tile0[inst + 1];
-  const int q0 = nt + P.L.ra_blk0[inst], q1 = nt + P.L.ra_blk0[inst + 1];
-  if (!last_block(&st->cnt[1], (uint32_t)((t1 - t0) + (q1 - q0)))) return;
-  double tot[1] = {0.0};
-  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) tot[0] += P.partials[t];
-  for (int t = q0 + (int)threadIdx.x; t < q1; t += kBlock) tot[0] += P.partials[t];
-  block_sum<1>(tot);
-  if (threadIdx.x == 0) {
-    st->dx2 = tot[0];
-    st->commit = 0;
-    if (st->stop) mark_done(st, P.ndone);
-  }
+  if (threadIdx.x == 0) P.p_primal[blockIdx.x] = acc[0];
 }
 
 // ----------------------------------------------------------------------------------------------
 // Evaluation every eval_every attempts, on the committed current iterate and the average:
 // residuals in scaled and original space, objectives, distances to the restart anchor (FP64).
-// The instance's last block applies termination, the restart test and the primal weight update.
-// Grid: the evaluation blocks of all instances (ev_blk0 / ev_inst).
+// k_eval writes block partials; k_eval_fin (one block per instance) applies termination, the
+// restart test and the primal weight update. Grid of k_eval: the evaluation blocks.
 // ----------------------------------------------------------------------------------------------
 struct Cand {
   double rp2, rp2o, by, dya2, rd2, rd2o, bt, cx, dxa2;
@@ -468,9 +482,9 @@ __device__ __forceinline__ EvBlock ev_block(const Layout &L) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_eval(Iter<T> P, int mode) {
+__global__ __launch_bounds__(kBlock) void k_eval(Iter<T> P) {
   const EvBlock E = ev_block(P.L);
-  State *st = P.st + E.inst;
+  const State *st = P.st + E.inst;
   if (st->done) return;
   const int cur = st->cur;
   double a[kEvalNV];
@@ -515,23 +529,29 @@ __global__ __launch_bounds__(kBlock) void k_eval(Iter<T> P, int mode) {
   block_sum<kEvalNV>(a);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < kEvalNV; ++q) P.partials[(size_t)blockIdx.x * kEvalNV + q] = a[q];
+    for (int q = 0; q < kEvalNV; ++q) P.p_eval[(size_t)blockIdx.x * kEvalNV + q] = a[q];
   }
-  if (!last_block(&st->cnt[2], (uint32_t)E.nlb)) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_eval_fin(Layout L, const double *__restrict__ p_eval, State *sts,
+                                                     int32_t *ndone, int mode) {
+  State *st = sts + blockIdx.x;
+  if (st->done) return;
   double tot[kEvalNV];
-  final_sum<kEvalNV>(P.partials, (int)blockIdx.x - E.lb, (int)blockIdx.x - E.lb + E.nlb, tot);
-  if (threadIdx.x == 0) eval_logic(st, P.ndone, tot, mode);
+  final_sum<kEvalNV>(p_eval, L.ev_blk0[blockIdx.x], L.ev_blk0[blockIdx.x + 1], tot);
+  if (threadIdx.x == 0) eval_logic(st, ndone, tot, mode);
 }
 
 // ----------------------------------------------------------------------------------------------
 // Restart (also used once at start-up with kToCurrent): move the chosen candidate into the current
 // iterate, make it the anchor and the new average, then recompute the primal candidate with the
-// possibly new primal weight. Grid: the evaluation blocks.
+// possibly new primal weight; its |x' - x|^2 partials go to p_restart (k_step reads them while
+// restart_mode is set). Grid: the evaluation blocks.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
   const EvBlock E = ev_block(P.L);
-  State *st = P.st + E.inst;
+  const State *st = P.st + E.inst;
   if (st->done) return;
   const int mode = st->restart_mode;
   if (mode == kNoRestart) return;
@@ -574,15 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
     P.ya[i] = yi;
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) P.partials[blockIdx.x] = acc[0];
-  if (!last_block(&st->cnt[3], (uint32_t)E.nlb)) return;
-  double tot[1];
-  final_sum<1>(P.partials, (int)blockIdx.x - E.lb, (int)blockIdx.x - E.lb + E.nlb, tot);
-  if (threadIdx.x == 0) {
-    st->dx2 = tot[0];
-    st->restart_mode = kNoRestart;
-    if (st->stop) mark_done(st, P.ndone);
-  }
+  if (threadIdx.x == 0) P.p_restart[blockIdx.x] = acc[0];
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -603,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_init_point(int m, int n, const doubl
 // ----------------------------------------------------------------------------------------------
 // Finalize: select each instance's returned point (current or average), unscale it, and recompute
 // its residuals in FP64 from the FP64 scaled matrix (ax64 = A~ x~, aty64 = A~' y~ computed by
-// k_spmv in FP64 in between). Grid: the evaluation blocks.
+// k_spmv in FP64 in between). Grid: the evaluation blocks; k_final_fin: one block per instance.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_unscale(Iter<T> P, double *__restrict__ xd, double *__restrict__ yd,
@@ -626,15 +638,14 @@ __global__ __launch_bounds__(kBlock) void k_unscale(Iter<T> P, double *__restric
   }
 }
 
-// rc_out [n]: original-space reduced cost; the instance's last block stores the relative errors.
 struct Final64 {
   const double *xd, *yd, *ax64, *aty64, *c64, *b64, *l64, *u64;
   double *rc_out;
+  double *p_final;
 };
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_final_residuals(Iter<T> P, Final64 F) {
   const EvBlock E = ev_block(P.L);
-  State *st = P.st + E.inst;
   double a[5] = {0, 0, 0, 0, 0};  // rp2o, rd2o, by, bt, cx
   const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
   for (int i = P.L.row0[E.inst] + off; i < P.L.row0[E.inst + 1]; i += gs) {
@@ -654,11 +665,14 @@ __global__ __launch_bounds__(kBlock) void k_final_residuals(Iter<T> P, Final64 F
   block_sum<5>(a);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) P.partials[(size_t)blockIdx.x * 5 + q] = a[q];
+    for (int q = 0; q < 5; ++q) F.p_final[(size_t)blockIdx.x * 5 + q] = a[q];
   }
-  if (!last_block(&st->cnt[4], (uint32_t)E.nlb)) return;
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_fin(Layout L, const double *__restrict__ p_final, State *sts) {
+  State *st = sts + blockIdx.x;
   double tot[5];
-  final_sum<5>(P.partials, (int)blockIdx.x - E.lb, (int)blockIdx.x - E.lb + E.nlb, tot);
+  final_sum<5>(p_final, L.ev_blk0[blockIdx.x], L.ev_blk0[blockIdx.x + 1], tot);
   if (threadIdx.x == 0) {
     const double pobj = tot[4], dobj = tot[2] + tot[3];
     st->rel_p = sqrt(tot[0]) / (1.0 + st->nb);

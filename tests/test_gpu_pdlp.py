@@ -8,13 +8,18 @@ Tolerances:
     sums of the Pock-Chambolle pass are taken in a different order, so bitwise equality is not
     expected.
   * Transpose: bit-exact (integer work; the values are gathered, not computed).
-  * Iterate tracking (FP64): |x_k^gpu - x_k^orc| <= 1e-9 |x_k^orc| (likewise y and omega) for
-    k = 1..100, unless the oracle logged a discrete decision with relative margin < 1e-12 at or
-    before k. The step size eta is a ratio of squared step lengths |dx|^2, |dy|^2: a relative error
-    e of the iterates enters it as e |x| / |dx| (and e |y| / |dy|), so its bound is 1e-9 times the
-    largest such factor the oracle recorded up to k.
-  * End to end: relative KKT <= tol as re-evaluated by the oracle from the returned point, and the
-    objective within 1e-4 relative (max(1, |f*|)) of HiGHS.
+  * Iterate tracking (FP64): |x_k^gpu - x_k^orc| <= B_k |x_k^orc| (likewise y and omega) for
+    k = 1..100 with B_k = max(1e-9, 10 d_k), where d_k is how far the oracle's own iterates move at
+    attempt k when its matrix values and costs change by one ulp (on degenerate LPs the method
+    amplifies rounding differences by ~15 % per attempt, and d_k reaches 1e-9 near k = 90). Attempts
+    after a discrete decision with relative margin < 1e-12 are not compared. The step size eta is a
+    ratio of squared step lengths |dx|^2, |dy|^2: a relative error e of the iterates enters it as
+    e |x| / |dx| (and e |y| / |dy|), so its bound is B_k times the largest such factor the oracle
+    recorded up to k.
+  * End to end: relative KKT <= tol as re-evaluated by the oracle from the returned point. The
+    objective: within 1e-4 relative (max(1, |f|)) of the oracle solved to the same tolerance, and
+    within 2.5 tol of the exact optimum f* (HiGHS): the gap test |pobj - dobj| <= tol (1 + |pobj| +
+    |dobj|) alone allows an objective error of about 2 tol |f*|.
 """
 import sys
 
@@ -112,6 +117,26 @@ def test_transpose_and_scaling(pdlp):
     assert np.array_equal(s["t_val"], tv)  # gathered, so bitwise equal to the row copy
 
 
+def _self_divergence(lp, K, base):
+    """How far the oracle's own iterates move when its matrix values and costs change by one ulp
+    (two random sign patterns): the precision to which any implementation with another
+    summation order can be expected to track it."""
+    import copy
+    div = np.zeros(K)
+    for seed in (1, 2):
+        rng = np.random.default_rng(seed)
+        lp2 = copy.deepcopy(lp)
+        lp2.val = lp.val * (1 + 2.0**-52 * rng.choice([-1.0, 1.0], size=lp.val.size))
+        lp2.c = lp.c * (1 + 2.0**-52 * rng.choice([-1.0, 1.0], size=lp.c.size))
+        tr = oracle.solve(lp2, tol=0.0, iter_limit=K, trace_len=K).trace
+        for k in range(K):
+            for key in ("x", "y"):
+                ref = base[key][k]
+                d = np.linalg.norm(tr[key][k] - ref) / max(np.linalg.norm(ref), 1e-30)
+                div[k] = max(div[k], d)
+    return div
+
+
 def _tracking(pdlp, lp, K=100, label=""):
     orc = oracle.solve(lp, tol=0.0, iter_limit=K, trace_len=K)
     tr = orc.trace
@@ -120,6 +145,8 @@ def _tracking(pdlp, lp, K=100, label=""):
     if bad.size:
         cut = int(bad[0])  # compare only before the first near-tie
         say(label, "near-tie at attempt", cut + 1, "- comparing attempts 1 ..", cut)
+    div = _self_divergence(lp, K, tr)
+    bound = np.maximum(1e-9, 10.0 * np.maximum.accumulate(div))
     ks = list(range(1, cut + 1))
     worst = 0.0
     with pdlp.Problem(lp, precision="fp64", tile_nnz=1024, warm_fallback=False) as p:
@@ -133,12 +160,14 @@ def _tracking(pdlp, lp, K=100, label=""):
             eom = abs(sol.info["omega"] - tr["omega"][k - 1]) / tr["omega"][k - 1]
             cond = float(tr["cond"][:k].max())
             assert sol.info["iterations"] == k
-            assert max(ex, ey, eom) <= 1e-9, (label, k, ex, ey, eom)
-            assert eeta <= 1e-9 * cond, (label, k, eeta, cond)
+            b = bound[k - 1]
+            assert max(ex, ey, eom) <= b, (label, k, ex, ey, eom, b)
+            assert eeta <= b * cond, (label, k, eeta, cond, b)
             worst = max(worst, ex, ey, eom)
     flags = tr["flags"][:cut]
     say(label, "tracked", cut, "attempts; accepted", int((flags & 1).sum()), "restarts",
-        int(((flags & 4) > 0).sum()), "worst iterate rel err %.2e" % worst)
+        int(((flags & 4) > 0).sum()), "worst iterate rel err %.2e; oracle 1-ulp self-divergence at %d: %.2e"
+        % (worst, cut, div[cut - 1]))
 
 
 def test_tracking_fp64_setcover(pdlp):
@@ -157,28 +186,46 @@ def test_tracking_fp64_energy(pdlp):
 def test_end_to_end_setcover(pdlp, prec):
     lp = g.set_cover(0)  # 2000 x 5000, the correctness / latency workload
     f, _, _ = P.highs(lp)
+    orc = oracle.solve(lp, tol=1e-4)
     with pdlp.Problem(lp, precision=prec) as p:
         info = p.solve(tol=1e-4)
         sol = p.get()
-    say("setcover", prec, info["status_name"], info["iterations"], info["primal_obj"], f)
+    say("setcover", prec, info["status_name"], info["iterations"], info["primal_obj"], "oracle", orc.pobj, "highs", f)
     assert info["status"] == pdlp.OPTIMAL
     k = oracle.kkt(lp, sol.x, sol.y)
     assert k["rel_kkt"] <= 1e-4, k
-    assert abs(info["primal_obj"] - f) <= 1e-4 * max(1.0, abs(f))
+    assert abs(info["primal_obj"] - orc.pobj) <= 1e-4 * max(1.0, abs(orc.pobj))
+    assert abs(info["primal_obj"] - f) <= 2.5e-4 * max(1.0, abs(f))
     assert abs(k["pobj"] - info["primal_obj"]) <= 1e-9 * max(1.0, abs(f))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_end_to_end_energy(pdlp, prec):
+    lp = g.energy(4, T=96, N=8, K=6, E=16)
+    f, _, _ = P.highs(lp)
+    orc = oracle.solve(lp, tol=1e-4)
+    with pdlp.Problem(lp, precision=prec) as p:
+        info = p.solve(tol=1e-4, iter_limit=400_000)
+        sol = p.get()
+    say("energy", prec, info["status_name"], info["iterations"], info["primal_obj"], "oracle", orc.pobj,
+        orc.iterations, "highs", f)
+    assert info["status"] == pdlp.OPTIMAL
+    assert oracle.kkt(lp, sol.x, sol.y)["rel_kkt"] <= 1e-4
+    assert abs(info["primal_obj"] - orc.pobj) <= 1e-4 * max(1.0, abs(orc.pobj))
+    assert abs(info["primal_obj"] - f) <= 2.5e-4 * max(1.0, abs(f))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_end_to_end_general(pdlp, prec):
-    lp = g.general_sparse(5, m=3000, n=6000, cap=1000)
+    lp = g.general_sparse(5, m=3000, n=6000, cap=1000)  # hard for PDLP: ~2e5 attempts
     f, _, _ = P.highs(lp)
     with pdlp.Problem(lp, precision=prec) as p:
-        info = p.solve(tol=1e-4, iter_limit=200_000)
+        info = p.solve(tol=1e-4, iter_limit=600_000)
         sol = p.get()
     say("general", prec, info["status_name"], info["iterations"], info["primal_obj"], f)
     assert info["status"] == pdlp.OPTIMAL
     assert oracle.kkt(lp, sol.x, sol.y)["rel_kkt"] <= 1e-4
-    assert abs(info["primal_obj"] - f) <= 1e-4 * max(1.0, abs(f))
+    assert abs(info["primal_obj"] - f) <= 2.5e-4 * max(1.0, abs(f))
 
 
 def test_fp64_matches_oracle_iterations(pdlp):
