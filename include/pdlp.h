@@ -63,7 +63,8 @@ typedef struct pdlp_options {
   int32_t pock_chambolle;  /* 1 = one Pock-Chambolle pass with alpha = 1 after Ruiz (default 1) */
   int32_t use_graphs;      /* 1 = run each evaluation interval as one captured hipGraph (default 1) */
   int32_t device_ptrs;     /* 1 = data pointers are device pointers (default 0) */
-  int32_t tile_nnz;        /* SpMV tile size in nonzeros; 0 = autotune (default 0) */
+  int32_t tile_nnz;        /* SpMV chunk size cap in nonzeros (512, 1024, 2048 or 4096);
+                              0 = autotune (default 0) */
   int32_t verbose;         /* 0 silent, 1 one line per solve, 2 one line per evaluation */
   int64_t device_mem_limit;/* > 0: cap on the bytes this handle may allocate (default 0 = none) */
   void *stream;            /* hipStream_t to order work on; NULL = library-owned stream */
@@ -72,7 +73,9 @@ typedef struct pdlp_options {
   int32_t kernel_timing;   /* 1 = bracket every launch of the two iteration kernels with HIP events
                               on the handle's stream (graphs are not used then); read the totals with
                               pdlp_kernel_stats (default 0) */
-  int32_t reserved[6];
+  int32_t work_blocks;     /* blocks per SpMV kernel across all instances (each owns a contiguous run
+                              of tiles); 0 = 2048 (default 0) */
+  int32_t reserved[5];
 } pdlp_options;
 
 typedef struct pdlp_result {
@@ -141,14 +144,23 @@ int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_resul
 int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y);
 
 /*
- * Scaling diagnostics: Dr [m] and Dc [n] (A~ = diag(Dr) A diag(Dc)), and optionally the scaled
- * matrix values in the CSR order of A (scaled_val [nnz], FP64) and the transpose's CSR
- * (t_row_ptr [n+1], t_col [nnz], t_val [nnz] scaled). Any pointer may be NULL. Host pointers.
+ * Scaling diagnostics in the caller's numbering: Dr [m] and Dc [n] (A~ = diag(Dr) A diag(Dc)) and,
+ * optionally, the scaled matrix values in the caller's CSR order (scaled_val [nnz], FP64). Any pointer
+ * may be NULL. Host pointers.
  */
-int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val, int32_t *t_row_ptr,
-                     int32_t *t_col, double *t_val);
+int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val);
 
-/* SpMV schedule chosen for A and A': tile size in nonzeros and number of tiles of each. */
+/*
+ * The matrix as stored on the device, for inspection: inside a handle the rows and the columns are
+ * renumbered so that rows of A and of A' come sorted by length class (stable within a class).
+ * row_ptr [m+1], col [nnz], val [nnz] is the scaled A (FP64) in internal numbering; t_row_ptr [n+1],
+ * t_col [nnz], t_val [nnz] its transpose as built on the device; internal row i is the caller's
+ * row row_perm[i] and internal column j the caller's column col_perm[j]. Any pointer may be NULL.
+ */
+int pdlp_get_internal(pdlp_problem *p, int32_t *row_ptr, int32_t *col, double *val, int32_t *t_row_ptr,
+                      int32_t *t_col, double *t_val, int32_t *row_perm, int32_t *col_perm);
+
+/* SpMV schedule chosen for A and A': chunk size cap in nonzeros and the number of chunks of each. */
 int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at);
 
 /*

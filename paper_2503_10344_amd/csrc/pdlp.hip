@@ -124,36 +124,52 @@ static void validate(const HostProblem &P) {
   }
 }
 
-// Tile schedule of rows [r0, r1) (see tile_spmv): runs of consecutive rows with <= tn nonzeros
-// and <= kBlock rows; a row longer than tn alone. An empty range yields one empty tile so that
-// every instance owns at least one block. Tile boundaries are appended to `t`.
-static void build_tiles(const int32_t *rp, int32_t r0, int32_t r1, int tn, std::vector<int32_t> &t) {
-  if (r1 == r0) {
-    t.push_back(r1);  // empty tile [r0, r0)
-    return;
-  }
-  int64_t acc = 0;
-  int cnt = 0;
-  for (int32_t i = r0; i < r1; ++i) {
-    const int64_t len = (int64_t)rp[i + 1] - rp[i];
-    if (len > tn) {
-      if (cnt > 0) t.push_back(i);
-      t.push_back(i + 1);
-      acc = 0, cnt = 0;
-      continue;
-    }
-    if (cnt > 0 && (acc + len > tn || cnt == kBlock)) {
-      t.push_back(i);
-      acc = 0, cnt = 0;
-    }
-    acc += len, cnt += 1;
-  }
-  if (cnt > 0) t.push_back(r1);
+// Length class of a row (see chunk_rows): 0 for len <= 3, else floor(log2 len) - 1, at most 6.
+static int length_class(int64_t len) {
+  if (len <= 3) return 0;
+  const int c = 62 - __builtin_clzll((unsigned long long)len);
+  return c < 6 ? c : 6;
 }
 
-static const int kTileCandidates[] = {512, 1024, 2048, 4096};
+// Chunks of rows [r0, r1) (rows sorted by descending class): runs of consecutive rows of one class
+// with at most `cap` nonzeros (a longer row alone) and at most four wave passes. Chunk boundaries
+// are appended to `rows`, classes to `cls`. An empty range yields one empty chunk so that every
+// instance owns at least one.
+static void build_chunks(const int32_t *rp, int32_t r0, int32_t r1, int cap, std::vector<int32_t> &rows,
+                         std::vector<int8_t> &cls) {
+  if (r1 == r0) {
+    rows.push_back(r1);
+    cls.push_back(0);
+    return;
+  }
+  int32_t start = r0;
+  int c_start = length_class((int64_t)rp[r0 + 1] - rp[r0]);
+  int64_t acc = 0;
+  for (int32_t i = r0; i < r1; ++i) {
+    const int64_t len = (int64_t)rp[i + 1] - rp[i];
+    const int c = length_class(len);
+    const int max_rows = (kWave >> c_start) * 4;
+    if (i > start && (c != c_start || acc + len > cap || i - start >= max_rows)) {
+      rows.push_back(i);
+      cls.push_back((int8_t)c_start);
+      start = i, c_start = c, acc = 0;
+    }
+    acc += len;
+  }
+  rows.push_back(r1);
+  cls.push_back((int8_t)c_start);
+}
 
-// Autotune cache: matrix signature -> chosen tile size.
+// Stable order of the items [lo, hi) by descending length class; out receives old indices.
+static void class_order(const std::vector<int64_t> &len, int32_t lo, int32_t hi, std::vector<int32_t> &out) {
+  std::vector<int32_t> bucket[7];
+  for (int32_t i = lo; i < hi; ++i) bucket[length_class(len[(size_t)(i - lo)])].push_back(i);
+  for (int c = 6; c >= 0; --c) out.insert(out.end(), bucket[c].begin(), bucket[c].end());
+}
+
+static const int kChunkCandidates[] = {512, 1024, 2048, 4096};
+
+// Autotune cache: matrix signature -> chosen chunk size.
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tune_cache;
 
@@ -168,21 +184,25 @@ struct Solver {
   Arena mem;
   int32_t K = 1, m = 0, n = 0, nnz = 0;
   // instance layout (host)
-  std::vector<int32_t> h_row0, h_col0, h_nnz0, h_a_tile0, h_t_tile0, h_ab0, h_tb0, h_ev0;
+  std::vector<int32_t> h_row0, h_col0, h_nnz0, h_a_chunk0, h_t_chunk0, h_ab0, h_tb0, h_ev0;
   std::vector<int32_t> h_arp, h_trp;
   std::string sig;
   // instance layout (device)
-  int32_t *d_row0 = nullptr, *d_col0 = nullptr, *d_nnz0 = nullptr, *d_a_tile0 = nullptr, *d_t_tile0 = nullptr;
+  int32_t *d_row0 = nullptr, *d_col0 = nullptr, *d_nnz0 = nullptr, *d_a_chunk0 = nullptr, *d_t_chunk0 = nullptr;
   int32_t *d_ab0 = nullptr, *d_ab_inst = nullptr, *d_tb0 = nullptr, *d_tb_inst = nullptr;
   int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
   int ab_blocks = 1, tb_blocks = 1, ev_blocks = 1;
   int work_blocks = 2048;  // target number of work blocks per side for the whole handle
   // matrix
   int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr, *perm = nullptr;
-  int32_t *a_tiles = nullptr, *t_tiles = nullptr;
+  int32_t *a_chunk_row = nullptr, *t_chunk_row = nullptr;
+  int8_t *a_chunk_cls = nullptr, *t_chunk_cls = nullptr;
   double *a_v64 = nullptr, *t_v64 = nullptr;
   T *a_v = nullptr, *t_v = nullptr;
-  int tile_nnz = 2048, a_ntiles = 0, t_ntiles = 0;
+  int chunk_nnz = 2048, a_nchunks = 0, t_nchunks = 0;
+  // internal <-> external numbering (rows and columns sorted by length class per instance)
+  std::vector<int32_t> h_perm_r, h_perm_c, h_inv_r, h_inv_c, h_nnz_map;
+  int32_t *d_perm_r = nullptr, *d_perm_c = nullptr, *d_inv_r = nullptr, *d_inv_c = nullptr;
   // data
   uint8_t *sense = nullptr;
   double *Dr = nullptr, *Dc = nullptr, *c64 = nullptr, *b64 = nullptr, *l64 = nullptr, *u64 = nullptr;
@@ -194,6 +214,7 @@ struct Solver {
   // finalize / staging
   double *xd = nullptr, *yd = nullptr, *ax64 = nullptr, *aty64 = nullptr;
   double *x_out = nullptr, *y_out = nullptr, *rc_out = nullptr, *stage_n = nullptr, *stage_m = nullptr;
+  double *x_ext = nullptr, *y_ext = nullptr, *rc_ext = nullptr;  // solution in the caller's numbering
   // reductions, state
   double *p_dual = nullptr, *p_primal = nullptr, *p_restart = nullptr, *p_eval = nullptr, *p_final = nullptr;
   double *d_red = nullptr;
@@ -252,6 +273,7 @@ struct Solver {
   // ---------------------------------------------------------------------------------------------
   void create(const std::vector<const HostProblem *> &Hs, const pdlp_options &o) {
     opt = o;
+    if (o.work_blocks > 0) work_blocks = o.work_blocks;
     K = (int32_t)Hs.size();
     mem.limit = o.device_mem_limit;
     if (o.stream) {
@@ -272,21 +294,40 @@ struct Solver {
       h_row0.push_back((int32_t)M), h_col0.push_back((int32_t)N), h_nnz0.push_back((int32_t)Z);
     }
     m = (int32_t)M, n = (int32_t)N, nnz = (int32_t)Z;
-    h_arp.resize((size_t)m + 1);
+    // concatenate, renumbering rows and columns of every instance by descending length class
+    h_arp.assign((size_t)m + 1, 0);
     std::vector<int32_t> ci((size_t)nnz);
     std::vector<double> val((size_t)nnz), c((size_t)n), b((size_t)m), l((size_t)n), u((size_t)n);
     std::vector<uint8_t> sn((size_t)m);
-    h_arp[0] = 0;
+    h_perm_r.clear(), h_perm_c.clear();
+    h_inv_r.assign((size_t)m, 0), h_inv_c.assign((size_t)n, 0), h_nnz_map.assign((size_t)nnz, 0);
     for (int q = 0; q < K; ++q) {
       const HostProblem &H = *Hs[q];
       const int32_t r0 = h_row0[q], c0 = h_col0[q], z0 = h_nnz0[q];
-      for (int32_t i = 0; i < H.m; ++i) h_arp[r0 + i + 1] = z0 + H.rp[i + 1];
-      for (int64_t k = 0; k < H.nnz; ++k) ci[z0 + k] = c0 + H.ci[k], val[z0 + k] = H.val[k];
-      std::copy(H.c.begin(), H.c.end(), c.begin() + c0);
-      std::copy(H.l.begin(), H.l.end(), l.begin() + c0);
-      std::copy(H.u.begin(), H.u.end(), u.begin() + c0);
-      std::copy(H.b.begin(), H.b.end(), b.begin() + r0);
-      std::copy(H.sense.begin(), H.sense.end(), sn.begin() + r0);
+      std::vector<int64_t> rlen((size_t)H.m), clen((size_t)H.n, 0);
+      for (int32_t i = 0; i < H.m; ++i) rlen[i] = (int64_t)H.rp[i + 1] - H.rp[i];
+      for (int64_t k = 0; k < H.nnz; ++k) clen[H.ci[k]] += 1;
+      std::vector<int32_t> pr, pc;
+      class_order(rlen, 0, H.m, pr);
+      class_order(clen, 0, H.n, pc);
+      for (int32_t i = 0; i < H.m; ++i) h_perm_r.push_back(r0 + pr[i]), h_inv_r[r0 + pr[i]] = r0 + i;
+      for (int32_t j = 0; j < H.n; ++j) h_perm_c.push_back(c0 + pc[j]), h_inv_c[c0 + pc[j]] = c0 + j;
+      int32_t z = z0;
+      for (int32_t i = 0; i < H.m; ++i) {
+        const int32_t old = pr[i];
+        for (int32_t k = H.rp[old]; k < H.rp[old + 1]; ++k, ++z) {
+          ci[z] = h_inv_c[c0 + H.ci[k]];
+          val[z] = H.val[k];
+          h_nnz_map[z0 + k] = z;
+        }
+        h_arp[r0 + i + 1] = z;
+        b[r0 + i] = H.b[old];
+        sn[r0 + i] = H.sense[old];
+      }
+      for (int32_t j = 0; j < H.n; ++j) {
+        const int32_t old = pc[j];
+        c[c0 + j] = H.c[old], l[c0 + j] = H.l[old], u[c0 + j] = H.u[old];
+      }
     }
     // signature of the sparsity pattern (autotune cache key)
     {
@@ -307,6 +348,8 @@ struct Solver {
     sense = alloc_upload(sn);
     double *c0 = alloc_upload(c), *b0 = alloc_upload(b), *l0 = alloc_upload(l), *u0 = alloc_upload(u);
     d_row0 = alloc_upload(h_row0), d_col0 = alloc_upload(h_col0), d_nnz0 = alloc_upload(h_nnz0);
+    d_perm_r = alloc_upload(h_perm_r), d_perm_c = alloc_upload(h_perm_c);
+    d_inv_r = alloc_upload(h_inv_r), d_inv_c = alloc_upload(h_inv_c);
     t_rp = mem.alloc<int32_t>(n + 1);
     t_ci = mem.alloc<int32_t>(nnz);
     perm = mem.alloc<int32_t>(nnz);
@@ -425,6 +468,7 @@ struct Solver {
     xd = mem.alloc<double>(nn), yd = mem.alloc<double>(mm), ax64 = mem.alloc<double>(mm), aty64 = mem.alloc<double>(nn);
     x_out = mem.alloc<double>(nn), y_out = mem.alloc<double>(mm), rc_out = mem.alloc<double>(nn);
     stage_n = mem.alloc<double>(nn), stage_m = mem.alloc<double>(mm);
+    x_ext = mem.alloc<double>(nn), y_ext = mem.alloc<double>(mm), rc_ext = mem.alloc<double>(nn);
     for (int q = 0; q < 2; ++q) {
       HIPCHK(hipMemsetAsync(xs[q], 0, sizeof(T) * (size_t)nn, stream));
       HIPCHK(hipMemsetAsync(ys[q], 0, sizeof(T) * (size_t)mm, stream));
@@ -459,13 +503,13 @@ struct Solver {
   void set_params() {
     Layout &L = P.L;
     L.K = K;
-    L.row0 = d_row0, L.col0 = d_col0, L.a_tile0 = d_a_tile0, L.t_tile0 = d_t_tile0;
+    L.row0 = d_row0, L.col0 = d_col0, L.a_chunk0 = d_a_chunk0, L.t_chunk0 = d_t_chunk0;
     L.ab0 = d_ab0, L.ab_inst = d_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
-    L.a_ntiles = a_ntiles, L.t_ntiles = t_ntiles, L.ab_blocks = ab_blocks, L.tb_blocks = tb_blocks;
+    L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ab_blocks, L.tb_blocks = tb_blocks;
     L.ev_blocks = ev_blocks;
-    P.a_rp = a_rp, P.a_ci = a_ci, P.a_tiles = a_tiles, P.a_val = a_v;
-    P.t_rp = t_rp, P.t_ci = t_ci, P.t_tiles = t_tiles, P.t_val = t_v;
+    P.a_rp = a_rp, P.a_ci = a_ci, P.a_chunk_row = a_chunk_row, P.a_chunk_cls = a_chunk_cls, P.a_val = a_v;
+    P.t_rp = t_rp, P.t_ci = t_ci, P.t_chunk_row = t_chunk_row, P.t_chunk_cls = t_chunk_cls, P.t_val = t_v;
     P.c = cT, P.l = lT, P.u = uT, P.b = bT, P.sense = sense, P.Dr = Dr, P.Dc = Dc;
     for (int q = 0; q < 2; ++q) P.x[q] = xs[q], P.y[q] = ys[q], P.ax[q] = axs[q];
     P.aty = aty, P.xbar = xbar, P.ybar = ybar, P.axbar = axbar, P.atybar = atybar, P.xa = xa, P.ya = ya;
@@ -476,80 +520,78 @@ struct Solver {
   // ---------------------------------------------------------------------------------------------
   // SpMV schedule
   // ---------------------------------------------------------------------------------------------
-  void make_tiles(int tn) {
-    std::vector<int32_t> ta(1, 0), tt(1, 0);
-    h_a_tile0.assign(1, 0), h_t_tile0.assign(1, 0);
+  void make_chunks(int cap) {
+    std::vector<int32_t> ra, rt;
+    std::vector<int8_t> ca, ct;
+    h_a_chunk0.assign(1, 0), h_t_chunk0.assign(1, 0);
     for (int q = 0; q < K; ++q) {
-      build_tiles(h_arp.data(), h_row0[q], h_row0[q + 1], tn, ta);
-      h_a_tile0.push_back((int32_t)ta.size() - 1);
-      build_tiles(h_trp.data(), h_col0[q], h_col0[q + 1], tn, tt);
-      h_t_tile0.push_back((int32_t)tt.size() - 1);
+      if (ra.empty()) ra.push_back(h_row0[q]);
+      build_chunks(h_arp.data(), h_row0[q], h_row0[q + 1], cap, ra, ca);
+      h_a_chunk0.push_back((int32_t)ca.size());
+      if (rt.empty()) rt.push_back(h_col0[q]);
+      build_chunks(h_trp.data(), h_col0[q], h_col0[q + 1], cap, rt, ct);
+      h_t_chunk0.push_back((int32_t)ct.size());
     }
-    for (int32_t *p : {a_tiles, t_tiles, d_a_tile0, d_t_tile0, d_ab0, d_ab_inst, d_tb0, d_tb_inst})
+    for (void *p : {(void *)a_chunk_row, (void *)t_chunk_row, (void *)a_chunk_cls, (void *)t_chunk_cls,
+                    (void *)d_a_chunk0, (void *)d_t_chunk0, (void *)d_ab0, (void *)d_ab_inst, (void *)d_tb0,
+                    (void *)d_tb_inst})
       if (p) mem.release(p);
-    a_tiles = alloc_upload(ta), t_tiles = alloc_upload(tt);
-    d_a_tile0 = alloc_upload(h_a_tile0), d_t_tile0 = alloc_upload(h_t_tile0);
-    a_ntiles = (int)ta.size() - 1, t_ntiles = (int)tt.size() - 1;
-    tile_nnz = tn;
-    // work blocks: about work_blocks per side in total, shared out by tile count, >= 1 per instance
+    a_chunk_row = alloc_upload(ra), t_chunk_row = alloc_upload(rt);
+    a_chunk_cls = alloc_upload(ca), t_chunk_cls = alloc_upload(ct);
+    d_a_chunk0 = alloc_upload(h_a_chunk0), d_t_chunk0 = alloc_upload(h_t_chunk0);
+    a_nchunks = (int)ca.size(), t_nchunks = (int)ct.size();
+    chunk_nnz = cap;
+    // work blocks: about work_blocks per side in total, shared out by chunk count, >= 1 per instance
     std::vector<int32_t> ab_inst, tb_inst;
-    auto blocks_for = [&](const std::vector<int32_t> &tile0, std::vector<int32_t> &b0, std::vector<int32_t> &binst) {
-      const int64_t total = tile0.back();
+    auto blocks_for = [&](const std::vector<int32_t> &ch0, std::vector<int32_t> &b0, std::vector<int32_t> &binst) {
+      const int64_t total = ch0.back();
       b0.assign(1, 0);
       binst.clear();
       for (int q = 0; q < K; ++q) {
-        const int64_t nt = tile0[q + 1] - tile0[q];
-        int64_t nbq = (nt * work_blocks + total - 1) / std::max<int64_t>(total, 1);
-        nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, nt));
+        const int64_t nc = ch0[q + 1] - ch0[q];
+        int64_t nbq = (nc * work_blocks + total - 1) / std::max<int64_t>(total, 1);
+        nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, (nc + kWaves - 1) / kWaves));
         for (int64_t r = 0; r < nbq; ++r) binst.push_back(q);
         b0.push_back(b0.back() + (int32_t)nbq);
       }
     };
-    blocks_for(h_a_tile0, h_ab0, ab_inst);
-    blocks_for(h_t_tile0, h_tb0, tb_inst);
+    blocks_for(h_a_chunk0, h_ab0, ab_inst);
+    blocks_for(h_t_chunk0, h_tb0, tb_inst);
     ab_blocks = h_ab0.back(), tb_blocks = h_tb0.back();
     d_ab0 = alloc_upload(h_ab0), d_ab_inst = alloc_upload(ab_inst);
     d_tb0 = alloc_upload(h_tb0), d_tb_inst = alloc_upload(tb_inst);
   }
 
   template <typename V, typename X, typename Acc, typename Y>
-  void spmv_tiles(int trans, int tile_begin, int tile_end, const X *x, Y *y) {
+  void spmv_chunks(int trans, const X *x, Y *y) {
     const int32_t *rp = trans ? t_rp : a_rp;
     const int32_t *ci = trans ? t_ci : a_ci;
     const V *v;
     if constexpr (sizeof(V) == sizeof(double)) v = (const V *)(trans ? t_v64 : a_v64);
     else v = (const V *)(trans ? t_v : a_v);
-    const int32_t *tl = (trans ? t_tiles : a_tiles) + tile_begin;
-    const int nt = tile_end - tile_begin;
-    if (nt <= 0) return;
-    switch (tile_nnz) {
-#define CASE(TN)                                                                                           \
-  case TN:                                                                                                  \
-    hipLaunchKernelGGL((k_spmv<V, X, Acc, Y, TN>), dim3(nt), dim3(kBlock), 0, stream, rp, ci, v, tl, nt, x, y); \
-    break;
-      CASE(512) CASE(1024) CASE(2048) CASE(4096)
-#undef CASE
-      default:
-        raise(PDLP_ERR_ARG, "unsupported tile size");
-    }
+    const int nch = trans ? t_nchunks : a_nchunks;
+    if (nch <= 0) return;
+    hipLaunchKernelGGL((k_spmv<V, X, Acc, Y>), dim3((nch + kWaves - 1) / kWaves), dim3(kBlock), 0, stream, rp, ci, v,
+                       (const int32_t *)(trans ? t_chunk_row : a_chunk_row),
+                       (const int8_t *)(trans ? t_chunk_cls : a_chunk_cls), nch, x, y);
   }
-  void spmv_T(int trans, const T *x, T *y) { spmv_tiles<T, T, T, T>(trans, 0, trans ? t_ntiles : a_ntiles, x, y); }
+  void spmv_T(int trans, const T *x, T *y) { spmv_chunks<T, T, T, T>(trans, x, y); }
 
-  // Autotuner: time A x and A'y for each candidate tile size and keep the fastest (the smallest
+  // Autotuner: time A x and A'y for each candidate chunk size and keep the fastest (the smallest
   // size within 3 % of the best). The choice is cached per sparsity signature.
   void choose_schedule() {
     if (opt.tile_nnz > 0) {
       bool ok = false;
-      for (int c : kTileCandidates) ok |= (c == opt.tile_nnz);
+      for (int c : kChunkCandidates) ok |= (c == opt.tile_nnz);
       if (!ok) raise(PDLP_ERR_ARG, "tile_nnz must be one of 512, 1024, 2048, 4096 (or 0 = autotune)");
-      make_tiles(opt.tile_nnz);
+      make_chunks(opt.tile_nnz);
       return;
     }
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       auto it = g_tune_cache.find(sig);
       if (it != g_tune_cache.end()) {
-        make_tiles(it->second);
+        make_chunks(it->second);
         return;
       }
     }
@@ -560,8 +602,8 @@ struct Solver {
       HIPCHK(hipEventCreate(&e1));
       float best = 1e30f;
       std::vector<std::pair<int, float>> times;
-      for (int cand : kTileCandidates) {
-        make_tiles(cand);
+      for (int cand : kChunkCandidates) {
+        make_chunks(cand);
         spmv_T(0, xs[0], axs[0]);
         spmv_T(1, ys[0], aty);
         HIPCHK(hipEventRecord(e0, stream));
@@ -584,7 +626,7 @@ struct Solver {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }
-    make_tiles(pick);
+    make_chunks(pick);
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[sig] = pick;
   }
@@ -593,16 +635,9 @@ struct Solver {
   // Iteration launches
   // ---------------------------------------------------------------------------------------------
   void launch_attempt() {
-    switch (tile_nnz) {
-#define CASE(TN)                                                                                       \
-  case TN:                                                                                              \
-    hipLaunchKernelGGL((k_dual<T, TN>), dim3(ab_blocks), dim3(kBlock), 0, stream, P);                   \
-    launch_step();                                                                                      \
-    hipLaunchKernelGGL((k_primal<T, TN>), dim3(tb_blocks), dim3(kBlock), 0, stream, P);                 \
-    break;
-      CASE(512) CASE(1024) CASE(2048) CASE(4096)
-#undef CASE
-    }
+    hipLaunchKernelGGL(k_dual<T>, dim3(ab_blocks), dim3(kBlock), 0, stream, P);
+    launch_step();
+    hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
   }
   void launch_step() {
     hipLaunchKernelGGL(k_step, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_dual,
@@ -627,20 +662,13 @@ struct Solver {
     }
     for (int r = 0; r < opt.eval_every; ++r) {
       hipEvent_t *e = &pool[(size_t)r * 4];
-      switch (tile_nnz) {
-#define CASE(TN)                                                                                    \
-  case TN:                                                                                           \
-    HIPCHK(hipEventRecord(e[0], stream));                                                            \
-    hipLaunchKernelGGL((k_dual<T, TN>), dim3(ab_blocks), dim3(kBlock), 0, stream, P);                \
-    HIPCHK(hipEventRecord(e[1], stream));                                                            \
-    launch_step();                                                                                   \
-    HIPCHK(hipEventRecord(e[2], stream));                                                            \
-    hipLaunchKernelGGL((k_primal<T, TN>), dim3(tb_blocks), dim3(kBlock), 0, stream, P);              \
-    HIPCHK(hipEventRecord(e[3], stream));                                                            \
-    break;
-        CASE(512) CASE(1024) CASE(2048) CASE(4096)
-#undef CASE
-      }
+      HIPCHK(hipEventRecord(e[0], stream));
+      hipLaunchKernelGGL(k_dual<T>, dim3(ab_blocks), dim3(kBlock), 0, stream, P);
+      HIPCHK(hipEventRecord(e[1], stream));
+      launch_step();
+      HIPCHK(hipEventRecord(e[2], stream));
+      hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
+      HIPCHK(hipEventRecord(e[3], stream));
     }
     launch_eval(kEvalChunk);
     launch_restart();
@@ -700,7 +728,9 @@ struct Solver {
       if (y0s && y0s[q] && mq)
         HIPCHK(hipMemcpyAsync(stage_m + h_row0[q], y0s[q], sizeof(double) * (size_t)mq, kind, stream));
     }
-    start_point(stage_n, stage_m, xs[0], ys[0]);
+    gather64(n, stage_n, d_perm_c, xd);  // external -> internal numbering
+    gather64(m, stage_m, d_perm_r, yd);
+    start_point(xd, yd, xs[0], ys[0]);
     return true;
   }
   void start_point(const double *dx, const double *dy, T *x, T *y) {
@@ -708,6 +738,11 @@ struct Solver {
                        (const double *)Dr, (const double *)Dc, (const double *)l64, (const double *)u64,
                        (const uint8_t *)sense, x, y);
     HIPCHK(hipGetLastError());
+  }
+
+  void gather64(int len, const double *src, const int32_t *idx, double *dst) {
+    if (len <= 0) return;
+    hipLaunchKernelGGL(k_gather64, dim3(grid_for(len)), dim3(kBlock), 0, stream, len, src, idx, dst);
   }
 
   void upload_state() { upload(st, h_st.data(), K); }
@@ -764,7 +799,9 @@ struct Solver {
           if (omega0s && omega0s[q] > 0.0) h_st[q].omega = omega_default[q];
         }
       if (any) {
-        start_point(stage_n, stage_m, xs[0], ys[0]);
+        gather64(n, stage_n, d_perm_c, xd);
+        gather64(m, stage_m, d_perm_r, yd);
+        start_point(xd, yd, xs[0], ys[0]);
         spmv_T(0, xs[0], axs[0]);
         spmv_T(1, ys[0], aty);
         upload_state();
@@ -856,11 +893,14 @@ struct Solver {
 
   void finalize() {
     hipLaunchKernelGGL(k_unscale<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, xd, yd, x_out, y_out);
-    spmv_tiles<double, double, double, double>(0, 0, a_ntiles, xd, ax64);
-    spmv_tiles<double, double, double, double>(1, 0, t_ntiles, yd, aty64);
+    spmv_chunks<double, double, double, double>(0, xd, ax64);
+    spmv_chunks<double, double, double, double>(1, yd, aty64);
     Final64 F{xd, yd, ax64, aty64, c64, b64, l64, u64, rc_out, p_final};
     hipLaunchKernelGGL(k_final_residuals<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, F);
     hipLaunchKernelGGL(k_final_fin, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_final, st);
+    gather64(n, x_out, d_inv_c, x_ext);  // internal -> external numbering
+    gather64(m, y_out, d_inv_r, y_ext);
+    gather64(n, rc_out, d_inv_c, rc_ext);
     HIPCHK(hipGetLastError());
   }
 
@@ -869,41 +909,69 @@ struct Solver {
     if (q < 0 || q >= K) raise(PDLP_ERR_ARG, "instance index out of range");
     const hipMemcpyKind kind = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const int32_t c0 = h_col0[q], nq = h_col0[q + 1] - c0, r0 = h_row0[q], mq = h_row0[q + 1] - r0;
-    if (x && nq) HIPCHK(hipMemcpyAsync(x, x_out + c0, sizeof(double) * (size_t)nq, kind, stream));
-    if (y && mq) HIPCHK(hipMemcpyAsync(y, y_out + r0, sizeof(double) * (size_t)mq, kind, stream));
-    if (rc && nq) HIPCHK(hipMemcpyAsync(rc, rc_out + c0, sizeof(double) * (size_t)nq, kind, stream));
+    if (x && nq) HIPCHK(hipMemcpyAsync(x, x_ext + c0, sizeof(double) * (size_t)nq, kind, stream));
+    if (y && mq) HIPCHK(hipMemcpyAsync(y, y_ext + r0, sizeof(double) * (size_t)mq, kind, stream));
+    if (rc && nq) HIPCHK(hipMemcpyAsync(rc, rc_ext + c0, sizeof(double) * (size_t)nq, kind, stream));
     sync();
     if (res) *res = last[q];
   }
 
-  // Original-space product y = A x = Dr^-1 A~ Dc^-1 x (trans = 0) or y = A'x (trans = 1).
+  // Original-space product y = A x = Dr^-1 A~ Dc^-1 x (trans = 0) or y = A'x (trans = 1), in the
+  // caller's numbering.
   void spmv(int trans, const double *x, double *y) {
     const int in = trans ? m : n, out = trans ? n : m;
     double *sin = trans ? stage_m : stage_n;
+    double *xin = trans ? yd : xd;
+    double *yint = trans ? aty64 : ax64;
     double *sout = trans ? stage_n : stage_m;
     T *tin = trans ? tmp_m : tmp_n;
     T *tout = trans ? tmp_n : tmp_m;
     const hipMemcpyKind k_in = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     const hipMemcpyKind k_out = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (in) HIPCHK(hipMemcpyAsync(sin, x, sizeof(double) * (size_t)in, k_in, stream));
-    hipLaunchKernelGGL(k_div_to<T>, dim3(grid_for(in)), dim3(kBlock), 0, stream, in, (const double *)sin,
+    gather64(in, sin, trans ? d_perm_r : d_perm_c, xin);
+    hipLaunchKernelGGL(k_div_to<T>, dim3(grid_for(in)), dim3(kBlock), 0, stream, in, (const double *)xin,
                        (const double *)(trans ? Dr : Dc), tin);
     spmv_T(trans, tin, tout);
     hipLaunchKernelGGL(k_div_from<T>, dim3(grid_for(out)), dim3(kBlock), 0, stream, out, (const T *)tout,
-                       (const double *)(trans ? Dc : Dr), sout);
+                       (const double *)(trans ? Dc : Dr), yint);
+    gather64(out, yint, trans ? d_inv_c : d_inv_r, sout);
     HIPCHK(hipGetLastError());
     if (out) HIPCHK(hipMemcpyAsync(y, sout, sizeof(double) * (size_t)out, k_out, stream));
     sync();
   }
 
-  void get_scaling(double *dr, double *dc, double *sv, int32_t *trp, int32_t *tci, double *tv) {
-    if (dr) download(dr, Dr, m);
-    if (dc) download(dc, Dc, n);
-    if (sv) download(sv, a_v64, nnz);
+  // Scaling in the caller's numbering: Dr [m], Dc [n], scaled values in the caller's CSR order.
+  void get_scaling(double *dr, double *dc, double *sv) {
+    std::vector<double> hr((size_t)m), hc((size_t)n), hv;
+    download(hr.data(), Dr, m);
+    download(hc.data(), Dc, n);
+    if (sv) {
+      hv.resize((size_t)nnz);
+      download(hv.data(), a_v64, nnz);
+    }
+    sync();
+    if (dr)
+      for (int32_t e = 0; e < m; ++e) dr[e] = hr[h_inv_r[e]];
+    if (dc)
+      for (int32_t e = 0; e < n; ++e) dc[e] = hc[h_inv_c[e]];
+    if (sv)
+      for (int32_t k = 0; k < nnz; ++k) sv[k] = hv[h_nnz_map[k]];
+  }
+
+  // The internal (renumbered, scaled) matrix and its transpose as built on the device, with the
+  // renumbering: internal row i is the caller's row row_perm[i], internal column j is col_perm[j].
+  void get_internal(int32_t *rp, int32_t *ci, double *v, int32_t *trp, int32_t *tci, double *tv, int32_t *pr,
+                    int32_t *pc) {
+    if (rp) download(rp, a_rp, m + 1);
+    if (ci) download(ci, a_ci, nnz);
+    if (v) download(v, a_v64, nnz);
     if (trp) download(trp, t_rp, n + 1);
     if (tci) download(tci, t_ci, nnz);
     if (tv) download(tv, t_v64, nnz);
     sync();
+    if (pr) std::copy(h_perm_r.begin(), h_perm_r.end(), pr);
+    if (pc) std::copy(h_perm_c.begin(), h_perm_c.end(), pc);
   }
 };
 
@@ -1079,13 +1147,23 @@ int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y) {
   return guarded([&] { p->s.visit([&](auto &s) { s.spmv(trans, x, y); }); });
 }
 
-int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val, int32_t *t_row_ptr,
-                     int32_t *t_col, double *t_val) {
+int pdlp_get_scaling(pdlp_problem *p, double *Dr, double *Dc, double *scaled_val) {
   if (!p) {
     pdlp::g_last_error = "NULL handle";
     return PDLP_ERR_ARG;
   }
-  return guarded([&] { p->s.visit([&](auto &s) { s.get_scaling(Dr, Dc, scaled_val, t_row_ptr, t_col, t_val); }); });
+  return guarded([&] { p->s.visit([&](auto &s) { s.get_scaling(Dr, Dc, scaled_val); }); });
+}
+
+int pdlp_get_internal(pdlp_problem *p, int32_t *row_ptr, int32_t *col, double *val, int32_t *t_row_ptr,
+                      int32_t *t_col, double *t_val, int32_t *row_perm, int32_t *col_perm) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    p->s.visit([&](auto &s) { s.get_internal(row_ptr, col, val, t_row_ptr, t_col, t_val, row_perm, col_perm); });
+  });
 }
 
 int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at) {
@@ -1095,9 +1173,9 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
   }
   return guarded([&] {
     p->s.visit([&](auto &s) {
-      if (tile_nnz) *tile_nnz = s.tile_nnz;
-      if (tiles_a) *tiles_a = s.a_ntiles;
-      if (tiles_at) *tiles_at = s.t_ntiles;
+      if (tile_nnz) *tile_nnz = s.chunk_nnz;
+      if (tiles_a) *tiles_a = s.a_nchunks;
+      if (tiles_at) *tiles_at = s.t_nchunks;
     });
   });
 }

@@ -3,6 +3,10 @@
 // One handle solves K >= 1 independent LPs. Their matrices are stored as one block-diagonal CSR
 // (and its transpose) with global row/column indices; every launch covers all instances, and each
 // block looks up the instance it works for. A single-LP handle is the case K = 1.
+//
+// Inside a handle the rows and the columns of every instance are renumbered so that rows of A and
+// rows of A' (columns of A) come sorted by length class (stable within a class). Every vector on
+// the device is in this internal order; inputs and outputs are mapped at the boundary.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,21 +56,24 @@ struct State {
 struct Layout {
   int32_t K;
   const int32_t *row0, *col0;       // [K+1] row / column offsets
-  const int32_t *a_tile0, *t_tile0; // [K+1] tile ranges of A and A'
+  const int32_t *a_chunk0, *t_chunk0; // [K+1] chunk ranges of A and A'
   const int32_t *ab0, *ab_inst;     // [K+1], [ab_blocks] A-side work blocks (k_dual)
   const int32_t *tb0, *tb_inst;     // [K+1], [tb_blocks] A'-side work blocks (k_primal)
   const int32_t *ev_blk0, *ev_inst; // [K+1], [ev_blocks] evaluation blocks
-  int32_t a_ntiles, t_ntiles, ab_blocks, tb_blocks, ev_blocks;
+  int32_t a_nchunks, t_nchunks, ab_blocks, tb_blocks, ev_blocks;
 };
 
 // Everything an iteration kernel reads or writes. Passed by value.
 template <typename T>
 struct Iter {
   Layout L;
-  // A (row view) and A' (column view), scaled, in the iteration precision
-  const int32_t *a_rp, *a_ci, *a_tiles;
+  // A (row view) and A' (column view), scaled, in the iteration precision, rows sorted by length
+  // class; chunk_row[k] is the first row of chunk k and chunk_cls[k] its class
+  const int32_t *a_rp, *a_ci, *a_chunk_row;
+  const int8_t *a_chunk_cls;
   const T *a_val;
-  const int32_t *t_rp, *t_ci, *t_tiles;
+  const int32_t *t_rp, *t_ci, *t_chunk_row;
+  const int8_t *t_chunk_cls;
   const T *t_val;
   // problem data, scaled
   const T *c, *l, *u, *b;

@@ -115,59 +115,73 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 }
 
 // ----------------------------------------------------------------------------------------------
-// Tile SpMV engine.
+// Row-class chunk SpMV engine.
 //
-// A tile is either a run of consecutive rows holding at most TN nonzeros and at most kBlock rows
-// (stream tile) or one row longer than TN (long tile). Stream tiles stage the products
-// val[e] * x[col[e]] in LDS with coalesced loads of val/col, then G = largest power of two with
-// G * rows <= kBlock (G <= 64) lanes reduce each row from LDS and a G-lane shuffle tree finishes
-// it. A long row is split over the whole block with a wave-shuffle + LDS reduction. The epilogue
-// epi(row, sum) runs in exactly one thread per row.
+// Inside a handle the rows of A (and of A') are stored sorted by length class: class c holds the
+// rows with 2^(c+1) <= len < 2^(c+2) (class 0: len <= 3, class 6: len >= 128), and a row of class
+// c is summed by G = 2^c lanes. A chunk is a run of consecutive rows of one class holding a bounded
+// number of nonzeros. A wave walks its chunks: lane groups of G take consecutive rows (so the 64
+// lanes of a wave read one contiguous stretch of val/col even for the shortest rows), each lane
+// sums its strided share with four independent accumulators (four loads and gathers in flight per
+// lane), a G-lane shuffle tree finishes the row, and the group's first lane runs the row's
+// epilogue epi(row, sum, prefetched operands). No LDS and no block barrier is involved.
+// The summation order of a row depends only on its length, so results are deterministic.
 // ----------------------------------------------------------------------------------------------
-template <typename V, typename X, typename Acc, int TN, typename Epi>
-__device__ __forceinline__ void tile_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                          const V *__restrict__ val, const X *__restrict__ x, int r0,
-                                          int r1, Acc *lds, Epi &&epi) {
-  const int tid = threadIdx.x;
-  const int k0 = rp[r0], k1 = rp[r1];
-  const int nt = k1 - k0;
-  if (nt > TN) {  // long row (r1 == r0 + 1)
-    Acc s = Acc(0);
-    for (int e = k0 + tid; e < k1; e += kBlock) s += Acc(val[e]) * Acc(x[ci[e]]);
-    s = block_sum_scalar(s);
-    if (tid == 0) epi(r0, s);
-    return;
+struct NoPre {};
+
+template <typename V, typename X, typename Acc, typename Pre, typename Epi>
+__device__ __forceinline__ void chunk_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                           const V *__restrict__ val, const X *__restrict__ x, int r0, int r1,
+                                           int cls, Pre &&pre, Epi &&epi) {
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  const int G = 1 << cls;
+  const int grp = lane >> cls, gl = lane & (G - 1);
+  const int per = kWave >> cls;
+  using PF = decltype(pre(r0));
+  for (int rb = r0; rb < r1; rb += per) {
+    const int r = rb + grp;
+    const bool act = r < r1;
+    const PF pf = (act && gl == 0) ? pre(r) : PF{};
+    Acc s0 = Acc(0), s1 = Acc(0), s2 = Acc(0), s3 = Acc(0);
+    if (act) {
+      const int k1 = rp[r + 1];
+      int e = rp[r] + gl;
+      for (; e + 3 * G < k1; e += 4 * G) {
+        const V v0 = val[e], v1 = val[e + G], v2 = val[e + 2 * G], v3 = val[e + 3 * G];
+        const int c0 = ci[e], c1 = ci[e + G], c2 = ci[e + 2 * G], c3 = ci[e + 3 * G];
+        s0 += Acc(v0) * Acc(x[c0]);
+        s1 += Acc(v1) * Acc(x[c1]);
+        s2 += Acc(v2) * Acc(x[c2]);
+        s3 += Acc(v3) * Acc(x[c3]);
+      }
+      for (; e < k1; e += G) s0 += Acc(val[e]) * Acc(x[ci[e]]);
+    }
+    Acc s = (s0 + s1) + (s2 + s3);
+    for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (act && gl == 0) epi(r, s, pf);
   }
-  __syncthreads();  // the previous tile of this block may still be reading lds
-#pragma unroll
-  for (int it = 0; it < TN / kBlock; ++it) {
-    const int e = it * kBlock + tid;
-    if (e < nt) lds[e] = Acc(val[k0 + e]) * Acc(x[ci[k0 + e]]);
-  }
-  __syncthreads();
-  const int R = r1 - r0;
-  int G = kWave;
-  while (G > 1 && G * R > kBlock) G >>= 1;
-  const int row = tid / G, lane = tid & (G - 1);
-  Acc s = Acc(0);
-  if (row < R) {
-    const int rs = rp[r0 + row] - k0, re = rp[r0 + row + 1] - k0;
-    for (int e = rs + lane; e < re; e += G) s += lds[e];
-  }
-  for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-  if (row < R && lane == 0) epi(r0 + row, s);
 }
 
-// y = A x on a tile schedule (plain store epilogue).
-template <typename V, typename X, typename Acc, typename Y, int TN>
+// The chunks [c_lo, c_hi) of a block, shared out over its waves (wave w takes c_lo + w, + 4, ...).
+template <typename V, typename X, typename Acc, typename Pre, typename Epi>
+__device__ __forceinline__ void block_chunks(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                             const V *__restrict__ val, const X *__restrict__ x,
+                                             const int32_t *__restrict__ chunk_row,
+                                             const int8_t *__restrict__ chunk_cls, int c_lo, int c_hi, Pre &&pre,
+                                             Epi &&epi) {
+  for (int ch = c_lo + ((int)threadIdx.x >> 6); ch < c_hi; ch += kWaves)
+    chunk_rows<V, X, Acc>(rp, ci, val, x, chunk_row[ch], chunk_row[ch + 1], chunk_cls[ch], pre, epi);
+}
+
+// y = A x over the chunks [0, nchunks) (plain store epilogue); one block per kWaves chunks.
+template <typename V, typename X, typename Acc, typename Y>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const V *__restrict__ val, const int32_t *__restrict__ tiles,
-                                                 int ntiles, const X *__restrict__ x, Y *__restrict__ y) {
-  __shared__ Acc lds[TN];
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  if (tile >= ntiles) return;
-  tile_spmv<V, X, Acc, TN>(rp, ci, val, x, tiles[tile], tiles[tile + 1], lds,
-                           [&](int i, Acc s) { y[i] = Y(s); });
+                                                 const V *__restrict__ val, const int32_t *__restrict__ chunk_row,
+                                                 const int8_t *__restrict__ chunk_cls, int nchunks,
+                                                 const X *__restrict__ x, Y *__restrict__ y) {
+  const int c_lo = (int)blockIdx.x * kWaves;
+  block_chunks<V, X, Acc>(rp, ci, val, x, chunk_row, chunk_cls, c_lo, min(nchunks, c_lo + kWaves),
+                          [&](int) { return NoPre{}; }, [&](int i, Acc s, NoPre) { y[i] = Y(s); });
 }
 
 // Sum of per-block partials [b0, b1) x [NV] in a fixed order; valid in thread 0.
@@ -217,9 +231,8 @@ __device__ __forceinline__ void share(int base, int count, int lb, int nb, int *
 //   per-block partial sums of |dy|^2 and dy'(ax' - ax).
 // Grid: the A-side work blocks of all instances; each owns a contiguous run of tiles.
 // ----------------------------------------------------------------------------------------------
-template <typename T, int TN>
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
-  __shared__ T lds[TN];
   const WBlock w = work_block(P.L.ab0, P.L.ab_inst);
   const State *st = P.st + w.inst;
   if (st->done | st->stop) return;
@@ -233,20 +246,22 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   const T *__restrict__ b = P.b;
   const uint8_t *__restrict__ sense = P.sense;
   double acc[2] = {0.0, 0.0};
-  int tb, te;
-  share(P.L.a_tile0[w.inst], P.L.a_tile0[w.inst + 1] - P.L.a_tile0[w.inst], w.lb, w.nb, &tb, &te);
-  for (int tile = tb; tile < te; ++tile) {
-    tile_spmv<T, T, T, TN>(P.a_rp, P.a_ci, P.a_val, xn, P.a_tiles[tile], P.a_tiles[tile + 1], lds,
-                           [&](int i, T s) {
-                             const T yi = yc[i], axi = axc[i];
-                             const T ynew = proj_dual(yi + sigma * (b[i] - T(2) * s + axi), sense[i]);
-                             yn[i] = ynew;
-                             axn[i] = s;
-                             const double dy = double(ynew) - double(yi);
-                             acc[0] += dy * dy;
-                             acc[1] += dy * (double(s) - double(axi));
-                           });
-  }
+  struct DualPre {
+    T y, ax, b;
+    uint8_t s;
+  };
+  int cb, ce;
+  share(P.L.a_chunk0[w.inst], P.L.a_chunk0[w.inst + 1] - P.L.a_chunk0[w.inst], w.lb, w.nb, &cb, &ce);
+  block_chunks<T, T, T>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, cb, ce,
+                        [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; },
+                        [&](int i, T s, const DualPre &q) {
+                          const T ynew = proj_dual(q.y + sigma * (q.b - T(2) * s + q.ax), q.s);
+                          yn[i] = ynew;
+                          axn[i] = s;
+                          const double dy = double(ynew) - double(q.y);
+                          acc[0] += dy * dy;
+                          acc[1] += dy * (double(s) - double(q.ax));
+                        });
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
     P.p_dual[2 * blockIdx.x] = acc[0];
@@ -321,9 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_step(Layout L, const double *__restr
 // candidate of the next attempt x' = proj_[l,u](x - tau (c - A'y)), tau = eta / omega, and its
 // |x' - x|^2 partial sum. Grid: the A'-side work blocks of all instances.
 // ----------------------------------------------------------------------------------------------
-template <typename T, int TN>
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
-  __shared__ T lds[TN];
   const WBlock w = work_block(P.L.tb0, P.L.tb_inst);
   const State *st = P.st + w.inst;
   if (st->done) return;
@@ -340,28 +354,30 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   T *__restrict__ xbar = P.xbar;
   T *__restrict__ atybar = P.atybar;
   double acc[1] = {0.0};
-  auto primal = [&](int j, T atyj) {
-    const T xj = xc[j];
+  struct PrimalPre {
+    T x, c, l, u, xbar, atybar;
+  };
+  auto fetch = [&](int j) { return PrimalPre{xc[j], c[j], lo[j], hi[j], xbar[j], atybar[j]}; };
+  auto primal = [&](int j, T atyj, const PrimalPre &q) {
     if (commit) {
-      xbar[j] += wa * (xj - xbar[j]);
-      atybar[j] += wa * (atyj - atybar[j]);
+      xbar[j] = q.xbar + wa * (q.x - q.xbar);
+      atybar[j] = q.atybar + wa * (atyj - q.atybar);
     }
     if (!stop) {
-      const T xnew = clipv(xj - tau * (c[j] - atyj), lo[j], hi[j]);
+      const T xnew = clipv(q.x - tau * (q.c - atyj), q.l, q.u);
       xnx[j] = xnew;
-      const double d = double(xnew) - double(xj);
+      const double d = double(xnew) - double(q.x);
       acc[0] += d * d;
     }
   };
-  int tb, te;
-  share(P.L.t_tile0[w.inst], P.L.t_tile0[w.inst + 1] - P.L.t_tile0[w.inst], w.lb, w.nb, &tb, &te);
+  int cb, ce;
+  share(P.L.t_chunk0[w.inst], P.L.t_chunk0[w.inst + 1] - P.L.t_chunk0[w.inst], w.lb, w.nb, &cb, &ce);
   if (commit) {
-    for (int tile = tb; tile < te; ++tile)
-      tile_spmv<T, T, T, TN>(P.t_rp, P.t_ci, P.t_val, yc, P.t_tiles[tile], P.t_tiles[tile + 1], lds,
-                             [&](int j, T s) {
-                               aty[j] = s;
-                               primal(j, s);
-                             });
+    block_chunks<T, T, T>(P.t_rp, P.t_ci, P.t_val, yc, P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
+                          [&](int j, T s, const PrimalPre &q) {
+                            aty[j] = s;
+                            primal(j, s, q);
+                          });
     const T *__restrict__ axc = P.ax[cur];
     T *__restrict__ ybar = P.ybar;
     T *__restrict__ axbar = P.axbar;
@@ -371,9 +387,9 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
       ybar[i] += wa * (yc[i] - ybar[i]);
       axbar[i] += wa * (axc[i] - axbar[i]);
     }
-  } else if (!stop && te > tb) {
-    const int j0 = P.t_tiles[tb], j1 = P.t_tiles[te];
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += kBlock) primal(j, aty[j]);
+  } else if (!stop && ce > cb) {
+    const int j0 = P.t_chunk_row[cb], j1 = P.t_chunk_row[ce];
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += kBlock) primal(j, aty[j], fetch(j));
   }
   block_sum<1>(acc);
   if (threadIdx.x == 0) P.p_primal[blockIdx.x] = acc[0];
@@ -942,6 +958,12 @@ __global__ __launch_bounds__(kBlock) void k_scale_vectors(int m, int n, const do
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_convert(int64_t n, const double *__restrict__ s, T *__restrict__ d) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) d[i] = T(s[i]);
+}
+
+// dst[i] = src[idx[i]] (boundary mapping between external and internal numbering)
+__global__ __launch_bounds__(kBlock) void k_gather64(int n, const double *__restrict__ src, const int32_t *__restrict__ idx,
+                                                     double *__restrict__ dst) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) dst[i] = src[idx[i]];
 }
 
 // Original-space product helper: xs = x / D (scaled input, rounded to T) and y = ys / D.

@@ -33,7 +33,7 @@ class Options(C.Structure):
                 ("pock_chambolle", C.c_int32), ("use_graphs", C.c_int32), ("device_ptrs", C.c_int32),
                 ("tile_nnz", C.c_int32), ("verbose", C.c_int32), ("device_mem_limit", C.c_int64),
                 ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("kernel_timing", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("work_blocks", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class Result(C.Structure):
@@ -57,7 +57,7 @@ class ProblemDesc(C.Structure):
 
 
 EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_spmv",
-           "pdlp_get_scaling", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
+           "pdlp_get_scaling", "pdlp_get_internal", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
            "pdlp_batch_get", "pdlp_batch_destroy"]
 
@@ -88,8 +88,10 @@ def load(path: str = LIB_PATH):
     lib.pdlp_get.restype = C.c_int
     lib.pdlp_spmv.argtypes = [vp, i32, vp, vp]
     lib.pdlp_spmv.restype = C.c_int
-    lib.pdlp_get_scaling.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.pdlp_get_scaling.argtypes = [vp, vp, vp, vp]
     lib.pdlp_get_scaling.restype = C.c_int
+    lib.pdlp_get_internal.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pdlp_get_internal.restype = C.c_int
     lib.pdlp_get_schedule.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.pdlp_get_schedule.restype = C.c_int
     lib.pdlp_kernel_stats.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(dp)]
@@ -131,7 +133,7 @@ def _ptr(a):
 
 def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
             device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
-            warm_fallback=True, kernel_timing=False) -> Options:
+            warm_fallback=True, kernel_timing=False, work_blocks=0) -> Options:
     o = Options()
     load().pdlp_options_default(C.byref(o))
     o.precision = FP64 if str(precision).lower() in ("fp64", "f64", "double", "1") else FP32
@@ -145,6 +147,7 @@ def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True,
     o.device_mem_limit = device_mem_limit
     o.warm_fallback = 1 if warm_fallback else 0
     o.kernel_timing = 1 if kernel_timing else 0
+    o.work_blocks = work_blocks
     if stream is None:
         try:
             import torch
@@ -230,9 +233,17 @@ class Problem:
 
     def scaling(self):
         Dr, Dc, sv = np.zeros(self.m), np.zeros(self.n), np.zeros(self.nnz)
-        trp, tci, tv = np.zeros(self.n + 1, np.int32), np.zeros(self.nnz, np.int32), np.zeros(self.nnz)
-        _check(load().pdlp_get_scaling(self.h, _ptr(Dr), _ptr(Dc), _ptr(sv), _ptr(trp), _ptr(tci), _ptr(tv)))
-        return dict(Dr=Dr, Dc=Dc, scaled_val=sv, t_row_ptr=trp, t_col=tci, t_val=tv)
+        _check(load().pdlp_get_scaling(self.h, _ptr(Dr), _ptr(Dc), _ptr(sv)))
+        return dict(Dr=Dr, Dc=Dc, scaled_val=sv)
+
+    def internal(self):
+        m, n, z = self.m, self.n, self.nnz
+        out = dict(row_ptr=np.zeros(m + 1, np.int32), col=np.zeros(z, np.int32), val=np.zeros(z),
+                   t_row_ptr=np.zeros(n + 1, np.int32), t_col=np.zeros(z, np.int32), t_val=np.zeros(z),
+                   row_perm=np.zeros(m, np.int32), col_perm=np.zeros(n, np.int32))
+        _check(load().pdlp_get_internal(self.h, *[_ptr(out[k]) for k in ("row_ptr", "col", "val", "t_row_ptr",
+                                                                          "t_col", "t_val", "row_perm", "col_perm")]))
+        return out
 
     def schedule(self) -> dict:
         tn, ta, tt = C.c_int32(), C.c_int32(), C.c_int32()
