@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 cold-solve comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=160, help="oracle attempts in the CPU sample")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a kernel of known size for scaling "
+                         "hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -96,6 +99,13 @@ def main():
     from paper_2503_10344_amd import pdlp
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib * 2**18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
     t = time.time()
     lp, desc = make_workload(args.workload, args.seed)
     log(f"workload generated in {time.time() - t:.1f} s: m={lp.m} n={lp.n} nnz={lp.nnz}")

@@ -74,7 +74,7 @@ typedef struct pdlp_options {
                               on the handle's stream (graphs are not used then); read the totals with
                               pdlp_kernel_stats (default 0) */
   int32_t work_blocks;     /* blocks per SpMV kernel across all instances (each owns a contiguous run
-                              of tiles); 0 = 2048 (default 0) */
+                              of chunks); 0 = 8192 (default 0) */
   int32_t reserved[5];
 } pdlp_options;
 

@@ -192,7 +192,7 @@ struct Solver {
   int32_t *d_ab0 = nullptr, *d_ab_inst = nullptr, *d_tb0 = nullptr, *d_tb_inst = nullptr;
   int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
   int ab_blocks = 1, tb_blocks = 1, ev_blocks = 1;
-  int work_blocks = 2048;  // target number of work blocks per side for the whole handle
+  int work_blocks = 8192;  // target number of work blocks per side for the whole handle
   // matrix
   int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr, *perm = nullptr;
   int32_t *a_chunk_row = nullptr, *t_chunk_row = nullptr;
@@ -640,7 +640,7 @@ struct Solver {
     hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
   }
   void launch_step() {
-    hipLaunchKernelGGL(k_step, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_dual,
+    hipLaunchKernelGGL(k_step, dim3(K), dim3(kStepBlock), 0, stream, P.L, (const double *)p_dual,
                        (const double *)p_primal, (const double *)p_restart, st, ndone);
   }
   void launch_eval(int mode) {

@@ -145,16 +145,23 @@ __device__ __forceinline__ void chunk_rows(const int32_t *__restrict__ rp, const
     Acc s0 = Acc(0), s1 = Acc(0), s2 = Acc(0), s3 = Acc(0);
     if (act) {
       const int k1 = rp[r + 1];
-      int e = rp[r] + gl;
-      for (; e + 3 * G < k1; e += 4 * G) {
-        const V v0 = val[e], v1 = val[e + G], v2 = val[e + 2 * G], v3 = val[e + 3 * G];
-        const int c0 = ci[e], c1 = ci[e + G], c2 = ci[e + 2 * G], c3 = ci[e + 3 * G];
-        s0 += Acc(v0) * Acc(x[c0]);
-        s1 += Acc(v1) * Acc(x[c1]);
-        s2 += Acc(v2) * Acc(x[c2]);
-        s3 += Acc(v3) * Acc(x[c3]);
+      // classes 0..5 give every lane at most four elements: one round of predicated loads, all
+      // issued before the first use; class 6 loops. val/col are streamed once per product and
+      // bypass the caches (non-temporal) so that x stays resident for the gathers.
+      for (int e = rp[r] + gl; e < k1; e += 4 * G) {
+        // branch-free: out-of-row slots re-read the row's last element and are masked out
+        const bool p1 = e + G < k1, p2 = e + 2 * G < k1, p3 = e + 3 * G < k1;
+        const int e1 = p1 ? e + G : k1 - 1, e2 = p2 ? e + 2 * G : k1 - 1, e3 = p3 ? e + 3 * G : k1 - 1;
+        const int c0 = __builtin_nontemporal_load(ci + e), c1 = __builtin_nontemporal_load(ci + e1);
+        const int c2 = __builtin_nontemporal_load(ci + e2), c3 = __builtin_nontemporal_load(ci + e3);
+        const V v0 = __builtin_nontemporal_load(val + e), v1 = __builtin_nontemporal_load(val + e1);
+        const V v2 = __builtin_nontemporal_load(val + e2), v3 = __builtin_nontemporal_load(val + e3);
+        const X x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+        s0 += Acc(v0) * Acc(x0);
+        s1 += p1 ? Acc(v1) * Acc(x1) : Acc(0);
+        s2 += p2 ? Acc(v2) * Acc(x2) : Acc(0);
+        s3 += p3 ? Acc(v3) * Acc(x3) : Acc(0);
       }
-      for (; e < k1; e += G) s0 += Acc(val[e]) * Acc(x[ci[e]]);
     }
     Acc s = (s0 + s1) + (s2 + s3);
     for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
@@ -302,10 +309,35 @@ __device__ inline void step_size_rule(State *st, int32_t *ndone, double dx2, dou
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_step(Layout L, const double *__restrict__ p_dual,
-                                                 const double *__restrict__ p_primal,
-                                                 const double *__restrict__ p_restart, State *sts,
-                                                 int32_t *ndone) {
+// Sum over [lo, hi) of p[stride * q + off] by a kStepBlock-thread block; four independent
+// accumulators per thread keep several loads in flight. Result valid in thread 0.
+constexpr int kStepBlock = 1024;
+__device__ __forceinline__ double step_sum(const double *__restrict__ p, int stride, int off, int lo, int hi) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int q = lo + (int)threadIdx.x;
+  for (; q + 3 * kStepBlock < hi; q += 4 * kStepBlock) {
+    a0 += p[(size_t)stride * q + off];
+    a1 += p[(size_t)stride * (q + kStepBlock) + off];
+    a2 += p[(size_t)stride * (q + 2 * kStepBlock) + off];
+    a3 += p[(size_t)stride * (q + 3 * kStepBlock) + off];
+  }
+  for (; q < hi; q += kStepBlock) a0 += p[(size_t)stride * q + off];
+  double v = wave_sum((a0 + a1) + (a2 + a3));
+  __shared__ double red[kStepBlock / kWave];
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = red[0];
+    for (int w = 1; w < kStepBlock / kWave; ++w) v += red[w];
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__restrict__ p_dual,
+                                                     const double *__restrict__ p_primal,
+                                                     const double *__restrict__ p_restart, State *sts,
+                                                     int32_t *ndone) {
   const int inst = blockIdx.x;
   State *st = sts + inst;
   if (st->done) return;
@@ -313,20 +345,14 @@ __global__ __launch_bounds__(kBlock) void k_step(Layout L, const double *__restr
     if (threadIdx.x == 0) mark_done(st, ndone);
     return;
   }
-  double a[3] = {0.0, 0.0, 0.0};
-  for (int q = L.ab0[inst] + (int)threadIdx.x; q < L.ab0[inst + 1]; q += kBlock) {
-    a[0] += p_dual[2 * q];
-    a[1] += p_dual[2 * q + 1];
-  }
-  if (st->restart_mode != kNoRestart) {
-    for (int q = L.ev_blk0[inst] + (int)threadIdx.x; q < L.ev_blk0[inst + 1]; q += kBlock) a[2] += p_restart[q];
-  } else {
-    for (int q = L.tb0[inst] + (int)threadIdx.x; q < L.tb0[inst + 1]; q += kBlock) a[2] += p_primal[q];
-  }
-  block_sum<3>(a);
+  const double dy2 = step_sum(p_dual, 2, 0, L.ab0[inst], L.ab0[inst + 1]);
+  const double inter = step_sum(p_dual, 2, 1, L.ab0[inst], L.ab0[inst + 1]);
+  const double dx2 = st->restart_mode != kNoRestart
+                         ? step_sum(p_restart, 1, 0, L.ev_blk0[inst], L.ev_blk0[inst + 1])
+                         : step_sum(p_primal, 1, 0, L.tb0[inst], L.tb0[inst + 1]);
   if (threadIdx.x == 0) {
     st->restart_mode = kNoRestart;
-    step_size_rule(st, ndone, a[2], a[0], a[1]);
+    step_size_rule(st, ndone, dx2, dy2, inter);
   }
 }
 
