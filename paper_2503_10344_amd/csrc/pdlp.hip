@@ -80,9 +80,12 @@ struct Arena {
         return;
       }
   }
-  ~Arena() {
+  void reset() {
     for (auto &b : blocks) (void)hipFree(b.first);
+    blocks.clear();
+    used = 0;
   }
+  ~Arena() { reset(); }
 };
 
 // ----------------------------------------------------------------------------------------------
@@ -1245,3 +1248,5 @@ int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_
 void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }
 
 }  // extern "C"
+
+#include "gnn_host.h"

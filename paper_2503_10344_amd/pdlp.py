@@ -112,6 +112,31 @@ def load(path: str = LIB_PATH):
     lib.pdlp_batch_get.restype = C.c_int
     lib.pdlp_batch_destroy.argtypes = [vp]
     lib.pdlp_batch_destroy.restype = None
+    lib.pdlp_batch_get_scaling.argtypes = [vp, vp, vp, vp]
+    lib.pdlp_batch_get_scaling.restype = C.c_int
+    lib.pdlp_batch_get_internal.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pdlp_batch_get_internal.restype = C.c_int
+    # learned warm start
+    lib.pdlp_gnn_num_params.argtypes = []
+    lib.pdlp_gnn_num_params.restype = i64
+    lib.pdlp_gnn_create.argtypes = [C.POINTER(vp), C.c_uint64]
+    lib.pdlp_gnn_create.restype = C.c_int
+    lib.pdlp_gnn_get_params.argtypes = [vp, vp]
+    lib.pdlp_gnn_get_params.restype = C.c_int
+    lib.pdlp_gnn_set_params.argtypes = [vp, vp]
+    lib.pdlp_gnn_set_params.restype = C.c_int
+    lib.pdlp_gnn_predict.argtypes = [vp, vp, vp, vp, vp]
+    lib.pdlp_gnn_predict.restype = C.c_int
+    lib.pdlp_gnn_predict_batch.argtypes = [vp, vp, vp, vp, vp]
+    lib.pdlp_gnn_predict_batch.restype = C.c_int
+    lib.pdlp_gnn_predict_raw.argtypes = [vp, vp, vp, vp, vp]
+    lib.pdlp_gnn_predict_raw.restype = C.c_int
+    lib.pdlp_gnn_gradients.argtypes = [vp, vp, vp, vp, vp, C.POINTER(dp), vp]
+    lib.pdlp_gnn_gradients.restype = C.c_int
+    lib.pdlp_gnn_train_step.argtypes = [vp, vp, vp, vp, vp, C.c_float, C.POINTER(dp)]
+    lib.pdlp_gnn_train_step.restype = C.c_int
+    lib.pdlp_gnn_destroy.argtypes = [vp]
+    lib.pdlp_gnn_destroy.restype = None
     _lib = lib
     return lib
 
@@ -349,6 +374,33 @@ class Batch:
         r = pdlp_batch_get(self.h, i, x, y, rc)
         return Solution(x, y, rc, r.as_dict())
 
+    @property
+    def m(self):
+        return sum(d[0] for d in self.dims)
+
+    @property
+    def n(self):
+        return sum(d[1] for d in self.dims)
+
+    @property
+    def nnz(self):
+        return sum(int(a["row_ptr"][-1]) for a in self.arrs)
+
+    def scaling(self):
+        """Dr [sum m], Dc [sum n] and the scaled values, over the concatenated instances."""
+        Dr, Dc, sv = np.zeros(self.m), np.zeros(self.n), np.zeros(self.nnz)
+        _check(load().pdlp_batch_get_scaling(self.h, _ptr(Dr), _ptr(Dc), _ptr(sv)))
+        return dict(Dr=Dr, Dc=Dc, scaled_val=sv)
+
+    def internal(self):
+        m, n, z = self.m, self.n, self.nnz
+        out = dict(row_ptr=np.zeros(m + 1, np.int32), col=np.zeros(z, np.int32), val=np.zeros(z),
+                   t_row_ptr=np.zeros(n + 1, np.int32), t_col=np.zeros(z, np.int32), t_val=np.zeros(z),
+                   row_perm=np.zeros(m, np.int32), col_perm=np.zeros(n, np.int32))
+        _check(load().pdlp_batch_get_internal(self.h, *[_ptr(out[k]) for k in (
+            "row_ptr", "col", "val", "t_row_ptr", "t_col", "t_val", "row_perm", "col_perm")]))
+        return out
+
     def close(self):
         if getattr(self, "h", None):
             pdlp_batch_destroy(self.h)
@@ -365,3 +417,81 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class WarmStartNet:
+    """The learned warm start (a 3-round bipartite message-passing network, width 64).
+
+    predict(handle) returns (x0, y0, omega0) in the original space for a Problem or a Batch (batch
+    vectors concatenated in instance order); train_step / gradients take a Batch and its targets.
+    All arithmetic runs in the HIP library.
+    """
+
+    def __init__(self, seed=0, params=None):
+        lib = load()
+        self.num_params = int(lib.pdlp_gnn_num_params())
+        h = C.c_void_p()
+        _check(lib.pdlp_gnn_create(C.byref(h), C.c_uint64(seed)))
+        self.h = h
+        if params is not None:
+            self.set_params(params)
+
+    def params(self) -> np.ndarray:
+        p = np.zeros(self.num_params, np.float32)
+        _check(load().pdlp_gnn_get_params(self.h, _ptr(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        if p.size != self.num_params:
+            raise ValueError(f"expected {self.num_params} parameters, got {p.size}")
+        _check(load().pdlp_gnn_set_params(self.h, _ptr(p)))
+
+    def predict(self, handle):
+        lib = load()
+        if isinstance(handle, Batch):
+            x0, y0, om = np.zeros(handle.n), np.zeros(handle.m), np.zeros(len(handle))
+            _check(lib.pdlp_gnn_predict_batch(self.h, handle.h, _ptr(x0), _ptr(y0), _ptr(om)))
+            return x0, y0, om
+        x0, y0, om = np.zeros(handle.n), np.zeros(handle.m), np.zeros(1)
+        _check(lib.pdlp_gnn_predict(self.h, handle.h, _ptr(x0), _ptr(y0), _ptr(om)))
+        return x0, y0, float(om[0])
+
+    def predict_raw(self, batch):
+        xh, yh, lw = np.zeros(batch.n, np.float32), np.zeros(batch.m, np.float32), np.zeros(len(batch), np.float32)
+        _check(load().pdlp_gnn_predict_raw(self.h, batch.h, _ptr(xh), _ptr(yh), _ptr(lw)))
+        return xh, yh, lw
+
+    @staticmethod
+    def _targets(batch, x_star, y_star, omega_star):
+        xs = np.ascontiguousarray(x_star, np.float64)
+        ys = np.ascontiguousarray(y_star, np.float64)
+        om = np.ascontiguousarray(omega_star, np.float64)
+        if xs.size != batch.n or ys.size != batch.m or om.size != len(batch):
+            raise ValueError("target sizes do not match the batch")
+        return xs, ys, om
+
+    def gradients(self, batch, x_star, y_star, omega_star):
+        xs, ys, om = self._targets(batch, x_star, y_star, omega_star)
+        g = np.zeros(self.num_params, np.float32)
+        loss = C.c_double()
+        _check(load().pdlp_gnn_gradients(self.h, batch.h, _ptr(xs), _ptr(ys), _ptr(om), C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train_step(self, batch, x_star, y_star, omega_star, lr=1e-3) -> float:
+        xs, ys, om = self._targets(batch, x_star, y_star, omega_star)
+        loss = C.c_double()
+        _check(load().pdlp_gnn_train_step(self.h, batch.h, _ptr(xs), _ptr(ys), _ptr(om), C.c_float(lr),
+                                          C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pdlp_gnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

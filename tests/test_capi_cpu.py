@@ -9,6 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pdlp.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pdlp.h", "pdlp_gnn.h")]
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +22,7 @@ def lib():
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "\n".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*(pdlp_[a-z_0-9]+)\s*\(", src, flags=re.M)
     return sorted(set(names))
@@ -30,7 +31,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_destroy", "pdlp_batch_create",
-                 "pdlp_batch_solve", "pdlp_batch_get"):
+                 "pdlp_batch_solve", "pdlp_batch_get", "pdlp_gnn_create", "pdlp_gnn_predict",
+                 "pdlp_gnn_train_step"):
         assert must in names
 
 
@@ -130,3 +132,21 @@ def test_null_arguments(lib):
     assert lib.pdlp_solve(None, 1e-4, 10, None, None, 0.0) == -1
     assert lib.pdlp_get(None, None, None, None, None) == -1
     assert lib.pdlp_error_string(-2) == b"malformed CSR matrix"
+
+
+def test_gnn_header_compiles_as_c_and_parameter_count(lib, tmp_path):
+    """pdlp_gnn.h is plain C, and the library's parameter count is the oracle's."""
+    import subprocess
+    from oracle import gnn_oracle
+    prog = tmp_path / "g.c"
+    prog.write_text('#include "pdlp_gnn.h"\nint main(void){return pdlp_gnn_num_params == 0;}\n')
+    subprocess.run(["gcc", "-c", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(tmp_path / "g.o")],
+                   check=True)
+    assert lib.pdlp_gnn_num_params() == gnn_oracle.num_params() == 50947
+
+
+def test_gnn_rejects_null_arguments(lib):
+    assert lib.pdlp_gnn_create(None, 0) == -1
+    assert lib.pdlp_gnn_predict(None, None, None, None, None) == -1
+    assert lib.pdlp_gnn_train_step(None, None, None, None, None, C.c_float(1e-3), None) == -1
+    assert lib.pdlp_batch_get_internal(None, *([None] * 8)) == -1

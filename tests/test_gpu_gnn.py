@@ -1,0 +1,184 @@
+"""The learned warm start on the GPU against its FP64 oracle (BF16 operand rounding emulated).
+
+Inputs: a batch of three seeded LPs of different families and sizes (a set-cover relaxation, an
+energy-shaped LP whose 1,350 columns span two pooling chunks, a dense tiny LP), so every dense
+kernel sees several 16-row tiles and ragged tails. The oracle is fed the scaled problem exactly as
+the handle holds it (values rounded to FP32) and the FP32 parameters.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import gnn_oracle as go  # noqa: E402
+from paper_2503_10344_amd import generators as gen  # noqa: E402
+from paper_2503_10344_amd import pdlp  # noqa: E402
+
+REL_OUT = 1e-4      # relative 2-norm error of outputs and loss
+COS_MIN = 0.9999    # cosine of gradient blocks
+REL_GRAD = 1e-4     # relative 2-norm error of each gradient block
+
+
+def _lps():
+    return [gen.set_cover(3, m=150, n=400, k=5), gen.energy(5, T=24, N=5, K=6, E=10), gen.tiny_lp(7, m=9, n=13)]
+
+
+def oracle_graph(batch, lps):
+    it = batch.internal()
+    sc = batch.scaling()
+    pr, pc = it["row_perm"], it["col_perm"]
+    c = np.concatenate([lp.c for lp in lps])
+    b = np.concatenate([lp.b for lp in lps])
+    l = np.concatenate([lp.l for lp in lps])
+    u = np.concatenate([lp.u for lp in lps])
+    sense = np.concatenate([lp.sense for lp in lps])
+    Dr, Dc = sc["Dr"][pr], sc["Dc"][pc]
+    row0 = np.concatenate([[0], np.cumsum([lp.m for lp in lps])])
+    col0 = np.concatenate([[0], np.cumsum([lp.n for lp in lps])])
+    G = go.Graph(it["row_ptr"], it["col"], it["val"], Dc * c[pc], Dr * b[pr], l[pc] / Dc, u[pc] / Dc,
+                 sense[pr], row0, col0)
+    return G, pr, pc, Dr, Dc
+
+
+def _params(seed):
+    p = go.init_params(seed) + np.random.default_rng(seed + 100).normal(size=go.num_params()) * 0.02
+    return p.astype(np.float32)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    lps = _lps()
+    batch = pdlp.Batch(lps, precision="fp32")
+    G, pr, pc, Dr, Dc = oracle_graph(batch, lps)
+    return lps, batch, G, pr, pc, Dr, Dc
+
+
+def test_forward_matches_oracle(setup):
+    lps, batch, G, *_ = setup
+    net = pdlp.WarmStartNet(seed=0)
+    p = _params(1)
+    net.set_params(p)
+    xh, yh, lw = net.predict_raw(batch)
+    ox, oy, olw, _ = go.forward(p.astype(np.float64), G, emulate_bf16=True)
+    print("forward rel err x %.2e y %.2e logw %.2e" % (_rel(xh, ox), _rel(yh, oy), _rel(lw, olw)))
+    assert _rel(xh, ox) <= REL_OUT and _rel(yh, oy) <= REL_OUT and _rel(lw, olw) <= REL_OUT
+    # the BF16 emulation matters: the exact network is farther away than the tolerance
+    ex, _, _, _ = go.forward(p.astype(np.float64), G, emulate_bf16=False)
+    assert _rel(xh, ex) > 10 * _rel(xh, ox)
+
+
+def test_predict_maps_to_original_space(setup):
+    lps, batch, G, pr, pc, Dr, Dc = setup
+    net = pdlp.WarmStartNet(seed=3)
+    xh, yh, lw = net.predict_raw(batch)
+    x0, y0, om = net.predict(batch)
+    np.testing.assert_allclose(x0[pc], Dc * xh.astype(np.float64), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(y0[pr], Dr * yh.astype(np.float64), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(om, np.exp(np.clip(lw.astype(np.float64), -20, 20)), rtol=1e-15)
+
+
+def test_batch_prediction_equals_single_problems(setup):
+    lps, batch, *_ = setup
+    net = pdlp.WarmStartNet(seed=4)
+    x0, y0, om = net.predict(batch)
+    co, ro = 0, 0
+    for q, lp in enumerate(lps):
+        with pdlp.Problem(lp, precision="fp32") as p:
+            xs, ys, o = net.predict(p)
+        np.testing.assert_array_equal(xs, x0[co:co + lp.n])
+        np.testing.assert_array_equal(ys, y0[ro:ro + lp.m])
+        assert o == om[q]
+        co += lp.n
+        ro += lp.m
+
+
+def test_fp64_handle_gives_the_same_prediction(setup):
+    lps, batch, *_ = setup
+    net = pdlp.WarmStartNet(seed=5)
+    with pdlp.Problem(lps[1], precision="fp32") as p32, pdlp.Problem(lps[1], precision="fp64") as p64:
+        a = net.predict(p32)
+        b = net.predict(p64)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def _targets(lps, seed):
+    rng = np.random.default_rng(seed)
+    xs = np.concatenate([rng.uniform(0, 2, lp.n) for lp in lps])
+    ys = np.concatenate([rng.normal(size=lp.m) for lp in lps])
+    om = rng.uniform(0.1, 10, len(lps))
+    return xs, ys, om
+
+
+def test_gradients_match_oracle(setup):
+    lps, batch, G, pr, pc, Dr, Dc = setup
+    net = pdlp.WarmStartNet(seed=0)
+    p = _params(2)
+    net.set_params(p)
+    xs, ys, om = _targets(lps, 3)
+    loss, g = net.gradients(batch, xs, ys, om)
+    # targets as the device forms them: scaled, internal numbering, rounded to FP32
+    txs = (xs[pc] / Dc).astype(np.float32).astype(np.float64)
+    tys = (ys[pr] / Dr).astype(np.float32).astype(np.float64)
+    tlw = np.log(om).astype(np.float32).astype(np.float64)
+    oL, og = go.loss_and_grad(p.astype(np.float64), G, txs, tys, tlw, emulate_bf16=True)
+    print("loss gpu %.10g oracle %.10g" % (loss, oL))
+    assert abs(loss - oL) <= REL_OUT * abs(oL)
+    o = 0
+    worst = []
+    for name, sh in go.param_shapes():
+        k = int(np.prod(sh))
+        a, b = g[o:o + k].astype(np.float64), og[o:o + k]
+        o += k
+        if np.linalg.norm(b) == 0:
+            assert np.linalg.norm(a) == 0, name
+            continue
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        worst.append((_rel(a, b), cos, name))
+        assert cos >= COS_MIN, (name, cos)
+        assert _rel(a, b) <= REL_GRAD, (name, _rel(a, b))
+    worst.sort(reverse=True)
+    print("worst gradient blocks:", worst[:4])
+
+
+def test_adam_step_and_determinism(setup):
+    lps, batch, *_ = setup
+    xs, ys, om = _targets(lps, 4)
+    nets = [pdlp.WarmStartNet(seed=9) for _ in range(2)]
+    p0 = nets[0].params()
+    _, g = nets[0].gradients(batch, xs, ys, om)
+    lr = 1e-3
+    nets[0].train_step(batch, xs, ys, om, lr=lr)
+    p1 = nets[0].params()
+    # first Adam step with bias correction: p - lr * g / (|g| + eps)
+    g64 = g.astype(np.float64)
+    expect = p0 - lr * g64 / (np.abs(g64) + 1e-8)
+    np.testing.assert_allclose(p1, expect, rtol=0, atol=2e-6)
+    # training is bitwise reproducible
+    losses = [[], []]
+    for t in range(2):
+        if t == 1:
+            nets[1].train_step(batch, xs, ys, om, lr=lr)
+        for _ in range(5):
+            losses[t].append(nets[t].train_step(batch, xs, ys, om, lr=lr))
+    np.testing.assert_array_equal(nets[0].params(), nets[1].params())
+    assert losses[0] == losses[1]
+
+
+def test_training_reduces_the_loss(setup):
+    lps, batch, *_ = setup
+    xs, ys, om = _targets(lps, 5)
+    net = pdlp.WarmStartNet(seed=11)
+    first = net.train_step(batch, xs, ys, om, lr=3e-3)
+    for _ in range(60):
+        last = net.train_step(batch, xs, ys, om, lr=3e-3)
+    print("loss %.4g -> %.4g" % (first, last))
+    assert last < 0.5 * first
