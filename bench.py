@@ -23,6 +23,21 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
+# HBM bytes per k_dual launch measured by rocprofv3 (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
+# factors of a 256 MiB device copy), keyed by workload and by the SHA-1 of the sources the kernel and
+# its launch configuration are built from; any change to them makes the figure stale (reported null).
+KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
+MEASURED_TRAFFIC = {}  # {(workload, sha1): bytes per launch}
+
+
+def kernel_source_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_10344_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -75,13 +90,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf", "setcover", "energy"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "setcover", "energy", "batch"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--iter-limit", type=int, default=500_000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 cold-solve comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=160, help="oracle attempts in the CPU sample")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start comparison")
+    ap.add_argument("--warm-instances", type=int, default=16)
+    ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known size for scaling "
                          "hardware byte counters)")
@@ -99,6 +117,8 @@ def main():
     from paper_2503_10344_amd import pdlp
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args)
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -147,8 +167,9 @@ def main():
         kern[name] = dict(launches=launches, avg_us=avg_ms * 1e3, alg_bytes=bytes_,
                           gbs=bytes_ / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None)
     dom = kern["dual"]
+    traffic = MEASURED_TRAFFIC.get((args.workload, kernel_source_sha1()))
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": "k_dual (A x' + dual update + step-size reductions)",
                 "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": round(dom["avg_us"], 2)}
     log(f"kernels: {json.dumps(kern)}")
@@ -196,6 +217,11 @@ def main():
                           f"host CPU: {cpu_model()}")}
         log(f"cpu baseline: {json.dumps(cpu)}")
 
+    # ---------------- learned warm start vs cold FP32 (held-out energy-shaped LPs) ----------------
+    warm = None
+    if not args.no_warm_start:
+        warm = warm_start_comparison(args.warm_instances, args.tol)
+
     out = {
         "metric": "time to 1e-4 rel. KKT + SpMV HBM GB/s; FP32/warm-start vs FP64 cold PDLP",
         "value": round(sec, 4),
@@ -223,8 +249,80 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "fp64_cold": fp64,
+        "warm_start": warm,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def warm_start_comparison(count, tol):
+    """Cold FP32 vs the committed trained warm start (inference included) on held-out seeds."""
+    from paper_2503_10344_amd import generators as g
+    from paper_2503_10344_amd import pdlp, warmstart
+    net, mode = warmstart.load_trained()
+    rows = []
+    for s in range(warmstart.TEST_SEEDS[0], warmstart.TEST_SEEDS[0] + count):
+        lp = g.warmstart_family(s)
+        with pdlp.Problem(lp) as p:
+            p.solve(tol=tol)   # warm-up of this handle's graphs
+            cold = p.solve(tol=tol)
+            w = warmstart.warm_solve(net, p, tol=tol, mode=mode)
+        rows.append((cold["iterations"], cold["solve_seconds"], w["iterations"], w["seconds"], w["fallback"],
+                     w["predict_seconds"]))
+    med = lambda k: statistics.median(r[k] for r in rows)  # noqa: E731
+    res = {"instances": f"energy-shaped LPs, m 10k-100k, held-out seeds {warmstart.TEST_SEEDS[0]}.."
+                        f"{warmstart.TEST_SEEDS[0] + count - 1}", "mode": mode,
+           "cold_median_s": round(med(1), 4), "warm_median_s": round(med(3), 4),
+           "cold_median_iterations": med(0), "warm_median_iterations": med(2),
+           "median_predict_ms": round(1e3 * med(5), 3),
+           "fallback_rate": round(sum(r[4] for r in rows) / len(rows), 3),
+           "warm_faster_fraction": round(sum(r[3] < r[1] for r in rows) / len(rows), 3)}
+    log(f"warm start: {json.dumps(res)}")
+    return res
+
+
+def bench_batch(args):
+    """Many uneven LPs in one handle: makespan of the batched solve vs the same LPs one by one."""
+    import torch
+    from paper_2503_10344_amd import generators as g
+    from paper_2503_10344_amd import pdlp
+    t = time.time()
+    lps = g.batch(args.seed, count=args.batch_count)
+    nnz = sum(lp.nnz for lp in lps)
+    log(f"{len(lps)} instances generated in {time.time() - t:.1f} s: sum m={sum(lp.m for lp in lps)} "
+        f"sum n={sum(lp.n for lp in lps)} nnz={nnz}")
+    t = time.time()
+    b = pdlp.Batch(lps, precision="fp32")
+    torch.cuda.synchronize()
+    create_s = time.time() - t
+    for w in range(args.warmup):
+        b.solve(tol=args.tol, iter_limit=args.iter_limit)
+    times, infos = [], None
+    for s in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = b.solve(tol=args.tol, iter_limit=args.iter_limit)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"step {s}: makespan {times[-1]:.3f} s, max iterations {max(i['iterations'] for i in infos)}")
+    b.close()
+    seq, seq_it = 0.0, []
+    for lp in lps:
+        with pdlp.Problem(lp, precision="fp32") as p:
+            p.solve(tol=args.tol, iter_limit=args.iter_limit)
+            i = p.solve(tol=args.tol, iter_limit=args.iter_limit)
+            seq += i["solve_seconds"]
+            seq_it.append(i["iterations"])
+    sec = statistics.median(times)
+    it = [i["iterations"] for i in infos]
+    out = {"metric": "makespan to 1e-4 rel. KKT of a batch of LPs (FP32 PDLP)", "value": round(sec, 4), "unit": "s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 2),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(lps)} LPs (even: set cover, odd: multi-knapsack), m ~ U[1000, 50000], "
+                                  f"n = 2.5 m, nnz={nnz}, batch seed {args.seed}", "tol": args.tol},
+           "optimal": sum(i["status_name"] == "optimal" for i in infos), "iterations_max": max(it),
+           "iterations_median": statistics.median(it), "sequential_s": round(seq, 3),
+           "speedup_vs_sequential": round(seq / sec, 2), "create_s": round(create_s, 2)}
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,66 @@
+"""Warm-started PDLP on the GPU: the fallback rule and the gain of the committed trained network.
+
+The network was trained by `python -m paper_2503_10344_amd.warmstart` on 2,000 solver-generated
+solutions of the energy-shaped family (seeds 0-1,999); the instances here are held-out seeds from
+1,000,000 on, which no training or model-selection step saw.
+"""
+import statistics
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_2503_10344_amd import generators as gen  # noqa: E402
+from paper_2503_10344_amd import pdlp, warmstart  # noqa: E402
+
+TOL = 1e-4
+
+
+def test_bad_prediction_falls_back_to_the_cold_start():
+    lp = gen.warmstart_family(1_000_500, m_lo=2_000, m_hi=6_000)
+    net = pdlp.WarmStartNet(seed=1)
+    p = net.params()
+    from oracle import gnn_oracle as go
+    off = {}
+    o = 0
+    for name, sh in go.param_shapes():
+        off[name] = o
+        o += int(np.prod(sh))
+    p[off["bx"]] = 1e4   # every predicted x is far outside the boxes of the demand rows' columns
+    p[off["by"]] = -1e4
+    net.set_params(p)
+    with pdlp.Problem(lp) as prob:
+        cold = prob.solve(tol=TOL)
+        w = warmstart.warm_solve(net, prob, tol=TOL, mode="primal_dual")
+    assert w["fallback"]
+    assert w["iterations"] == cold["iterations"]
+    assert w["primal_obj"] == cold["primal_obj"]
+
+
+def test_trained_network_reduces_iterations_on_held_out_instances():
+    net, mode = warmstart.load_trained()
+    cold_it, warm_it = [], []
+    for s in range(1_000_000, 1_000_016):
+        lp = gen.warmstart_family(s)
+        with pdlp.Problem(lp) as prob:
+            cold = prob.solve(tol=TOL)
+            w = warmstart.warm_solve(net, prob, tol=TOL, mode=mode)
+            sol = prob.get()
+        assert w["status"] == "optimal" and cold["status_name"] == "optimal"
+        # the returned point reaches the tolerance when the FP64 oracle re-evaluates it
+        assert oracle.kkt(lp, sol.x, sol.y)["rel_kkt"] <= TOL * 1.0001
+        cold_it.append(cold["iterations"])
+        warm_it.append(w["iterations"])
+        print(f"seed {s}: m={lp.m} cold {cold['iterations']} warm {w['iterations']} ({mode})", flush=True)
+    ratio = np.array(warm_it, float) / np.array(cold_it, float)
+    geo = float(np.exp(np.log(ratio).mean()))
+    print("median cold", statistics.median(cold_it), "median warm", statistics.median(warm_it),
+          "geometric-mean ratio %.3f, total ratio %.3f" % (geo, sum(warm_it) / sum(cold_it)))
+    assert geo < 1.0
+    assert sum(warm_it) < sum(cold_it)
