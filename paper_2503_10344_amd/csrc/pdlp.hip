@@ -194,6 +194,7 @@ struct Solver {
   int32_t *d_row0 = nullptr, *d_col0 = nullptr, *d_nnz0 = nullptr, *d_a_chunk0 = nullptr, *d_t_chunk0 = nullptr;
   int32_t *d_ab0 = nullptr, *d_ab_inst = nullptr, *d_tb0 = nullptr, *d_tb_inst = nullptr;
   int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
+  int32_t *d_a_bchunk = nullptr, *d_t_bchunk = nullptr;  // first chunk of each work block
   int ab_blocks = 1, tb_blocks = 1, ev_blocks = 1;
   int work_blocks = 8192;  // target number of work blocks per side for the whole handle
   // matrix
@@ -508,6 +509,7 @@ struct Solver {
     L.K = K;
     L.row0 = d_row0, L.col0 = d_col0, L.a_chunk0 = d_a_chunk0, L.t_chunk0 = d_t_chunk0;
     L.ab0 = d_ab0, L.ab_inst = d_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
+    L.a_bchunk = d_a_bchunk, L.t_bchunk = d_t_bchunk;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
     L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ab_blocks, L.tb_blocks = tb_blocks;
     L.ev_blocks = ev_blocks;
@@ -537,32 +539,52 @@ struct Solver {
     }
     for (void *p : {(void *)a_chunk_row, (void *)t_chunk_row, (void *)a_chunk_cls, (void *)t_chunk_cls,
                     (void *)d_a_chunk0, (void *)d_t_chunk0, (void *)d_ab0, (void *)d_ab_inst, (void *)d_tb0,
-                    (void *)d_tb_inst})
+                    (void *)d_tb_inst, (void *)d_a_bchunk, (void *)d_t_bchunk})
       if (p) mem.release(p);
     a_chunk_row = alloc_upload(ra), t_chunk_row = alloc_upload(rt);
     a_chunk_cls = alloc_upload(ca), t_chunk_cls = alloc_upload(ct);
     d_a_chunk0 = alloc_upload(h_a_chunk0), d_t_chunk0 = alloc_upload(h_t_chunk0);
     a_nchunks = (int)ca.size(), t_nchunks = (int)ct.size();
     chunk_nnz = cap;
-    // work blocks: about work_blocks per side in total, shared out by chunk count, >= 1 per instance
-    std::vector<int32_t> ab_inst, tb_inst;
-    auto blocks_for = [&](const std::vector<int32_t> &ch0, std::vector<int32_t> &b0, std::vector<int32_t> &binst) {
-      const int64_t total = ch0.back();
+    // Work blocks: about work_blocks per side for the whole handle, shared out over the instances by
+    // weight (nonzeros + rows: every row has an epilogue), at least one per instance and at most one
+    // per chunk. Inside an instance each block takes a contiguous run of chunks of about equal
+    // weight; a chunk heavier than a block's share (one very long row) gets a block of its own.
+    std::vector<int32_t> ab_inst, tb_inst, a_bchunk, t_bchunk;
+    auto blocks_for = [&](const std::vector<int32_t> &rp, const std::vector<int32_t> &crow,
+                          const std::vector<int32_t> &ch0, std::vector<int32_t> &b0, std::vector<int32_t> &binst,
+                          std::vector<int32_t> &bchunk) {
+      const int nch = ch0.back();
+      std::vector<int64_t> wpre((size_t)nch + 1, 0);  // prefix of chunk weights (global)
+      for (int c = 0; c < nch; ++c)
+        wpre[c + 1] = wpre[c] + (rp[crow[c + 1]] - rp[crow[c]]) + (crow[c + 1] - crow[c]);
+      const int64_t total = std::max<int64_t>(wpre[nch], 1);
       b0.assign(1, 0);
       binst.clear();
+      bchunk.clear();
       for (int q = 0; q < K; ++q) {
-        const int64_t nc = ch0[q + 1] - ch0[q];
-        int64_t nbq = (nc * work_blocks + total - 1) / std::max<int64_t>(total, 1);
-        nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, (nc + kWaves - 1) / kWaves));
-        for (int64_t r = 0; r < nbq; ++r) binst.push_back(q);
+        const int c0 = ch0[q], c1 = ch0[q + 1];
+        const int64_t wq = wpre[c1] - wpre[c0];
+        int64_t nbq = (wq * work_blocks + total - 1) / total;
+        nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, std::max(c1 - c0, 1)));
+        int c = c0;
+        for (int64_t lb = 0; lb < nbq; ++lb) {
+          // first chunk whose start lies at or past this block's share of the weight
+          const int64_t target = wpre[c0] + (wq * lb + nbq - 1) / nbq;
+          while (c < c1 && wpre[c] < target) ++c;
+          bchunk.push_back(c);
+          binst.push_back(q);
+        }
         b0.push_back(b0.back() + (int32_t)nbq);
       }
+      bchunk.push_back(nch);
     };
-    blocks_for(h_a_chunk0, h_ab0, ab_inst);
-    blocks_for(h_t_chunk0, h_tb0, tb_inst);
+    blocks_for(h_arp, ra, h_a_chunk0, h_ab0, ab_inst, a_bchunk);
+    blocks_for(h_trp, rt, h_t_chunk0, h_tb0, tb_inst, t_bchunk);
     ab_blocks = h_ab0.back(), tb_blocks = h_tb0.back();
     d_ab0 = alloc_upload(h_ab0), d_ab_inst = alloc_upload(ab_inst);
     d_tb0 = alloc_upload(h_tb0), d_tb_inst = alloc_upload(tb_inst);
+    d_a_bchunk = alloc_upload(a_bchunk), d_t_bchunk = alloc_upload(t_bchunk);
   }
 
   template <typename V, typename X, typename Acc, typename Y>
@@ -574,9 +596,11 @@ struct Solver {
     else v = (const V *)(trans ? t_v : a_v);
     const int nch = trans ? t_nchunks : a_nchunks;
     if (nch <= 0) return;
-    hipLaunchKernelGGL((k_spmv<V, X, Acc, Y>), dim3((nch + kWaves - 1) / kWaves), dim3(kBlock), 0, stream, rp, ci, v,
-                       (const int32_t *)(trans ? t_chunk_row : a_chunk_row),
-                       (const int8_t *)(trans ? t_chunk_cls : a_chunk_cls), nch, x, y);
+    hipLaunchKernelGGL((k_spmv<V, X, Acc, Y>), dim3(trans ? tb_blocks : ab_blocks), dim3(kBlock), 0, stream, rp, ci,
+                       v, (const int32_t *)(trans ? t_chunk_row : a_chunk_row),
+                       (const int8_t *)(trans ? t_chunk_cls : a_chunk_cls), (const int32_t *)(trans ? d_tb0 : d_ab0),
+                       (const int32_t *)(trans ? d_tb_inst : d_ab_inst),
+                       (const int32_t *)(trans ? d_t_bchunk : d_a_bchunk), x, y);
   }
   void spmv_T(int trans, const T *x, T *y) { spmv_chunks<T, T, T, T>(trans, x, y); }
 

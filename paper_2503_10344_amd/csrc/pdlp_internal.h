@@ -59,6 +59,7 @@ struct Layout {
   const int32_t *a_chunk0, *t_chunk0; // [K+1] chunk ranges of A and A'
   const int32_t *ab0, *ab_inst;     // [K+1], [ab_blocks] A-side work blocks (k_dual)
   const int32_t *tb0, *tb_inst;     // [K+1], [tb_blocks] A'-side work blocks (k_primal)
+  const int32_t *a_bchunk, *t_bchunk; // [blocks+1] first chunk of each work block (nnz-balanced)
   const int32_t *ev_blk0, *ev_inst; // [K+1], [ev_blocks] evaluation blocks
   int32_t a_nchunks, t_nchunks, ab_blocks, tb_blocks, ev_blocks;
 };

@@ -124,10 +124,27 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 // lanes of a wave read one contiguous stretch of val/col even for the shortest rows), each lane
 // sums its strided share with four independent accumulators (four loads and gathers in flight per
 // lane), a G-lane shuffle tree finishes the row, and the group's first lane runs the row's
-// epilogue epi(row, sum, prefetched operands). No LDS and no block barrier is involved.
+// epilogue epi(row, sum, prefetched operands).
+// A chunk that is one row of at least kCoopNnz nonzeros is summed by the whole block (all four
+// waves, LDS across waves) instead of one wave, so a few very long rows (the shared capacity
+// columns of the energy models, the heavy tail of power-law rows) do not serialise on one wave.
 // The summation order of a row depends only on its length, so results are deterministic.
 // ----------------------------------------------------------------------------------------------
 struct NoPre {};
+
+// The two accumulation forms of the engine, spelled out so that every path that sums a row rounds
+// identically: the first accumulator of a lane takes a fused multiply-add; the masked ones take a
+// rounded product, a select against zero and a rounded add.
+template <typename Acc>
+__device__ __forceinline__ Acc acc_fma(Acc s, Acc v, Acc x) {
+  return fma(v, x, s);
+}
+template <typename Acc>
+__device__ __forceinline__ Acc acc_masked(Acc s, bool p, Acc v, Acc x) {
+#pragma clang fp contract(off)
+  const Acc prod = v * x;
+  return s + (p ? prod : Acc(0));
+}
 
 template <typename V, typename X, typename Acc, typename Pre, typename Epi>
 __device__ __forceinline__ void chunk_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -157,10 +174,10 @@ __device__ __forceinline__ void chunk_rows(const int32_t *__restrict__ rp, const
         const V v0 = __builtin_nontemporal_load(val + e), v1 = __builtin_nontemporal_load(val + e1);
         const V v2 = __builtin_nontemporal_load(val + e2), v3 = __builtin_nontemporal_load(val + e3);
         const X x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-        s0 += Acc(v0) * Acc(x0);
-        s1 += p1 ? Acc(v1) * Acc(x1) : Acc(0);
-        s2 += p2 ? Acc(v2) * Acc(x2) : Acc(0);
-        s3 += p3 ? Acc(v3) * Acc(x3) : Acc(0);
+        s0 = acc_fma(s0, Acc(v0), Acc(x0));
+        s1 = acc_masked(s1, p1, Acc(v1), Acc(x1));
+        s2 = acc_masked(s2, p2, Acc(v2), Acc(x2));
+        s3 = acc_masked(s3, p3, Acc(v3), Acc(x3));
       }
     }
     Acc s = (s0 + s1) + (s2 + s3);
@@ -169,26 +186,78 @@ __device__ __forceinline__ void chunk_rows(const int32_t *__restrict__ rp, const
   }
 }
 
-// The chunks [c_lo, c_hi) of a block, shared out over its waves (wave w takes c_lo + w, + 4, ...).
+constexpr int kCoopNnz = 1024;
+static_assert(kBlock == 4 * kWave, "coop_row maps the four accumulators of a lane onto four waves");
+
+// Row r summed by all kBlock threads of the block with exactly the arithmetic of one wave of 64
+// lanes (class 6): wave w computes the lanes' accumulator w (elements rp[r] + lane + 64 w + 256 i),
+// the four accumulators meet in LDS, and wave 0 finishes with the same shuffle tree. The row sum is
+// therefore bitwise the one chunk_rows gives; only the work is spread over four waves. Every thread
+// of the block must call this (it contains block barriers); thread 0 runs the epilogue.
+template <typename V, typename X, typename Acc, typename Pre, typename Epi>
+__device__ __forceinline__ void coop_row(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                         const V *__restrict__ val, const X *__restrict__ x, int r, Acc *red,
+                                         Pre &&pre, Epi &&epi) {
+  const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  using PF = decltype(pre(r));
+  const PF pf = tid == 0 ? pre(r) : PF{};
+  const int k1 = rp[r + 1];
+  Acc s = Acc(0);
+  if (w == 0) {
+    for (int e = rp[r] + lane; e < k1; e += 4 * kWave) {
+      const int c0 = __builtin_nontemporal_load(ci + e);
+      const V v0 = __builtin_nontemporal_load(val + e);
+      s = acc_fma(s, Acc(v0), Acc(x[c0]));
+    }
+  } else {
+    for (int e = rp[r] + lane; e < k1; e += 4 * kWave) {
+      const bool p = e + w * kWave < k1;
+      const int ew = p ? e + w * kWave : k1 - 1;
+      const int c = __builtin_nontemporal_load(ci + ew);
+      const V v = __builtin_nontemporal_load(val + ew);
+      s = acc_masked(s, p, Acc(v), Acc(x[c]));
+    }
+  }
+  red[tid] = s;
+  __syncthreads();
+  if (w == 0) {
+    Acc t = (red[lane] + red[kWave + lane]) + (red[2 * kWave + lane] + red[3 * kWave + lane]);
+    for (int off = kWave >> 1; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
+    if (lane == 0) epi(r, t, pf);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool long_chunk(const int32_t *__restrict__ rp, const int32_t *__restrict__ chunk_row,
+                                           const int8_t *__restrict__ chunk_cls, int c) {
+  if (chunk_cls[c] != 6) return false;
+  const int r = chunk_row[c];
+  return chunk_row[c + 1] == r + 1 && rp[r + 1] - rp[r] >= kCoopNnz;
+}
+
+// The chunks [c_lo, c_hi) of a block: runs of ordinary chunks are shared out over the waves (wave w
+// takes the run's chunks w, w + 4, ...); a long single-row chunk is summed by the whole block. The
+// range is the same for every thread of the block, so all of them meet the same barriers.
 template <typename V, typename X, typename Acc, typename Pre, typename Epi>
 __device__ __forceinline__ void block_chunks(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                              const V *__restrict__ val, const X *__restrict__ x,
                                              const int32_t *__restrict__ chunk_row,
                                              const int8_t *__restrict__ chunk_cls, int c_lo, int c_hi, Pre &&pre,
                                              Epi &&epi) {
-  for (int ch = c_lo + ((int)threadIdx.x >> 6); ch < c_hi; ch += kWaves)
-    chunk_rows<V, X, Acc>(rp, ci, val, x, chunk_row[ch], chunk_row[ch + 1], chunk_cls[ch], pre, epi);
-}
-
-// y = A x over the chunks [0, nchunks) (plain store epilogue); one block per kWaves chunks.
-template <typename V, typename X, typename Acc, typename Y>
-__global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const V *__restrict__ val, const int32_t *__restrict__ chunk_row,
-                                                 const int8_t *__restrict__ chunk_cls, int nchunks,
-                                                 const X *__restrict__ x, Y *__restrict__ y) {
-  const int c_lo = (int)blockIdx.x * kWaves;
-  block_chunks<V, X, Acc>(rp, ci, val, x, chunk_row, chunk_cls, c_lo, min(nchunks, c_lo + kWaves),
-                          [&](int) { return NoPre{}; }, [&](int i, Acc s, NoPre) { y[i] = Y(s); });
+  __shared__ Acc red[kBlock];
+  const int wave = (int)threadIdx.x >> 6;
+  int ch = c_lo;
+  while (ch < c_hi) {
+    int stop = ch;
+    while (stop < c_hi && !long_chunk(rp, chunk_row, chunk_cls, stop)) ++stop;
+    for (int c = ch + wave; c < stop; c += kWaves)
+      chunk_rows<V, X, Acc>(rp, ci, val, x, chunk_row[c], chunk_row[c + 1], chunk_cls[c], pre, epi);
+    if (stop < c_hi) {
+      coop_row<V, X, Acc>(rp, ci, val, x, chunk_row[stop], red, pre, epi);
+      ++stop;
+    }
+    ch = stop;
+  }
 }
 
 // Sum of per-block partials [b0, b1) x [NV] in a fixed order; valid in thread 0.
@@ -223,6 +292,20 @@ __device__ __forceinline__ WBlock work_block(const int32_t *__restrict__ b0, con
   w.lb = xcd_remap((int)blockIdx.x - s, w.nb);
   return w;
 }
+// y = A x over every instance's chunks (plain store epilogue); grid: the work blocks of the side.
+template <typename V, typename X, typename Acc, typename Y>
+__global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                 const V *__restrict__ val, const int32_t *__restrict__ chunk_row,
+                                                 const int8_t *__restrict__ chunk_cls, const int32_t *__restrict__ b0,
+                                                 const int32_t *__restrict__ binst,
+                                                 const int32_t *__restrict__ bchunk, const X *__restrict__ x,
+                                                 Y *__restrict__ y) {
+  const WBlock w = work_block(b0, binst);
+  const int gb = b0[w.inst] + w.lb;
+  block_chunks<V, X, Acc>(rp, ci, val, x, chunk_row, chunk_cls, bchunk[gb], bchunk[gb + 1],
+                          [&](int) { return NoPre{}; }, [&](int i, Acc s, NoPre) { y[i] = Y(s); });
+}
+
 // Balanced contiguous share [*lo, *hi) of `count` items for block lb of nb.
 __device__ __forceinline__ void share(int base, int count, int lb, int nb, int *lo, int *hi) {
   *lo = base + (int)(((int64_t)lb * count) / nb);
@@ -258,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
     uint8_t s;
   };
   int cb, ce;
-  share(P.L.a_chunk0[w.inst], P.L.a_chunk0[w.inst + 1] - P.L.a_chunk0[w.inst], w.lb, w.nb, &cb, &ce);
+  cb = P.L.a_bchunk[P.L.ab0[w.inst] + w.lb], ce = P.L.a_bchunk[P.L.ab0[w.inst] + w.lb + 1];
   block_chunks<T, T, T>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, cb, ce,
                         [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; },
                         [&](int i, T s, const DualPre &q) {
@@ -397,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
     }
   };
   int cb, ce;
-  share(P.L.t_chunk0[w.inst], P.L.t_chunk0[w.inst + 1] - P.L.t_chunk0[w.inst], w.lb, w.nb, &cb, &ce);
+  cb = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb], ce = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb + 1];
   if (commit) {
     block_chunks<T, T, T>(P.t_rp, P.t_ci, P.t_val, yc, P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
                           [&](int j, T s, const PrimalPre &q) {

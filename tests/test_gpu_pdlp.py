@@ -118,6 +118,32 @@ def test_spmv_edge_shapes(pdlp):
         assert np.all(ax[::7] == 0.0) and np.all(aty[-50:] == 0.0)
 
 
+def test_long_rows_block_path_is_bitwise_the_wave_path(pdlp):
+    """Rows of >= 1024 nonzeros alone in a chunk are summed by a whole block; the sum must be
+    bitwise the one wave computes when the same row shares a chunk with others (larger chunks)."""
+    rng = np.random.default_rng(11)
+    m, n = 2000, 8000
+    rows, cols, vals = [], [], []
+    for i in range(m):
+        L = int(rng.choice([1100, 1300, 1500, 1800, 2900])) if i % 5 == 0 else int(rng.integers(1, 60))
+        cs = np.union1d(np.arange(10), rng.choice(np.arange(10, n), size=L, replace=False))  # 10 dense columns
+        rows += [i] * cs.size
+        cols += cs.tolist()
+        vals += rng.standard_normal(cs.size).tolist()
+    rp, ci, v = g._csr_from_triplets(m, n, rows, cols, vals)
+    lp = g.LP(m, n, rp, ci, v, np.zeros(n), np.zeros(m), np.full(m, ord("E"), np.uint8),
+              np.full(n, -np.inf), np.full(n, np.inf))
+    x = rng.standard_normal(n)
+    y = rng.standard_normal(m)
+    for prec in ("fp32", "fp64"):
+        out = {}
+        for cap in (512, 4096):
+            with pdlp.Problem(lp, precision=prec, tile_nnz=cap) as p:
+                out[cap] = (p.spmv(x), p.spmv(y, trans=True))
+        np.testing.assert_array_equal(out[512][0], out[4096][0])
+        np.testing.assert_array_equal(out[512][1], out[4096][1])
+
+
 def test_transpose_and_scaling(pdlp):
     lp = g.general_sparse(3, m=4000, n=9000, cap=2000)
     say("scaling", lp.m, lp.n, lp.nnz)
