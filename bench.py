@@ -27,7 +27,10 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # factors of a 256 MiB device copy), keyed by workload and by the SHA-1 of the sources the kernel and
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
-MEASURED_TRAFFIC = {}  # {(workload, sha1): bytes per launch}
+MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
+    ("zipf", "f63672e68aa3a4b6495289c4b985efd650ab5bb4"): 454_897_254,
+    ("energy", "f63672e68aa3a4b6495289c4b985efd650ab5bb4"): 466_952_090,
+}
 
 
 def kernel_source_sha1():
