@@ -171,6 +171,7 @@ static void class_order(const std::vector<int64_t> &len, int32_t lo, int32_t hi,
 }
 
 static const int kChunkCandidates[] = {512, 1024, 2048, 4096};
+constexpr int kMaxResumes = 6;  // FP64 re-checks that may send an instance back into the loop
 
 // Autotune cache: matrix signature -> chosen chunk size.
 static std::mutex g_tune_mu;
@@ -675,8 +676,19 @@ struct Solver {
     hipLaunchKernelGGL(k_eval_fin, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_eval, st, ndone, mode);
   }
   void launch_restart() { hipLaunchKernelGGL(k_restart<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P); }
+  // In FP32 the products of the averages, kept up to date by the same weighted updates as the
+  // averages themselves, drift from A x-bar and A'y-bar by accumulated rounding; they are
+  // recomputed before each evaluation so that the average's KKT error, and the caches a restart to
+  // the average hands on, are those of the averaged point itself. (FP64 keeps the updates.)
+  void refresh_averages() {
+    if constexpr (sizeof(T) == sizeof(float)) {
+      spmv_T(0, xbar, axbar);
+      spmv_T(1, ybar, atybar);
+    }
+  }
   void launch_chunk_body() {
     for (int r = 0; r < opt.eval_every; ++r) launch_attempt();
+    refresh_averages();
     launch_eval(kEvalChunk);
     launch_restart();
   }
@@ -697,6 +709,7 @@ struct Solver {
       hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
       HIPCHK(hipEventRecord(e[3], stream));
     }
+    refresh_averages();
     launch_eval(kEvalChunk);
     launch_restart();
     HIPCHK(hipGetLastError());
@@ -852,10 +865,11 @@ struct Solver {
         const double rk = std::max(s.rel_p, std::max(s.rel_d, s.rel_gap));
         if (checks[q] == 0 || s.status == PDLP_STATUS_OPTIMAL) checks[q] += (s.status != 0);
         if (s.status == PDLP_STATUS_OPTIMAL && tol > 0.0 && !(rk <= tol)) {
-          if (checks[q] < 4 && s.k < iter_limit) {
+          if (checks[q] <= kMaxResumes && s.k < iter_limit) {
             // the FP64 recomputation from the FP64 matrix disagrees with the in-loop evaluation:
-            // continue this instance from the same state with a tighter internal tolerance
-            tol_int[q] *= 0.5;
+            // continue this instance from the same state with the internal tolerance tightened by
+            // the observed miss (at least 20 %), so a point that just missed costs a short resume
+            tol_int[q] *= std::min(0.8, 0.95 * tol / rk);
             s.done = 0, s.status = 0, s.stop = 0, s.tol = tol_int[q];
             resume = true;
           } else {
