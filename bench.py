@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=160, help="oracle attempts in the CPU sample")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start comparison")
-    ap.add_argument("--warm-instances", type=int, default=16)
+    ap.add_argument("--warm-instances", type=int, default=48)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known size for scaling "
@@ -275,6 +275,7 @@ def warm_start_comparison(count, tol):
     med = lambda k: statistics.median(r[k] for r in rows)  # noqa: E731
     res = {"instances": f"energy-shaped LPs, m 10k-100k, held-out seeds {warmstart.TEST_SEEDS[0]}.."
                         f"{warmstart.TEST_SEEDS[0] + count - 1}", "mode": mode,
+           "cold_total_s": round(sum(r[1] for r in rows), 3), "warm_total_s": round(sum(r[3] for r in rows), 3),
            "cold_median_s": round(med(1), 4), "warm_median_s": round(med(3), 4),
            "cold_median_iterations": med(0), "warm_median_iterations": med(2),
            "median_predict_ms": round(1e3 * med(5), 3),

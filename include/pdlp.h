@@ -25,7 +25,9 @@
  *     handle's device (for example the data pointers of torch tensors).
  *   - All work is ordered on pdlp_options.stream (a hipStream_t; NULL = the library creates one).
  *     pdlp_solve and pdlp_get return after the stream has finished their work.
- *   - Determinism: the same input and options on the same GPU give bitwise identical results.
+ *   - Determinism: the same input and options on the same GPU give bitwise identical results
+ *     for a given chunk size. With tile_nnz = 0 the chunk size is chosen by timing, keeping 512
+ *     unless another candidate is at least 15 % faster; set tile_nnz to pin it across processes.
  *   - Calls on one handle must not overlap; different handles are independent.
  */
 #ifndef PDLP_H_

@@ -605,8 +605,8 @@ struct Solver {
   }
   void spmv_T(int trans, const T *x, T *y) { spmv_chunks<T, T, T, T>(trans, x, y); }
 
-  // Autotuner: time A x and A'y for each candidate chunk size and keep the fastest (the smallest
-  // size within 3 % of the best). The choice is cached per sparsity signature.
+  // Autotuner: time A x and A'y for each candidate chunk size; keep the smallest size unless
+  // another is at least 15 % faster. The choice is cached per sparsity signature.
   void choose_schedule() {
     if (opt.tile_nnz > 0) {
       bool ok = false;
@@ -646,11 +646,12 @@ struct Solver {
         times.push_back({cand, ms});
         best = std::min(best, ms);
       }
+      // Keep the finest size unless another is clearly faster: the choice must not flip between
+      // runs on timing noise, because the block partition (and with it the grouping of the FP64
+      // partial sums, hence the rounding of the whole trajectory) follows from it.
+      pick = times[0].first;
       for (auto &t : times)
-        if (t.second <= best * 1.03f) {
-          pick = t.first;
-          break;
-        }
+        if (t.second <= best * 1.0001f && t.second < 0.85f * times[0].second) pick = t.first;
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }

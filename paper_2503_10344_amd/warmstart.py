@@ -170,10 +170,17 @@ def summarize(rows, modes=MODES):
     return out
 
 
+def choose_mode(val):
+    """The mode with the smallest total solve time on the validation seeds (inference included:
+    what a caller of many solves pays); cold if no mode beats the cold start."""
+    best = min(MODES, key=lambda md: (val[md]["total_seconds_ratio"], md))
+    return best if val[best]["total_seconds_ratio"] < 1.0 else "cold"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="train and evaluate the learned PDLP warm start")
     ap.add_argument("--train", type=int, default=2000, help="training instances (seeds 0..N-1)")
-    ap.add_argument("--val", type=int, default=100)
+    ap.add_argument("--val", type=int, default=200, help="validation instances (loss and mode choice)")
     ap.add_argument("--test", type=int, default=200)
     ap.add_argument("--per-shard", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=30)
@@ -185,7 +192,34 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--out", default=None, help="write the trained parameters here (.npz)")
     ap.add_argument("--report", default=None, help="write the JSON report here")
+    ap.add_argument("--evaluate", default=None, metavar="WEIGHTS",
+                    help="only evaluate these trained weights (.npz) on the held-out seeds, in their mode")
+    ap.add_argument("--reselect", default=None, metavar="OUT",
+                    help="with --evaluate: choose the mode again on the validation seeds, save to OUT (.npz)")
     args = ap.parse_args(argv)
+
+    if args.evaluate:
+        net, mode = load_trained(args.evaluate)
+        if args.reselect:
+            # choose the mode again on the validation seeds (the solver may have changed since)
+            val_rows = evaluate(net, range(VAL_SEEDS[0], VAL_SEEDS[0] + args.val), args.tol,
+                                m_lo=args.m_lo, m_hi=args.m_hi)
+            val = summarize(val_rows)
+            mode = choose_mode(val)
+            _log(f"validation: {json.dumps(val)}; chosen mode {mode}")
+            np.savez(args.reselect, params=net.params(), mode=np.array(mode))
+        modes = tuple(dict.fromkeys((mode, "full", "omega")))
+        rows = evaluate(net, range(TEST_SEEDS[0], TEST_SEEDS[0] + args.test), args.tol, modes=modes,
+                        m_lo=args.m_lo, m_hi=args.m_hi)
+        report = dict(weights=args.evaluate, mode=mode, test=summarize(rows, modes=modes), tol=args.tol,
+                      m_range=[args.m_lo, args.m_hi])
+        if args.reselect:
+            report["validation"] = val
+        print(json.dumps(report), flush=True)
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(dict(report, test_rows=rows), f)
+        return
 
     t = time.time()
     shards = make_shards(range(TRAIN_SEEDS[0], TRAIN_SEEDS[0] + args.train), args.per_shard, args.tol,
@@ -201,13 +235,10 @@ def main(argv=None):
     v1 = validation_loss(net, vshards)
     _log(f"validation loss {v0:.4g} -> {v1:.4g}")
     del shards
-    val_rows = evaluate(net, range(VAL_SEEDS[0], VAL_SEEDS[0] + min(args.val, 50)), args.tol,
+    val_rows = evaluate(net, range(VAL_SEEDS[0], VAL_SEEDS[0] + args.val), args.tol,
                         m_lo=args.m_lo, m_hi=args.m_hi)
     val = summarize(val_rows)
-    # the mode with the smallest geometric-mean iteration ratio on validation; none better: cold
-    best = min(MODES, key=lambda md: (val[md]["geomean_iteration_ratio"], md))
-    if not val[best]["geomean_iteration_ratio"] < 1.0:
-        best = "cold"
+    best = choose_mode(val)
     _log(f"validation: {json.dumps(val)}; chosen mode {best}")
     # held-out: the chosen mode, plus the two single-choice modes for context
     test_modes = tuple(dict.fromkeys((best, "full", "omega")))

@@ -46,7 +46,9 @@ def test_bad_prediction_falls_back_to_the_cold_start():
 def test_trained_network_reduces_iterations_on_held_out_instances():
     net, mode = warmstart.load_trained()
     cold_it, warm_it = [], []
-    for s in range(1_000_000, 1_000_016):
+    # attempt counts are heavy-tailed, so the gain is asserted on an aggregate over 48 held-out
+    # instances (16 were too few for a stable aggregate)
+    for s in range(1_000_000, 1_000_048):
         lp = gen.warmstart_family(s)
         with pdlp.Problem(lp) as prob:
             cold = prob.solve(tol=TOL)
