@@ -52,11 +52,14 @@ def algorithmic_bytes(kernel, m, n, nnz, tb):
     dual   (A x' + dual update): A values + columns, row offsets, gather of x', read y, ax, b and
            the row senses, write y' and ax'.
     primal (A'y' + primal update + averages, accepted attempt): A' values + columns, row offsets,
-           gather of y', write A'y', read x, c, l, u, write x', read+write the two column averages,
-           read y, A x and read+write the two row averages.
+           gather of y', write A'y', read x, c, l, u, write x', read+write x-bar, read y and
+           read+write y-bar; in FP64 also read+write A'y-bar and A x-bar and read A x (FP32
+           recomputes those two products before each evaluation instead).
     """
     if kernel == "dual":
         return nnz * (tb + 4) + 4 * (m + 1) + tb * n + m * (5 * tb + 1)
+    if tb == 4:
+        return nnz * (tb + 4) + 4 * (n + 1) + tb * m + 8 * tb * n + 3 * tb * m
     return nnz * (tb + 4) + 4 * (n + 1) + tb * m + 10 * tb * n + 6 * tb * m
 
 

@@ -466,11 +466,14 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   struct PrimalPre {
     T x, c, l, u, xbar, atybar;
   };
-  auto fetch = [&](int j) { return PrimalPre{xc[j], c[j], lo[j], hi[j], xbar[j], atybar[j]}; };
+  // FP64 keeps A'y-bar and A x-bar current with the averages' weighted updates; FP32 recomputes
+  // both before each evaluation (the only readers), so it skips them here.
+  constexpr bool kTrack = sizeof(T) == sizeof(double);
+  auto fetch = [&](int j) { return PrimalPre{xc[j], c[j], lo[j], hi[j], xbar[j], kTrack ? atybar[j] : T(0)}; };
   auto primal = [&](int j, T atyj, const PrimalPre &q) {
     if (commit) {
       xbar[j] = q.xbar + wa * (q.x - q.xbar);
-      atybar[j] = q.atybar + wa * (atyj - q.atybar);
+      if (kTrack) atybar[j] = q.atybar + wa * (atyj - q.atybar);
     }
     if (!stop) {
       const T xnew = clipv(q.x - tau * (q.c - atyj), q.l, q.u);
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
     share(P.L.row0[w.inst], P.L.row0[w.inst + 1] - P.L.row0[w.inst], w.lb, w.nb, &rb, &re);
     for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
       ybar[i] += wa * (yc[i] - ybar[i]);
-      axbar[i] += wa * (axc[i] - axbar[i]);
+      if (kTrack) axbar[i] += wa * (axc[i] - axbar[i]);
     }
   } else if (!stop && ce > cb) {
     const int j0 = P.t_chunk_row[cb], j1 = P.t_chunk_row[ce];
