@@ -19,7 +19,7 @@
  *                  log omega = mean(hv) wov + mean(hc) woc + bo        (means over one instance)
  *   outputs        x0 = Dc x~, y0 = Dr y~ (original space), omega0 = exp(clamp(log omega, -20, 20))
  *   loss           mean over instances of mean_j (x~_j - x*_j/Dc_j)^2 + mean_i (y~_i - y*_i/Dr_i)^2
- *                  + (log omega - log omega*)^2
+ *                  + w_omega (log omega - log omega*)^2     (w_omega = 1 unless set)
  * Dense products run on the BF16 matrix cores with FP32 accumulation (both operands rounded to
  * BF16, nearest even); everything else is FP32. Training uses Adam (beta 0.9 / 0.999, eps 1e-8,
  * bias-corrected) on FP32 master weights.
@@ -60,6 +60,9 @@ int pdlp_gnn_get_params(pdlp_gnn *g, float *params);
 
 /* Replace the parameters (all finite, else PDLP_ERR_ARG) and reset the Adam state. */
 int pdlp_gnn_set_params(pdlp_gnn *g, const float *params);
+
+/* Weight w_omega >= 0 of the log-omega term of the loss (default 1); PDLP_ERR_ARG otherwise. */
+int pdlp_gnn_set_omega_weight(pdlp_gnn *g, float w);
 
 /* Predict a warm start for a single problem: x0 [n], y0 [m] in the original space and the
  * caller's numbering, omega0 [1]. Any output pointer may be NULL. Pass the results to pdlp_solve. */

@@ -17,7 +17,7 @@ initial LP relaxation, section 2). Its definition here:
   heads:      xhat = hv wx + bx ; yhat = hc wy + by ;
               log omega_q = mean_q(hv) wov + mean_q(hc) woc + bo     (per instance q)
   loss:       mean over instances of  mean_j (xhat - x*)^2 + mean_i (yhat - y*)^2
-                                       + (log omega - log omega*)^2
+                                       + w_omega (log omega - log omega*)^2     (w_omega >= 0)
 
 The GPU runs the dense layers on BF16 matrix cores with FP32 accumulation: both operands of every
 dense product (activations and weights, forward and backward) are rounded to BF16 (round to nearest
@@ -152,7 +152,7 @@ def forward(flat, G: Graph, emulate_bf16=True):
     return xhat, yhat, logw, cache
 
 
-def loss_and_grad(flat, G: Graph, xs, ys, logws, emulate_bf16=True):
+def loss_and_grad(flat, G: Graph, xs, ys, logws, emulate_bf16=True, omega_weight=1.0):
     """Loss and its gradient (flat, same layout as the parameters)."""
     P = unpack(flat)
     e = emulate_bf16
@@ -165,11 +165,12 @@ def loss_and_grad(flat, G: Graph, xs, ys, logws, emulate_bf16=True):
     for q in range(K):
         a, b_ = G.col0[q], G.col0[q + 1]
         c0, c1 = G.row0[q], G.row0[q + 1]
-        L += (np.mean(ex[a:b_] ** 2) if b_ > a else 0.0) + (np.mean(ey[c0:c1] ** 2) if c1 > c0 else 0.0) + ew[q] ** 2
+        L += ((np.mean(ex[a:b_] ** 2) if b_ > a else 0.0) + (np.mean(ey[c0:c1] ** 2) if c1 > c0 else 0.0)
+              + omega_weight * ew[q] ** 2)
     L /= K
     dxh = 2.0 * ex / np.maximum(nq[G.cinst], 1.0) / K
     dyh = 2.0 * ey / np.maximum(mq[G.rinst], 1.0) / K
-    dlw = 2.0 * ew / K
+    dlw = 2.0 * omega_weight * ew / K
     g = {name: np.zeros(sh) for name, sh in param_shapes()}
     hv, hc = C[f"hv{LAYERS}"], C[f"hc{LAYERS}"]
     g["wx"] = hv.T @ dxh

@@ -68,6 +68,7 @@ struct Model {
   Arena mem;  // parameters and optimiser state
   float *P = nullptr, *G = nullptr, *M1 = nullptr, *M2 = nullptr;
   int64_t step = 0;
+  float omega_weight = 1.f;  // weight of the log-omega term of the loss
   // per-graph workspace, regrown when a larger graph arrives
   Arena ws;
   int64_t cap_n = -1, cap_m = -1, cap_nnz = -1, cap_k = -1, cap_chv = -1, cap_chc = -1;
@@ -235,8 +236,8 @@ struct Model {
     hipLaunchKernelGGL(g_head_inst, dim3(g.K), dim3(64), 0, st, g.K, g.col0, g.row0, (const int32_t *)vch0,
                        (const int32_t *)cch0, (const float *)vpool, (const float *)cpool, (const double *)vsq,
                        (const double *)csq, (const float *)(P + kOffWov), (const float *)(P + kOffWoc),
-                       (const float *)(P + kOffBo), with_targets ? (const float *)tw : nullptr, pv, pc, logw, lossq,
-                       dlw);
+                       (const float *)(P + kOffBo), with_targets ? (const float *)tw : nullptr, omega_weight, pv, pc,
+                       logw, lossq, dlw);
     HIPCHK(hipGetLastError());
   }
 
@@ -394,6 +395,15 @@ int pdlp_gnn_set_params(pdlp_gnn *g, const float *params) {
     HIPCHK(hipDeviceSynchronize());
     g->model.set_params(params, nullptr);
   });
+}
+
+int pdlp_gnn_set_omega_weight(pdlp_gnn *g, float w) {
+  if (!g || !std::isfinite(w) || w < 0.f) {
+    pdlp::g_last_error = "bad argument to pdlp_gnn_set_omega_weight";
+    return PDLP_ERR_ARG;
+  }
+  g->model.omega_weight = w;
+  return PDLP_OK;
 }
 
 int pdlp_gnn_predict(pdlp_gnn *g, pdlp_problem *p, double *x0, double *y0, double *omega0) {

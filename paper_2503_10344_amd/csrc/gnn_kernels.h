@@ -443,7 +443,8 @@ __global__ __launch_bounds__(kGB) void g_head_fwd(const int32_t *__restrict__ cs
 }
 
 // Per instance q (one block of 64 threads): pooled means, log omega, loss terms and dL/dlog omega.
-//   pv, pc [K x 64]; logw [K]; if tw: lossq[q] = sqx/n_q + sqy/m_q + (logw - tw)^2, dlw = 2 (logw - tw)/K
+//   pv, pc [K x 64]; logw [K]; if tw: lossq[q] = sqx/n_q + sqy/m_q + w_om (logw - tw)^2,
+//   dlw = 2 w_om (logw - tw)/K
 __global__ __launch_bounds__(64) void g_head_inst(int32_t K, const int32_t *__restrict__ col0,
                                                   const int32_t *__restrict__ row0,
                                                   const int32_t *__restrict__ vch0, const int32_t *__restrict__ cch0,
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(64) void g_head_inst(int32_t K, const int32_t *__re
                                                   const double *__restrict__ vsq, const double *__restrict__ csq,
                                                   const float *__restrict__ wov, const float *__restrict__ woc,
                                                   const float *__restrict__ bo, const float *__restrict__ tw,
-                                                  float *__restrict__ pv, float *__restrict__ pc,
+                                                  float w_om, float *__restrict__ pv, float *__restrict__ pc,
                                                   float *__restrict__ logw, double *__restrict__ lossq,
                                                   float *__restrict__ dlw) {
   __shared__ float red[64];
@@ -476,8 +477,8 @@ __global__ __launch_bounds__(64) void g_head_inst(int32_t K, const int32_t *__re
       for (int32_t k = vch0[q]; k < vch0[q + 1]; ++k) sx += vsq[k];
       for (int32_t k = cch0[q]; k < cch0[q + 1]; ++k) sy += csq[k];
       const double d = (double)lw - (double)tw[q];
-      lossq[q] = (nq ? sx / nq : 0.0) + (mq ? sy / mq : 0.0) + d * d;
-      dlw[q] = (float)(2.0 * d / K);
+      lossq[q] = (nq ? sx / nq : 0.0) + (mq ? sy / mq : 0.0) + (double)w_om * d * d;
+      dlw[q] = (float)(2.0 * (double)w_om * d / K);
     }
   }
 }

@@ -135,6 +135,8 @@ def load(path: str = LIB_PATH):
     lib.pdlp_gnn_gradients.restype = C.c_int
     lib.pdlp_gnn_train_step.argtypes = [vp, vp, vp, vp, vp, C.c_float, C.POINTER(dp)]
     lib.pdlp_gnn_train_step.restype = C.c_int
+    lib.pdlp_gnn_set_omega_weight.argtypes = [vp, C.c_float]
+    lib.pdlp_gnn_set_omega_weight.restype = C.c_int
     lib.pdlp_gnn_destroy.argtypes = [vp]
     lib.pdlp_gnn_destroy.restype = None
     _lib = lib
@@ -427,7 +429,7 @@ class WarmStartNet:
     All arithmetic runs in the HIP library.
     """
 
-    def __init__(self, seed=0, params=None):
+    def __init__(self, seed=0, params=None, omega_weight=1.0):
         lib = load()
         self.num_params = int(lib.pdlp_gnn_num_params())
         h = C.c_void_p()
@@ -435,6 +437,12 @@ class WarmStartNet:
         self.h = h
         if params is not None:
             self.set_params(params)
+        if omega_weight != 1.0:
+            self.set_omega_weight(omega_weight)
+
+    def set_omega_weight(self, w):
+        """Weight of the log-omega term of the training loss (default 1)."""
+        _check(load().pdlp_gnn_set_omega_weight(self.h, C.c_float(w)))
 
     def params(self) -> np.ndarray:
         p = np.zeros(self.num_params, np.float32)

@@ -186,6 +186,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--schedule", default="constant", choices=["constant", "cosine"])
+    ap.add_argument("--omega-weight", type=float, default=10.0, help="weight of the log-omega loss term")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--m-lo", type=int, default=10_000)
     ap.add_argument("--m-hi", type=int, default=100_000)
@@ -227,7 +228,7 @@ def main(argv=None):
     gen_s = time.time() - t
     vshards = make_shards(range(VAL_SEEDS[0], VAL_SEEDS[0] + args.val), args.per_shard, args.tol,
                           m_lo=args.m_lo, m_hi=args.m_hi, log=None)
-    net = pdlp.WarmStartNet(seed=args.seed)
+    net = pdlp.WarmStartNet(seed=args.seed, omega_weight=args.omega_weight)
     v0 = validation_loss(net, vshards)
     t = time.time()
     hist = train(net, shards, args.epochs, args.lr, args.seed, args.schedule)
@@ -246,6 +247,7 @@ def main(argv=None):
                          m_lo=args.m_lo, m_hi=args.m_hi)
     test = summarize(test_rows, modes=test_modes)
     report = dict(train_instances=args.train, epochs=args.epochs, lr=args.lr, schedule=args.schedule,
+                  omega_weight=args.omega_weight,
                   data_seconds=round(gen_s, 1),
                   train_seconds=round(train_s, 1), loss_history=hist, val_loss_before=v0, val_loss_after=v1,
                   validation=val, mode=best, test=test, m_range=[args.m_lo, args.m_hi], tol=args.tol)

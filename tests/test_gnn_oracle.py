@@ -122,7 +122,8 @@ def pin_gradients_by_finite_differences(go=go):
     flat = go.init_params(5)
     rng = np.random.default_rng(9)
     flat += rng.normal(size=flat.size) * 0.05     # non-zero biases
-    L, g = go.loss_and_grad(flat, G, xs, ys, lws, emulate_bf16=False)
+    w_om = 3.0   # a weight other than 1 on the log-omega term
+    L, g = go.loss_and_grad(flat, G, xs, ys, lws, emulate_bf16=False, omega_weight=w_om)
     offs, o = {}, 0
     for name, sh in go.param_shapes():
         offs[name] = (o, int(np.prod(sh)))
@@ -135,8 +136,8 @@ def pin_gradients_by_finite_differences(go=go):
     for i in idx:
         fp = flat.copy(); fp[i] += h
         fm = flat.copy(); fm[i] -= h
-        Lp, _ = go.loss_and_grad(fp, G, xs, ys, lws, emulate_bf16=False)
-        Lm, _ = go.loss_and_grad(fm, G, xs, ys, lws, emulate_bf16=False)
+        Lp, _ = go.loss_and_grad(fp, G, xs, ys, lws, emulate_bf16=False, omega_weight=w_om)
+        Lm, _ = go.loss_and_grad(fm, G, xs, ys, lws, emulate_bf16=False, omega_weight=w_om)
         fd = (Lp - Lm) / (2 * h)
         err = abs(fd - g[i]) / max(1e-6, abs(fd), abs(g[i]))
         worst = max(worst, err)
@@ -207,6 +208,7 @@ MUTANTS = {
                                         "dyh = 2.0 * ey / np.maximum(nq[G.rinst], 1.0) / K"),
     "bf16_rounds_ties_up": ("u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u = (u + 0x8000) & 0xFFFF0000"),
     "degree_feature_scale": ("fv[:, 5] = np.log1p(degc) / 4.0", "fv[:, 5] = np.log1p(degc) / 2.0"),
+    "omega_weight_missing_in_gradient": ("dlw = 2.0 * omega_weight * ew / K", "dlw = 2.0 * ew / K"),
 }
 
 

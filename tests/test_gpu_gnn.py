@@ -118,9 +118,10 @@ def _targets(lps, seed):
     return xs, ys, om
 
 
-def test_gradients_match_oracle(setup):
+@pytest.mark.parametrize("w_om", [1.0, 7.5])
+def test_gradients_match_oracle(setup, w_om):
     lps, batch, G, pr, pc, Dr, Dc = setup
-    net = pdlp.WarmStartNet(seed=0)
+    net = pdlp.WarmStartNet(seed=0, omega_weight=w_om)
     p = _params(2)
     net.set_params(p)
     xs, ys, om = _targets(lps, 3)
@@ -129,7 +130,7 @@ def test_gradients_match_oracle(setup):
     txs = (xs[pc] / Dc).astype(np.float32).astype(np.float64)
     tys = (ys[pr] / Dr).astype(np.float32).astype(np.float64)
     tlw = np.log(om).astype(np.float32).astype(np.float64)
-    oL, og = go.loss_and_grad(p.astype(np.float64), G, txs, tys, tlw, emulate_bf16=True)
+    oL, og = go.loss_and_grad(p.astype(np.float64), G, txs, tys, tlw, emulate_bf16=True, omega_weight=w_om)
     print("loss gpu %.10g oracle %.10g" % (loss, oL))
     assert abs(loss - oL) <= REL_OUT * abs(oL)
     o = 0
