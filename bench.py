@@ -53,13 +53,14 @@ def algorithmic_bytes(kernel, m, n, nnz, tb):
            the row senses, write y' and ax'.
     primal (A'y' + primal update + averages, accepted attempt): A' values + columns, row offsets,
            gather of y', write A'y', read x, c, l, u, write x', read+write x-bar, read y and
-           read+write y-bar; in FP64 also read+write A'y-bar and A x-bar and read A x (FP32
-           recomputes those two products before each evaluation instead).
+           read+write y-bar (the averages are FP64, 8 bytes, in both precisions); in FP64 also
+           read+write A'y-bar and A x-bar and read A x (FP32 recomputes those two products before
+           each evaluation instead).
     """
     if kernel == "dual":
         return nnz * (tb + 4) + 4 * (m + 1) + tb * n + m * (5 * tb + 1)
     if tb == 4:
-        return nnz * (tb + 4) + 4 * (n + 1) + tb * m + 8 * tb * n + 3 * tb * m
+        return nnz * (tb + 4) + 4 * (n + 1) + tb * m + (6 * tb + 16) * n + (tb + 16) * m
     return nnz * (tb + 4) + 4 * (n + 1) + tb * m + 10 * tb * n + 6 * tb * m
 
 

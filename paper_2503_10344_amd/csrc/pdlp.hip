@@ -214,7 +214,8 @@ struct Solver {
   T *cT = nullptr, *bT = nullptr, *lT = nullptr, *uT = nullptr;
   // iterates
   T *xs[2] = {nullptr, nullptr}, *ys[2] = {nullptr, nullptr}, *axs[2] = {nullptr, nullptr};
-  T *aty = nullptr, *xbar = nullptr, *ybar = nullptr, *axbar = nullptr, *atybar = nullptr;
+  T *aty = nullptr, *axbar = nullptr, *atybar = nullptr;
+  double *xbar = nullptr, *ybar = nullptr;  // running averages, FP64 in both precisions
   T *xa = nullptr, *ya = nullptr, *tmp_n = nullptr, *tmp_m = nullptr;
   // finalize / staging
   double *xd = nullptr, *yd = nullptr, *ax64 = nullptr, *aty64 = nullptr;
@@ -467,8 +468,8 @@ struct Solver {
 
     // iterates and staging
     for (int q = 0; q < 2; ++q) xs[q] = mem.alloc<T>(nn), ys[q] = mem.alloc<T>(mm), axs[q] = mem.alloc<T>(mm);
-    aty = mem.alloc<T>(nn), xbar = mem.alloc<T>(nn), atybar = mem.alloc<T>(nn), xa = mem.alloc<T>(nn);
-    ybar = mem.alloc<T>(mm), axbar = mem.alloc<T>(mm), ya = mem.alloc<T>(mm);
+    aty = mem.alloc<T>(nn), xbar = mem.alloc<double>(nn), atybar = mem.alloc<T>(nn), xa = mem.alloc<T>(nn);
+    ybar = mem.alloc<double>(mm), axbar = mem.alloc<T>(mm), ya = mem.alloc<T>(mm);
     tmp_n = mem.alloc<T>(nn), tmp_m = mem.alloc<T>(mm);
     xd = mem.alloc<double>(nn), yd = mem.alloc<double>(mm), ax64 = mem.alloc<double>(mm), aty64 = mem.alloc<double>(nn);
     x_out = mem.alloc<double>(nn), y_out = mem.alloc<double>(mm), rc_out = mem.alloc<double>(nn);
@@ -479,8 +480,10 @@ struct Solver {
       HIPCHK(hipMemsetAsync(ys[q], 0, sizeof(T) * (size_t)mm, stream));
       HIPCHK(hipMemsetAsync(axs[q], 0, sizeof(T) * (size_t)mm, stream));
     }
-    for (T *p : {aty, xbar, atybar, xa, tmp_n}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)nn, stream));
-    for (T *p : {ybar, axbar, ya, tmp_m}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)mm, stream));
+    for (T *p : {aty, atybar, xa, tmp_n}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)nn, stream));
+    for (T *p : {axbar, ya, tmp_m}) HIPCHK(hipMemsetAsync(p, 0, sizeof(T) * (size_t)mm, stream));
+    HIPCHK(hipMemsetAsync(xbar, 0, sizeof(double) * (size_t)nn, stream));
+    HIPCHK(hipMemsetAsync(ybar, 0, sizeof(double) * (size_t)mm, stream));
     HIPCHK(hipMemsetAsync(st, 0, sizeof(State) * (size_t)K, stream));
 
     // ---- SpMV schedule, work blocks and evaluation blocks ----
@@ -683,8 +686,8 @@ struct Solver {
   // the average hands on, are those of the averaged point itself. (FP64 keeps the updates.)
   void refresh_averages() {
     if constexpr (sizeof(T) == sizeof(float)) {
-      spmv_T(0, xbar, axbar);
-      spmv_T(1, ybar, atybar);
+      spmv_chunks<T, double, T, T>(0, xbar, axbar);
+      spmv_chunks<T, double, T, T>(1, ybar, atybar);
     }
   }
   void launch_chunk_body() {
@@ -774,8 +777,9 @@ struct Solver {
     start_point(xd, yd, xs[0], ys[0]);
     return true;
   }
-  void start_point(const double *dx, const double *dy, T *x, T *y) {
-    hipLaunchKernelGGL(k_init_point<T>, dim3(grid_for(std::max(m, n))), dim3(kBlock), 0, stream, m, n, dx, dy,
+  template <typename U>
+  void start_point(const double *dx, const double *dy, U *x, U *y) {
+    hipLaunchKernelGGL(k_init_point<U>, dim3(grid_for(std::max(m, n))), dim3(kBlock), 0, stream, m, n, dx, dy,
                        (const double *)Dr, (const double *)Dc, (const double *)l64, (const double *)u64,
                        (const uint8_t *)sense, x, y);
     HIPCHK(hipGetLastError());
@@ -825,8 +829,8 @@ struct Solver {
     if (warm && opt.warm_fallback) {
       // cold start in the average slots; compare the relative KKT errors of both points
       start_point(nullptr, nullptr, xbar, ybar);
-      spmv_T(0, xbar, axbar);
-      spmv_T(1, ybar, atybar);
+      spmv_chunks<T, double, T, T>(0, xbar, axbar);
+      spmv_chunks<T, double, T, T>(1, ybar, atybar);
       launch_eval(kEvalPoint);
       HIPCHK(hipGetLastError());
       read_state();

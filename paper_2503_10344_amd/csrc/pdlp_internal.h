@@ -83,7 +83,8 @@ struct Iter {
   // iterates
   T *x[2], *y[2], *ax[2];
   T *aty;
-  T *xbar, *ybar, *axbar, *atybar;
+  double *xbar, *ybar;  // running averages: FP64 in both precisions (FP32 would lose late updates)
+  T *axbar, *atybar;
   T *xa, *ya;
   // block partial sums (one slot per block of the producing kernel) and state
   double *p_dual;     // [ab_blocks][2]  |dy|^2, dy'(A dx)

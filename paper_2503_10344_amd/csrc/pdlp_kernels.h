@@ -453,6 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   const int cur = st->cur, commit = st->commit, stop = st->stop;
   const T tau = T(st->eta / st->omega);
   const T wa = T(st->avg_w);
+  const double wad = st->avg_w;
   const T *__restrict__ xc = P.x[cur];
   T *__restrict__ xnx = P.x[cur ^ 1];
   const T *__restrict__ yc = P.y[cur];
@@ -460,11 +461,13 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   const T *__restrict__ lo = P.l;
   const T *__restrict__ hi = P.u;
   T *__restrict__ aty = P.aty;
-  T *__restrict__ xbar = P.xbar;
+  double *__restrict__ xbar = P.xbar;
   T *__restrict__ atybar = P.atybar;
   double acc[1] = {0.0};
   struct PrimalPre {
-    T x, c, l, u, xbar, atybar;
+    T x, c, l, u;
+    double xbar;
+    T atybar;
   };
   // FP64 keeps A'y-bar and A x-bar current with the averages' weighted updates; FP32 recomputes
   // both before each evaluation (the only readers), so it skips them here.
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   auto fetch = [&](int j) { return PrimalPre{xc[j], c[j], lo[j], hi[j], xbar[j], kTrack ? atybar[j] : T(0)}; };
   auto primal = [&](int j, T atyj, const PrimalPre &q) {
     if (commit) {
-      xbar[j] = q.xbar + wa * (q.x - q.xbar);
+      xbar[j] = q.xbar + wad * (double(q.x) - q.xbar);
       if (kTrack) atybar[j] = q.atybar + wa * (atyj - q.atybar);
     }
     if (!stop) {
@@ -491,12 +494,12 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
                             primal(j, s, q);
                           });
     const T *__restrict__ axc = P.ax[cur];
-    T *__restrict__ ybar = P.ybar;
+    double *__restrict__ ybar = P.ybar;
     T *__restrict__ axbar = P.axbar;
     int rb, re;
     share(P.L.row0[w.inst], P.L.row0[w.inst + 1] - P.L.row0[w.inst], w.lb, w.nb, &rb, &re);
     for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-      ybar[i] += wa * (yc[i] - ybar[i]);
+      ybar[i] += wad * (double(yc[i]) - ybar[i]);
       if (kTrack) axbar[i] += wa * (axc[i] - axbar[i]);
     }
   } else if (!stop && ce > cb) {
@@ -695,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
   for (int j = P.L.col0[E.inst] + off; j < c1; j += gs) {
     T xj, atyj;
     if (mode == kToAverage) {
-      xj = P.xbar[j], atyj = P.atybar[j];
+      xj = T(P.xbar[j]), atyj = P.atybar[j];
       xc[j] = xj, P.aty[j] = atyj;
     } else {
       xj = xc[j], atyj = P.aty[j];
@@ -713,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
   for (int i = P.L.row0[E.inst] + off; i < r1; i += gs) {
     T yi;
     if (mode == kToAverage) {
-      yi = P.ybar[i];
+      yi = T(P.ybar[i]);
       yc[i] = yi, axc[i] = P.axbar[i];
     } else {
       yi = yc[i];
@@ -751,16 +754,16 @@ __global__ __launch_bounds__(kBlock) void k_unscale(Iter<T> P, double *__restric
   const EvBlock E = ev_block(P.L);
   const State *st = P.st + E.inst;
   const int cur = st->cur, which = st->which;
-  const T *__restrict__ x = which ? P.xbar : P.x[cur];
-  const T *__restrict__ y = which ? P.ybar : P.y[cur];
+  const T *__restrict__ x = P.x[cur];
+  const T *__restrict__ y = P.y[cur];
   const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
   for (int j = P.L.col0[E.inst] + off; j < P.L.col0[E.inst + 1]; j += gs) {
-    const double v = double(x[j]);
+    const double v = which ? P.xbar[j] : double(x[j]);
     xd[j] = v;
     x_out[j] = P.Dc[j] * v;
   }
   for (int i = P.L.row0[E.inst] + off; i < P.L.row0[E.inst + 1]; i += gs) {
-    const double v = double(y[i]);
+    const double v = which ? P.ybar[i] : double(y[i]);
     yd[i] = v;
     y_out[i] = P.Dr[i] * v;
   }
