@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--iter-limit", type=int, default=500_000)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 cold-solve comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=160, help="oracle attempts in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=1000, help="oracle attempts in the CPU sample")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--warm-instances", type=int, default=48)
     ap.add_argument("--batch-count", type=int, default=256)

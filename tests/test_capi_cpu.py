@@ -150,3 +150,4 @@ def test_gnn_rejects_null_arguments(lib):
     assert lib.pdlp_gnn_predict(None, None, None, None, None) == -1
     assert lib.pdlp_gnn_train_step(None, None, None, None, None, C.c_float(1e-3), None) == -1
     assert lib.pdlp_batch_get_internal(None, *([None] * 8)) == -1
+    assert lib.pdlp_gnn_set_omega_weight(None, C.c_float(1.0)) == -1
