@@ -123,23 +123,37 @@ struct Model {
     side(g.h_row0, h_ccs, h_cce, h_ccq, h_cch0);
   }
 
-  void ensure(const GraphView &g) {
+  // Workspace for the graph. Prediction keeps two activation buffers and one message buffer per
+  // side (the layers alternate between them); training keeps every layer for the backward pass and
+  // the gradient buffers (about 14 x 64 floats per node against 3 x 64).
+  bool cap_train = false;
+  void ensure(const GraphView &g, bool training) {
     const int64_t nchv = (int64_t)h_vcs.size(), nchc = (int64_t)h_ccs.size();
     const bool need_vals = g.a_v == nullptr;
     if (g.n <= cap_n && g.m <= cap_m && g.K <= cap_k && nchv <= cap_chv && nchc <= cap_chc &&
-        (!need_vals || g.nnz <= cap_nnz))
+        (!need_vals || g.nnz <= cap_nnz) && (!training || cap_train))
       return;
     ws.reset();
+    cap_train = cap_train || training;
     cap_n = std::max<int64_t>(g.n, cap_n), cap_m = std::max<int64_t>(g.m, cap_m);
     cap_k = std::max<int64_t>(g.K, cap_k), cap_chv = std::max(nchv, cap_chv), cap_chc = std::max(nchc, cap_chc);
     cap_nnz = std::max<int64_t>(need_vals ? g.nnz : 0, cap_nnz);
     const int64_t N = cap_n, M = cap_m;
     fv = ws.alloc<float>(N * kF), fc = ws.alloc<float>(M * kF);
-    for (int l = 0; l <= kLayers; ++l) hv[l] = ws.alloc<float>(N * kH), hc[l] = ws.alloc<float>(M * kH);
-    for (int l = 0; l < kLayers; ++l) mv[l] = ws.alloc<float>(N * kH), mc[l] = ws.alloc<float>(M * kH);
-    for (int t = 0; t < 2; ++t) dhv[t] = ws.alloc<float>(N * kH), dhc[t] = ws.alloc<float>(M * kH);
-    dmv = ws.alloc<float>(N * kH), dmc = ws.alloc<float>(M * kH);
-    part = ws.alloc<float>((int64_t)kMaxWavesBwd * (kH * kH * 2 + kH));
+    if (cap_train) {
+      for (int l = 0; l <= kLayers; ++l) hv[l] = ws.alloc<float>(N * kH), hc[l] = ws.alloc<float>(M * kH);
+      for (int l = 0; l < kLayers; ++l) mv[l] = ws.alloc<float>(N * kH), mc[l] = ws.alloc<float>(M * kH);
+      for (int t = 0; t < 2; ++t) dhv[t] = ws.alloc<float>(N * kH), dhc[t] = ws.alloc<float>(M * kH);
+      dmv = ws.alloc<float>(N * kH), dmc = ws.alloc<float>(M * kH);
+      part = ws.alloc<float>((int64_t)kMaxWavesBwd * (kH * kH * 2 + kH));
+    } else {
+      float *v2[2] = {ws.alloc<float>(N * kH), ws.alloc<float>(N * kH)};
+      float *c2[2] = {ws.alloc<float>(M * kH), ws.alloc<float>(M * kH)};
+      float *mv1 = ws.alloc<float>(N * kH), *mc1 = ws.alloc<float>(M * kH);
+      for (int l = 0; l <= kLayers; ++l) hv[l] = v2[l & 1], hc[l] = c2[l & 1];
+      for (int l = 0; l < kLayers; ++l) mv[l] = mv1, mc[l] = mc1;
+      dhv[0] = dhv[1] = dhc[0] = dhc[1] = dmv = dmc = part = nullptr;
+    }
     gpart_v = ws.alloc<float>(cap_chv * (kH + 1)), gpart_c = ws.alloc<float>(cap_chc * (kH + 1));
     xhat = ws.alloc<float>(N), yhat = ws.alloc<float>(M), tx = ws.alloc<float>(N), ty = ws.alloc<float>(M);
     logw = ws.alloc<float>(cap_k), tw = ws.alloc<float>(cap_k), dlw = ws.alloc<float>(cap_k);
@@ -155,9 +169,9 @@ struct Model {
   }
 
   // Upload chunk tables, FP32 values when the handle iterates in FP64. Returns the value arrays.
-  void prepare(const GraphView &g, const float *&av, const float *&tv) {
+  void prepare(const GraphView &g, const float *&av, const float *&tv, bool training) {
     build_chunks(g);
-    ensure(g);
+    ensure(g, training);
     hipStream_t st = g.stream;
     auto up = [&](int32_t *d, const std::vector<int32_t> &h) {
       if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, st));
@@ -331,7 +345,7 @@ void gnn_predict(pdlp::gnn::Model &M, const pdlp::gnn::GraphView &v, double *x0,
                  float *raw_x, float *raw_y, float *raw_logw) {
   using namespace pdlp::gnn;
   const float *av = nullptr, *tv = nullptr;
-  M.prepare(v, av, tv);
+  M.prepare(v, av, tv, false);
   M.forward(v, av, tv, false);
   hipStream_t st = v.stream;
   if (x0 && v.n) {
@@ -445,7 +459,7 @@ int pdlp_gnn_gradients(pdlp_gnn *g, pdlp_batch *b, const double *x_star, const d
   return with_graph(g, b->s, [&](const pdlp::gnn::GraphView &v) {
     auto &M = g->model;
     const float *av = nullptr, *tv = nullptr;
-    M.prepare(v, av, tv);
+    M.prepare(v, av, tv, true);
     M.load_targets(v, x_star, y_star, omega_star);
     M.forward(v, av, tv, true);
     M.backward(v, av, tv);
@@ -465,7 +479,7 @@ int pdlp_gnn_train_step(pdlp_gnn *g, pdlp_batch *b, const double *x_star, const 
     using namespace pdlp::gnn;
     auto &M = g->model;
     const float *av = nullptr, *tv = nullptr;
-    M.prepare(v, av, tv);
+    M.prepare(v, av, tv, true);
     M.load_targets(v, x_star, y_star, omega_star);
     M.forward(v, av, tv, true);
     M.backward(v, av, tv);

@@ -133,6 +133,28 @@ def warm_solve(net, problem: pdlp.Problem, tol=1e-4, iter_limit=100_000, mode="f
                 primal_obj=info["primal_obj"])
 
 
+def warm_solve_batch(net, batch: pdlp.Batch, tol=1e-4, iter_limit=100_000, mode="full") -> list:
+    """Predict starts for every instance of a batch in one pass and solve them together; instances
+    that end at the budget are not repeated here (per-instance results carry the status)."""
+    if mode not in MODES and mode != "cold":
+        raise ValueError(f"unknown warm-start mode {mode}")
+    if mode == "cold":
+        return batch.solve(tol=tol, iter_limit=iter_limit)
+    x0, y0, om = net.predict(batch)
+    xs, ys, co, ro = [], [], 0, 0
+    for m, n in batch.dims:
+        xs.append(x0[co:co + n] if mode not in ("omega", "dual_omega") else None)
+        ys.append(y0[ro:ro + m] if mode not in ("omega", "primal_omega") else None)
+        co += n
+        ro += m
+    oms = om if mode != "primal_dual" else None
+    if all(v is None for v in xs):
+        xs = None
+    if all(v is None for v in ys):
+        ys = None
+    return batch.solve(tol=tol, iter_limit=iter_limit, x0s=xs, y0s=ys, omega0s=oms)
+
+
 def evaluate(net, seeds, tol=1e-4, iter_limit=100_000, modes=MODES, m_lo=10_000, m_hi=100_000, log=_log):
     """Cold vs warm on each instance (same handle, cold first)."""
     rows = []

@@ -66,3 +66,22 @@ def test_trained_network_reduces_iterations_on_held_out_instances():
           "geometric-mean ratio %.3f, total ratio %.3f" % (geo, sum(warm_it) / sum(cold_it)))
     assert geo < 1.0
     assert sum(warm_it) < sum(cold_it)
+
+
+def test_batched_warm_solve_matches_single_warm_solves():
+    """One batched prediction + one batched solve gives each instance what it gets alone."""
+    net, _ = warmstart.load_trained()
+    lps = [gen.warmstart_family(s, m_lo=2_000, m_hi=8_000) for s in range(1_000_100, 1_000_106)]
+    for mode in ("full", "omega"):
+        with pdlp.Batch(lps, tile_nnz=512) as b:
+            infos = warmstart.warm_solve_batch(net, b, tol=TOL, mode=mode)
+            sols = [b.get(i) for i in range(len(lps))]
+        for lp, info, sol in zip(lps, infos, sols):
+            with pdlp.Problem(lp, tile_nnz=512) as p:
+                x0, y0, om = net.predict(p)
+                one = p.solve(tol=TOL, x0=None if mode == "omega" else x0, y0=None if mode == "omega" else y0,
+                              omega0=om)
+                s1 = p.get()
+            assert info["iterations"] == one["iterations"], (mode, info["iterations"], one["iterations"])
+            assert info["fallback_used"] == one["fallback_used"]
+            np.testing.assert_array_equal(sol.x, s1.x)
