@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "60c88eb33de276416e26a1a8c4112f9b411af347"): 454_221_926,
-    ("energy", "60c88eb33de276416e26a1a8c4112f9b411af347"): 467_188_941,
+    ("zipf", "ca91fd178faaf9700f7ce92294a88bda919bd326"): 454_908_723,
+    ("energy", "ca91fd178faaf9700f7ce92294a88bda919bd326"): 467_667_558,
 }
 
 
