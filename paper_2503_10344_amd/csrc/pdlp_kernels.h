@@ -392,29 +392,49 @@ __device__ inline void step_size_rule(State *st, int32_t *ndone, double dx2, dou
   }
 }
 
-// Sum over [lo, hi) of p[stride * q + off] by a kStepBlock-thread block; four independent
-// accumulators per thread keep several loads in flight. Result valid in thread 0.
+// The three step-size sums in one pass: |dy|^2 and dy'(A dx) over p_dual[2 q], p_dual[2 q + 1],
+// q in [a_lo, a_hi), and |dx|^2 over p_dx[q], q in [t_lo, t_hi). Each sum keeps the order of a
+// single strided reduction (four accumulators per thread over q, q + B, q + 2B, q + 3B, a wave
+// tree, then the waves in order), so the three loads chains overlap without changing any result.
+// Results valid in thread 0.
 constexpr int kStepBlock = 1024;
-__device__ __forceinline__ double step_sum(const double *__restrict__ p, int stride, int off, int lo, int hi) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int q = lo + (int)threadIdx.x;
-  for (; q + 3 * kStepBlock < hi; q += 4 * kStepBlock) {
-    a0 += p[(size_t)stride * q + off];
-    a1 += p[(size_t)stride * (q + kStepBlock) + off];
-    a2 += p[(size_t)stride * (q + 2 * kStepBlock) + off];
-    a3 += p[(size_t)stride * (q + 3 * kStepBlock) + off];
+__device__ __forceinline__ void step_sums(const double *__restrict__ p_dual, int a_lo, int a_hi,
+                                          const double *__restrict__ p_dx, int t_lo, int t_hi, double &dy2,
+                                          double &inter, double &dx2) {
+  constexpr int B = kStepBlock;
+  double a[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+  int q = a_lo + (int)threadIdx.x;
+  for (; q + 3 * B < a_hi; q += 4 * B) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[0][u] += p_dual[2 * (size_t)(q + u * B)];
+      a[1][u] += p_dual[2 * (size_t)(q + u * B) + 1];
+    }
   }
-  for (; q < hi; q += kStepBlock) a0 += p[(size_t)stride * q + off];
-  double v = wave_sum((a0 + a1) + (a2 + a3));
-  __shared__ double red[kStepBlock / kWave];
-  __syncthreads();
-  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  for (; q < a_hi; q += B) a[0][0] += p_dual[2 * (size_t)q], a[1][0] += p_dual[2 * (size_t)q + 1];
+  q = t_lo + (int)threadIdx.x;
+  for (; q + 3 * B < t_hi; q += 4 * B) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[2][u] += p_dx[q + u * B];
+  }
+  for (; q < t_hi; q += B) a[2][0] += p_dx[q];
+  __shared__ double red[3][B / kWave];
+  double v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = wave_sum((a[i][0] + a[i][1]) + (a[i][2] + a[i][3]));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) red[i][threadIdx.x / kWave] = v[i];
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    v = red[0];
-    for (int w = 1; w < kStepBlock / kWave; ++w) v += red[w];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      v[i] = red[i][0];
+      for (int w = 1; w < B / kWave; ++w) v[i] += red[i][w];
+    }
+    dy2 = v[0], inter = v[1], dx2 = v[2];
   }
-  return v;
 }
 
 __global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__restrict__ p_dual,
@@ -428,11 +448,10 @@ __global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__r
     if (threadIdx.x == 0) mark_done(st, ndone);
     return;
   }
-  const double dy2 = step_sum(p_dual, 2, 0, L.ab0[inst], L.ab0[inst + 1]);
-  const double inter = step_sum(p_dual, 2, 1, L.ab0[inst], L.ab0[inst + 1]);
-  const double dx2 = st->restart_mode != kNoRestart
-                         ? step_sum(p_restart, 1, 0, L.ev_blk0[inst], L.ev_blk0[inst + 1])
-                         : step_sum(p_primal, 1, 0, L.tb0[inst], L.tb0[inst + 1]);
+  const bool rs = st->restart_mode != kNoRestart;
+  double dy2 = 0.0, inter = 0.0, dx2 = 0.0;
+  step_sums(p_dual, L.ab0[inst], L.ab0[inst + 1], rs ? p_restart : p_primal, rs ? L.ev_blk0[inst] : L.tb0[inst],
+            rs ? L.ev_blk0[inst + 1] : L.tb0[inst + 1], dy2, inter, dx2);
   if (threadIdx.x == 0) {
     st->restart_mode = kNoRestart;
     step_size_rule(st, ndone, dx2, dy2, inter);
