@@ -167,8 +167,9 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
 
 /*
  * Kernel timing of the last pdlp_solve with pdlp_options.kernel_timing = 1.
- *   kernel 0: A x' fused with the dual update and the step-size decision
+ *   kernel 0: A x' fused with the dual update and the step-size partial sums
  *   kernel 1: A'y' fused with the primal update and the iterate averages
+ * (the step-size decision itself runs in a small per-instance kernel between them and is not timed)
  * *launches receives the number of launches, *total_ms their summed HIP-event durations.
  */
 int pdlp_kernel_stats(pdlp_problem *p, int32_t kernel, int64_t *launches, double *total_ms);

@@ -103,9 +103,9 @@ __device__ __forceinline__ A block_sum_scalar(A v) {
   return v;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs. Give every XCD a contiguous range of
-// tiles so that neighbouring tiles (which gather neighbouring parts of x in structured matrices)
-// share that XCD's L2.
+// Workgroups are dispatched round-robin over the 8 XCDs. Give every XCD a contiguous range of an
+// instance's work blocks so that neighbouring chunks (which gather neighbouring parts of x in
+// structured matrices) share that XCD's L2.
 __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   constexpr int kXcd = 8;
   if (nb < kXcd) return bid;
@@ -319,7 +319,7 @@ __device__ __forceinline__ void share(int base, int count, int lb, int nb, int *
 // k_dual: A x' fused with the dual update.
 //   ax'_i = (A x')_i ;  y'_i = proj_Y(y_i + sigma (b_i - 2 ax'_i + ax_i)), sigma = eta * omega
 //   per-block partial sums of |dy|^2 and dy'(ax' - ax).
-// Grid: the A-side work blocks of all instances; each owns a contiguous run of tiles.
+// Grid: the A-side work blocks of all instances; each owns a contiguous run of chunks.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
