@@ -26,8 +26,9 @@
  *   - All work is ordered on pdlp_options.stream (a hipStream_t; NULL = the library creates one).
  *     pdlp_solve and pdlp_get return after the stream has finished their work.
  *   - Determinism: the same input and options on the same GPU give bitwise identical results
- *     for a given chunk size. With tile_nnz = 0 the chunk size is chosen by timing, keeping 512
- *     unless another candidate is at least 15 % faster; set tile_nnz to pin it across processes.
+ *     for a given chunk size, and an instance of a batch gets the bits it gets solved alone. With
+ *     tile_nnz = 0 the chunk size is 512 unless, for 200,000 or more nonzeros, timing finds another
+ *     candidate at least 15 % faster; set tile_nnz to pin it across processes.
  *   - Calls on one handle must not overlap; different handles are independent.
  */
 #ifndef PDLP_H_
@@ -75,8 +76,9 @@ typedef struct pdlp_options {
   int32_t kernel_timing;   /* 1 = bracket every launch of the two iteration kernels with HIP events
                               on the handle's stream (graphs are not used then); read the totals with
                               pdlp_kernel_stats (default 0) */
-  int32_t work_blocks;     /* blocks per SpMV kernel across all instances (each owns a contiguous run
-                              of chunks); 0 = 8192 (default 0) */
+  int32_t work_blocks;     /* most blocks per SpMV kernel for one instance (each block owns a
+                              contiguous run of chunks; an instance gets one block per 2048 nonzeros
+                              + rows up to this count); 0 = 8192 (default 0) */
   int32_t reserved[5];
 } pdlp_options;
 
@@ -212,6 +214,12 @@ int pdlp_batch_solve(pdlp_batch *bt, double tol, int64_t iter_limit, const doubl
 /* Solution of instance i (0 <= i < k), as pdlp_get. */
 int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_cost,
                    pdlp_result *res);
+
+/* SpMV schedule of the batch, as pdlp_get_schedule (chunk counts over all instances). An
+ * instance's chunks and work blocks depend on the instance and the chunk size alone, so a single
+ * problem created with pdlp_options.tile_nnz set to this chunk size (and the same other options)
+ * follows the instance's trajectory bit for bit. */
+int pdlp_batch_get_schedule(pdlp_batch *bt, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at);
 
 void pdlp_batch_destroy(pdlp_batch *bt);
 

@@ -171,6 +171,9 @@ static void class_order(const std::vector<int64_t> &len, int32_t lo, int32_t hi,
 }
 
 static const int kChunkCandidates[] = {512, 1024, 2048, 4096};
+// Smallest weight (nonzeros + rows) worth a work block of its own: about one 512-nonzero chunk per
+// wave of the block.
+static const int64_t kMinBlockWeight = 2048;
 constexpr int kMaxResumes = 6;  // FP64 re-checks that may send an instance back into the loop
 
 // Autotune cache: matrix signature -> chosen chunk size.
@@ -197,7 +200,7 @@ struct Solver {
   int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
   int32_t *d_a_bchunk = nullptr, *d_t_bchunk = nullptr;  // first chunk of each work block
   int ab_blocks = 1, tb_blocks = 1, ev_blocks = 1;
-  int work_blocks = 8192;  // target number of work blocks per side for the whole handle
+  int work_blocks = 8192;  // most work blocks per side of one instance
   // matrix
   int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr, *perm = nullptr;
   int32_t *a_chunk_row = nullptr, *t_chunk_row = nullptr;
@@ -550,10 +553,12 @@ struct Solver {
     d_a_chunk0 = alloc_upload(h_a_chunk0), d_t_chunk0 = alloc_upload(h_t_chunk0);
     a_nchunks = (int)ca.size(), t_nchunks = (int)ct.size();
     chunk_nnz = cap;
-    // Work blocks: about work_blocks per side for the whole handle, shared out over the instances by
-    // weight (nonzeros + rows: every row has an epilogue), at least one per instance and at most one
-    // per chunk. Inside an instance each block takes a contiguous run of chunks of about equal
-    // weight; a chunk heavier than a block's share (one very long row) gets a block of its own.
+    // Work blocks: an instance of weight w (nonzeros + rows: every row has an epilogue) gets
+    // ceil(w / kMinBlockWeight) blocks per side, at most work_blocks, at least one and at most one
+    // per chunk. The count depends on the instance alone, so an instance solved in a batch groups
+    // its FP64 partial sums exactly as it does solved alone (same chunk size), and follows the same
+    // trajectory bit for bit. Inside an instance each block takes a contiguous run of chunks of about
+    // equal weight; a chunk heavier than a block's share (one very long row) gets a block of its own.
     std::vector<int32_t> ab_inst, tb_inst, a_bchunk, t_bchunk;
     auto blocks_for = [&](const std::vector<int32_t> &rp, const std::vector<int32_t> &crow,
                           const std::vector<int32_t> &ch0, std::vector<int32_t> &b0, std::vector<int32_t> &binst,
@@ -562,14 +567,13 @@ struct Solver {
       std::vector<int64_t> wpre((size_t)nch + 1, 0);  // prefix of chunk weights (global)
       for (int c = 0; c < nch; ++c)
         wpre[c + 1] = wpre[c] + (rp[crow[c + 1]] - rp[crow[c]]) + (crow[c + 1] - crow[c]);
-      const int64_t total = std::max<int64_t>(wpre[nch], 1);
       b0.assign(1, 0);
       binst.clear();
       bchunk.clear();
       for (int q = 0; q < K; ++q) {
         const int c0 = ch0[q], c1 = ch0[q + 1];
         const int64_t wq = wpre[c1] - wpre[c0];
-        int64_t nbq = (wq * work_blocks + total - 1) / total;
+        int64_t nbq = std::min<int64_t>(work_blocks, (wq + kMinBlockWeight - 1) / kMinBlockWeight);
         nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, std::max(c1 - c0, 1)));
         int c = c0;
         for (int64_t lb = 0; lb < nbq; ++lb) {
@@ -626,7 +630,7 @@ struct Solver {
         return;
       }
     }
-    int pick = 2048;
+    int pick = kChunkCandidates[0];
     if (nnz >= 200000) {
       hipEvent_t e0, e1;
       HIPCHK(hipEventCreate(&e0));
@@ -1286,6 +1290,20 @@ int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_
     return PDLP_ERR_ARG;
   }
   return guarded([&] { bt->s.visit([&](auto &s) { s.get(i, x, y, red_cost, res); }); });
+}
+
+int pdlp_batch_get_schedule(pdlp_batch *bt, int32_t *tile_nnz, int32_t *tiles_a, int32_t *tiles_at) {
+  if (!bt) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    bt->s.visit([&](auto &s) {
+      if (tile_nnz) *tile_nnz = s.chunk_nnz;
+      if (tiles_a) *tiles_a = s.a_nchunks;
+      if (tiles_at) *tiles_at = s.t_nchunks;
+    });
+  });
 }
 
 void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }

@@ -59,7 +59,7 @@ class ProblemDesc(C.Structure):
 EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_spmv",
            "pdlp_get_scaling", "pdlp_get_internal", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
-           "pdlp_batch_get", "pdlp_batch_destroy"]
+           "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy"]
 
 _lib = None
 
@@ -94,6 +94,8 @@ def load(path: str = LIB_PATH):
     lib.pdlp_get_internal.restype = C.c_int
     lib.pdlp_get_schedule.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.pdlp_get_schedule.restype = C.c_int
+    lib.pdlp_batch_get_schedule.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.pdlp_batch_get_schedule.restype = C.c_int
     lib.pdlp_kernel_stats.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(dp)]
     lib.pdlp_kernel_stats.restype = C.c_int
     lib.pdlp_device_bytes.argtypes = [vp]
@@ -375,6 +377,11 @@ class Batch:
         x, y, rc = np.zeros(n), np.zeros(m), np.zeros(n)
         r = pdlp_batch_get(self.h, i, x, y, rc)
         return Solution(x, y, rc, r.as_dict())
+
+    def schedule(self) -> dict:
+        tn, ta, tt = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().pdlp_batch_get_schedule(self.h, C.byref(tn), C.byref(ta), C.byref(tt)))
+        return dict(tile_nnz=tn.value, tiles_a=ta.value, tiles_at=tt.value)
 
     @property
     def m(self):

@@ -131,6 +131,7 @@ def test_null_arguments(lib):
     assert lib.pdlp_create(None, 1, 1, 0, None, None, None, None, None, None, None, None, None) == -1
     assert lib.pdlp_solve(None, 1e-4, 10, None, None, 0.0) == -1
     assert lib.pdlp_get(None, None, None, None, None) == -1
+    assert lib.pdlp_batch_get_schedule(None, None, None, None) == -1
     assert lib.pdlp_error_string(-2) == b"malformed CSR matrix"
 
 

@@ -338,8 +338,10 @@ def test_device_memory_cap(pdlp):
 
 
 def test_batch_matches_single(pdlp):
+    """Each instance's chunks and work blocks depend on it alone: bitwise the single solve. The
+    general sparse member is large enough for dozens of work blocks per side."""
     lps = [g.set_cover(10, m=300, n=700), g.general_sparse(11, m=200, n=500, cap=60),
-           g.multi_knapsack(12, m=150, n=400)]
+           g.multi_knapsack(12, m=150, n=400), g.general_sparse(13, m=6000, n=12000, cap=800)]
     singles = []
     for lp in lps:
         with pdlp.Problem(lp, precision="fp32", tile_nnz=1024) as p:
