@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "705951def32871432b0d8d14da2632cdcf6a806b"): 454_825_574,
-    ("energy", "705951def32871432b0d8d14da2632cdcf6a806b"): 466_959_667,
+    ("zipf", "ed65b2c7f2a8adfeb2042adb2e12ed3bbb5ef8d4"): 454_690_163,
+    ("energy", "ed65b2c7f2a8adfeb2042adb2e12ed3bbb5ef8d4"): 467_401_474,
 }
 
 
