@@ -127,6 +127,24 @@ def test_rejects_bad_data(lib):
     assert _create(lib, lp, sense=s)[0] == -1
 
 
+def test_rejects_sizes_beyond_int32_indices(lib):
+    """Indices are 32-bit: 2^31 - 1 or more nonzeros, or negative sizes, are rejected before any
+    input is read (the data pointers below are far too short to be read)."""
+    from paper_2503_10344_amd import pdlp
+    o = pdlp.Options()
+    lib.pdlp_options_default(C.byref(o))
+    one_i = np.zeros(2, np.int32)
+    one_d = np.zeros(2)
+    sense = np.full(2, ord("E"), np.uint8)
+    for m, n, nnz in ((1, 1, 2**31 - 1), (1, 1, 2**31), (1, 1, 2**40), (-1, 1, 0), (1, -1, 0), (1, 1, -1)):
+        h = C.c_void_p()
+        rc = lib.pdlp_create(C.byref(h), m, n, nnz, pdlp._ptr(one_i), pdlp._ptr(one_i), pdlp._ptr(one_d),
+                             pdlp._ptr(one_d), pdlp._ptr(one_d), pdlp._ptr(sense), pdlp._ptr(one_d),
+                             pdlp._ptr(one_d), C.byref(o))
+        assert rc == -1, (m, n, nnz)
+        assert not h.value
+
+
 def test_null_arguments(lib):
     assert lib.pdlp_create(None, 1, 1, 0, None, None, None, None, None, None, None, None, None) == -1
     assert lib.pdlp_solve(None, 1e-4, 10, None, None, 0.0) == -1
