@@ -330,3 +330,38 @@ def warmstart_family(seed: int, m_lo: int = 10_000, m_hi: int = 100_000) -> LP:
     m_target = float(rng.uniform(m_lo, m_hi))
     T = max(2, int(round(m_target / (N * 8))))
     return energy(int(rng.integers(0, 2**31 - 1)), T=T, N=N, K=6, E=2 * N)
+
+
+# ----------------------------------------------------------------------------------------------
+# Inputs of the LP-based variable strategies and LP-based fixing (random draws only)
+# ----------------------------------------------------------------------------------------------
+VAR_CONTINUOUS, VAR_BINARY, VAR_INTEGER = 0, 1, 2
+
+
+def fixing_inputs(seed: int, lp: LP, int_share: float = 0.6, tie_share: float = 0.3) -> dict:
+    """Seeded stand-ins for an LP solution and a MIP's integrality: variable types (binary where the
+    bounds are [0, 1], otherwise integer with probability int_share, else continuous), a point x
+    inside the bounds, duals y, reduced costs rc and one uniform sample in (0, 1) per variable.
+
+    A share tie_share of x, |y| and rc is drawn from small grids (eighths, a few magnitudes), so that
+    orderings meet many equal keys; some x are integral and some rc are zero.
+    """
+    rng = np.random.default_rng([11, seed])
+    n, m = lp.n, lp.m
+    lo = np.where(np.isfinite(lp.l), lp.l, -20.0)
+    hi = np.where(np.isfinite(lp.u), lp.u, 20.0)
+    hi = np.maximum(hi, lo)
+    binary = (lp.l == 0.0) & (lp.u == 1.0)
+    vtype = np.where(binary, VAR_BINARY,
+                     np.where(rng.random(n) < int_share, VAR_INTEGER, VAR_CONTINUOUS)).astype(np.uint8)
+    x = lo + (hi - lo) * rng.random(n)
+    grid = rng.random(n) < tie_share
+    x = np.where(grid, np.clip(np.floor(x) + rng.integers(0, 9, n) / 8.0, lo, hi), x)
+    y = rng.standard_normal(m) * np.exp(rng.normal(0.0, 1.0, m))
+    ygrid = rng.random(m) < tie_share
+    y = np.where(ygrid, rng.choice([-2.0, -0.5, 0.0, 0.5, 2.0], m), y)
+    rc = rng.standard_normal(n) * np.exp(rng.normal(0.0, 1.0, n))
+    rgrid = rng.random(n) < tie_share
+    rc = np.where(rgrid, rng.choice([-1.0, 0.0, 0.0, 0.25, 1.0], n), rc)
+    uniform = (rng.integers(0, 2**53, n, dtype=np.int64).astype(np.float64) + 0.5) * 2.0**-53
+    return dict(var_type=vtype, x=x, y=y, rc=rc, uniform=uniform)
