@@ -1,0 +1,234 @@
+// Host side of the LP-based variable strategies and LP-based fixing: device workspace, the radix
+// sort driver and the extern "C" entry points declared in include/pdlp_fix.h. Included at the end of
+// pdlp.hip (it uses the solver handle, Arena, HIPCHK and guarded from there).
+#pragma once
+
+#include <cmath>
+#include <vector>
+
+#include "../../include/pdlp_fix.h"
+#include "fix_kernels.h"
+
+namespace pdlp {
+namespace fix {
+
+static int fix_grid(int64_t n) {
+  const int64_t g = (n + kSortBlock - 1) / kSortBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+// Device buffers of one call, released when it returns.
+struct Work {
+  Arena &mem;
+  std::vector<void *> held;
+  explicit Work(Arena &a) : mem(a) {}
+  template <typename U>
+  U *get(int64_t count) {
+    U *p = mem.alloc<U>(count);
+    held.push_back(p);
+    return p;
+  }
+  ~Work() {
+    for (void *p : held) mem.release(p);
+  }
+};
+
+// Stable LSD radix sort of (keys, vals) of n items by the low `digits` bytes of the keys. Buffers
+// ping-pong between (k0, v0) and (k1, v1); on return (k0, v0) hold the result.
+struct RadixSort {
+  hipStream_t stream;
+  int32_t *counts = nullptr, *offs = nullptr, *tsum = nullptr;
+  void scan(int64_t N, const int32_t *in, int32_t *out) {
+    const int64_t tiles = (N + kScanTile - 1) / kScanTile;
+    if (tiles > (int64_t)kSortBlock * 1024) raise(PDLP_ERR_ARG, "scan too long");
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)tiles), dim3(kSortBlock), 0, stream, N, in, out, tsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kSortBlock), 0, stream, (int)tiles, tsum);
+    hipLaunchKernelGGL(k_scan_add, dim3(fix_grid(N)), dim3(kSortBlock), 0, stream, N, out, (const int32_t *)tsum);
+  }
+  void sort(int n, int digits, uint32_t *&k0, int32_t *&v0, uint32_t *&k1, int32_t *&v1) {
+    if (n <= 1) return;
+    const int nb = (n + kSortTile - 1) / kSortTile;
+    for (int d = 0; d < digits; ++d) {
+      const int shift = 8 * d;
+      hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortBlock), 0, stream, n, (const uint32_t *)k0, shift, nb,
+                         counts);
+      scan((int64_t)kDigits * nb, counts, offs);
+      hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortBlock), 0, stream, n, shift, nb, (const uint32_t *)k0,
+                         (const int32_t *)v0, (const int32_t *)offs, k1, v1);
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+    HIPCHK(hipGetLastError());
+  }
+};
+
+// Key list of a strategy, most significant first.
+static void strategy_keys(int s, std::vector<int> &keys) {
+  switch (s) {
+    case PDLP_ORDER_FRAC: keys.push_back(kKeyFrac); break;
+    case PDLP_ORDER_REDCOST: keys.push_back(kKeyRedCost); break;
+    case PDLP_ORDER_DUAL: keys.push_back(kKeyGroup), keys.push_back(kKeyRedCost); break;
+    case PDLP_ORDER_TYPE: keys.push_back(kKeyType); break;
+    default: break;
+  }
+}
+
+template <typename T>
+void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *var_type, const double *x,
+                       const double *y, const double *rc, int32_t *order, int32_t *count) {
+  const bool valid_s = strategy >= PDLP_ORDER_FRAC && strategy <= PDLP_ORDER_TYPE;
+  const bool valid_t = tiebreak >= PDLP_ORDER_NONE && tiebreak <= PDLP_ORDER_TYPE;
+  if (!valid_s || !valid_t) raise(PDLP_ERR_ARG, "unknown variable strategy or tiebreak");
+  if (s.K != 1) raise(PDLP_ERR_ARG, "variable strategies take a single-problem handle");
+  std::vector<int> keys;
+  strategy_keys(strategy, keys);
+  strategy_keys(tiebreak, keys);
+  bool need_x = false, need_rc = false, need_y = false;
+  for (int k : keys) need_x |= k == kKeyFrac, need_rc |= k == kKeyRedCost, need_y |= k == kKeyGroup;
+  if (!var_type || !order || !count || (need_x && !x) || (need_rc && !rc) || (need_y && !y))
+    raise(PDLP_ERR_ARG, "NULL argument that the strategy needs");
+  const int n = s.n, m = s.m;
+  const bool dev = s.opt.device_ptrs != 0;
+  if (!dev) {  // host inputs are checked here; device inputs must be finite
+    auto finite = [](const double *v, int len) {
+      for (int i = 0; i < len; ++i)
+        if (!std::isfinite(v[i])) return false;
+      return true;
+    };
+    if ((need_x && !finite(x, n)) || (need_rc && !finite(rc, n)) || (need_y && !finite(y, m)))
+      raise(PDLP_ERR_ARG, "x, y and red_cost must be finite");
+  }
+  hipStream_t st = s.stream;
+  const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind kout = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  Work w(s.mem);
+  const int64_t big = std::max<int64_t>(std::max(n, m), 1);
+  uint8_t *d_vt = w.get<uint8_t>(n);
+  double *d_x = need_x ? w.get<double>(n) : nullptr;
+  double *d_rc = need_rc ? w.get<double>(n) : nullptr;
+  double *d_y = need_y ? w.get<double>(m) : nullptr;
+  if (n) HIPCHK(hipMemcpyAsync(d_vt, var_type, (size_t)n, kin, st));
+  if (d_x && n) HIPCHK(hipMemcpyAsync(d_x, x, sizeof(double) * (size_t)n, kin, st));
+  if (d_rc && n) HIPCHK(hipMemcpyAsync(d_rc, rc, sizeof(double) * (size_t)n, kin, st));
+  if (d_y && m) HIPCHK(hipMemcpyAsync(d_y, y, sizeof(double) * (size_t)m, kin, st));
+  uint32_t *k0 = w.get<uint32_t>(big), *k1 = w.get<uint32_t>(big);
+  int32_t *v0 = w.get<int32_t>(big), *v1 = w.get<int32_t>(big);
+  const int64_t max_tiles = (big + kSortTile - 1) / kSortTile;
+  RadixSort rs{st};
+  rs.counts = w.get<int32_t>((int64_t)kDigits * max_tiles);
+  rs.offs = w.get<int32_t>(std::max<int64_t>((int64_t)kDigits * max_tiles, big));
+  rs.tsum = w.get<int32_t>(((std::max<int64_t>((int64_t)kDigits * max_tiles, big)) + kScanTile - 1) / kScanTile + 1);
+
+  // binary and integer variables, in index order
+  int32_t k = 0;
+  if (n) {
+    hipLaunchKernelGGL(k_int_flags, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, (const uint8_t *)d_vt, v1);
+    rs.scan(n, v1, rs.offs);
+    hipLaunchKernelGGL(k_int_compact, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, (const uint8_t *)d_vt,
+                       (const int32_t *)rs.offs, v0);
+    int32_t tail[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&tail[0], rs.offs + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&tail[1], v1 + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    k = tail[0] + tail[1];
+  }
+
+  // Dual: rank of each constraint in descending |y| (ties: lower index), then each variable's group
+  uint32_t *d_group = nullptr;
+  if (need_y && k > 0) {
+    d_group = w.get<uint32_t>(n);
+    int32_t *R0 = w.get<int32_t>(std::max(m, 1)), *R1 = w.get<int32_t>(std::max(m, 1));
+    int32_t *rank = w.get<int32_t>(std::max(m, 1));
+    if (m > 0) {
+      hipLaunchKernelGGL(k_iota, dim3(fix_grid(m)), dim3(kSortBlock), 0, st, m, R0);
+      for (int word = 0; word < 2; ++word) {
+        hipLaunchKernelGGL(k_fix_key, dim3(fix_grid(m)), dim3(kSortBlock), 0, st, m, (const int32_t *)R0,
+                           (int)kKeyRowDual, word, (const double *)nullptr, (const double *)nullptr,
+                           (const double *)d_y, (const uint8_t *)nullptr, (const uint32_t *)nullptr, k0);
+        rs.sort(m, 4, k0, R0, k1, R1);
+      }
+      hipLaunchKernelGGL(k_rank, dim3(fix_grid(m)), dim3(kSortBlock), 0, st, m, (const int32_t *)R0, rank);
+    }
+    hipLaunchKernelGGL(k_dual_group, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, m, (const int32_t *)s.t_rp,
+                       (const int32_t *)s.t_ci, (const int32_t *)s.d_perm_r, (const int32_t *)s.d_perm_c,
+                       (const uint8_t *)d_vt, (const int32_t *)rank, d_group);
+  }
+
+  // stable sorts, least significant key first
+  const int group_digits = m < 256 ? 1 : m < 65536 ? 2 : m < (1 << 24) ? 3 : 4;
+  for (int q = (int)keys.size() - 1; q >= 0 && k > 1; --q) {
+    const int kind = keys[q];
+    const bool wide = kind == kKeyFrac || kind == kKeyRedCost;
+    const int digits = wide ? 4 : kind == kKeyGroup ? group_digits : 1;
+    for (int word = 0; word < (wide ? 2 : 1); ++word) {
+      hipLaunchKernelGGL(k_fix_key, dim3(fix_grid(k)), dim3(kSortBlock), 0, st, k, (const int32_t *)v0, kind, word,
+                         (const double *)d_x, (const double *)d_rc, (const double *)nullptr,
+                         (const uint8_t *)d_vt, (const uint32_t *)d_group, k0);
+      rs.sort(k, digits, k0, v0, k1, v1);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  if (k > 0) HIPCHK(hipMemcpyAsync(order, v0, sizeof(int32_t) * (size_t)k, kout, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *count = k;
+}
+
+template <typename T>
+void lp_fixing(Solver<T> &s, const uint8_t *var_type, const double *x, const double *l, const double *u,
+               const double *uniform, double *value) {
+  if (!var_type || !x || !l || !u || !uniform || !value) raise(PDLP_ERR_ARG, "NULL argument to pdlp_lp_fixing");
+  if (s.K != 1) raise(PDLP_ERR_ARG, "LP-based fixing takes a single-problem handle");
+  const int n = s.n;
+  const bool dev = s.opt.device_ptrs != 0;
+  if (!dev) {
+    for (int j = 0; j < n; ++j)
+      if (!std::isfinite(x[j]) || std::isnan(l[j]) || std::isnan(u[j]) || !(uniform[j] > 0.0 && uniform[j] < 1.0))
+        raise(PDLP_ERR_ARG, "x must be finite, bounds not NaN and samples in (0, 1)");
+  }
+  if (n == 0) return;
+  hipStream_t st = s.stream;
+  const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const hipMemcpyKind kout = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  Work w(s.mem);
+  uint8_t *d_vt = w.get<uint8_t>(n);
+  double *d_x = w.get<double>(n), *d_l = w.get<double>(n), *d_u = w.get<double>(n), *d_s = w.get<double>(n);
+  double *d_out = w.get<double>(n);
+  HIPCHK(hipMemcpyAsync(d_vt, var_type, (size_t)n, kin, st));
+  HIPCHK(hipMemcpyAsync(d_x, x, sizeof(double) * (size_t)n, kin, st));
+  HIPCHK(hipMemcpyAsync(d_l, l, sizeof(double) * (size_t)n, kin, st));
+  HIPCHK(hipMemcpyAsync(d_u, u, sizeof(double) * (size_t)n, kin, st));
+  HIPCHK(hipMemcpyAsync(d_s, uniform, sizeof(double) * (size_t)n, kin, st));
+  hipLaunchKernelGGL(k_lp_fixing, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, (const double *)d_x,
+                     (const double *)d_l, (const double *)d_u, (const uint8_t *)d_vt, (const double *)d_s, d_out);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(value, d_out, sizeof(double) * (size_t)n, kout, st));
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+}  // namespace fix
+}  // namespace pdlp
+
+extern "C" {
+
+int pdlp_variable_strategy(pdlp_problem *p, int32_t strategy, int32_t tiebreak, const uint8_t *var_type,
+                           const double *x, const double *y, const double *red_cost, int32_t *order,
+                           int32_t *count) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    p->s.visit([&](auto &s) { pdlp::fix::variable_strategy(s, strategy, tiebreak, var_type, x, y, red_cost, order, count); });
+  });
+}
+
+int pdlp_lp_fixing(pdlp_problem *p, const uint8_t *var_type, const double *x, const double *l, const double *u,
+                   const double *uniform, double *value) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { pdlp::fix::lp_fixing(s, var_type, x, l, u, uniform, value); }); });
+}
+
+}  // extern "C"

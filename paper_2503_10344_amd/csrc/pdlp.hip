@@ -1312,3 +1312,4 @@ void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }
 }  // extern "C"
 
 #include "gnn_host.h"
+#include "fix_host.h"

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libpdlp.so")
 FP32, FP64 = 0, 1
 STATUS = {0: "none", 1: "optimal", 2: "iteration_limit", 3: "numerical"}
 OPTIMAL, ITER_LIMIT, NUMERICAL = 1, 2, 3
+VAR_CONTINUOUS, VAR_BINARY, VAR_INTEGER = 0, 1, 2
+ORDER_NONE, ORDER_FRAC, ORDER_REDCOST, ORDER_DUAL, ORDER_TYPE = 0, 1, 2, 3, 4
 ERR = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_CSR", -3: "PDLP_ERR_OOM", -4: "PDLP_ERR_HIP", -5: "PDLP_ERR_STATE"}
 
 
@@ -59,7 +61,8 @@ class ProblemDesc(C.Structure):
 EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_spmv",
            "pdlp_get_scaling", "pdlp_get_internal", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
-           "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy"]
+           "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy", "pdlp_variable_strategy",
+           "pdlp_lp_fixing"]
 
 _lib = None
 
@@ -141,6 +144,11 @@ def load(path: str = LIB_PATH):
     lib.pdlp_gnn_set_omega_weight.restype = C.c_int
     lib.pdlp_gnn_destroy.argtypes = [vp]
     lib.pdlp_gnn_destroy.restype = None
+    # LP-based variable strategies and fixing
+    lib.pdlp_variable_strategy.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, C.POINTER(i32)]
+    lib.pdlp_variable_strategy.restype = C.c_int
+    lib.pdlp_lp_fixing.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.pdlp_lp_fixing.restype = C.c_int
     _lib = lib
     return lib
 
@@ -290,6 +298,25 @@ class Problem:
 
     def device_bytes(self) -> int:
         return int(load().pdlp_device_bytes(self.h))
+
+    def variable_strategy(self, strategy, var_type, x=None, y=None, rc=None, tiebreak=ORDER_NONE) -> np.ndarray:
+        """Indices of the binary and integer variables in fixing order (see include/pdlp_fix.h)."""
+        vt = np.ascontiguousarray(var_type, np.uint8)
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (x, y, rc)]
+        order = np.zeros(max(self.n, 1), np.int32)
+        cnt = C.c_int32()
+        _check(load().pdlp_variable_strategy(self.h, int(strategy), int(tiebreak), _ptr(vt),
+                                             *[None if a is None else _ptr(a) for a in arrs], _ptr(order),
+                                             C.byref(cnt)))
+        return order[:cnt.value].copy()
+
+    def lp_fixing(self, var_type, x, l, u, uniform) -> np.ndarray:
+        """Fixing value of every variable under LP-based fixing (continuous ones keep x)."""
+        a = [np.ascontiguousarray(v, np.float64) for v in (x, l, u, uniform)]
+        vt = np.ascontiguousarray(var_type, np.uint8)
+        out = np.zeros(self.n)
+        _check(load().pdlp_lp_fixing(self.h, _ptr(vt), *[_ptr(v) for v in a], _ptr(out)))
+        return out
 
     def close(self):
         if getattr(self, "h", None):

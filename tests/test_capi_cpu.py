@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pdlp.h")
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("pdlp.h", "pdlp_gnn.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pdlp.h", "pdlp_gnn.h", "pdlp_fix.h")]
 
 
 @pytest.fixture(scope="module")
@@ -150,6 +150,9 @@ def test_null_arguments(lib):
     assert lib.pdlp_solve(None, 1e-4, 10, None, None, 0.0) == -1
     assert lib.pdlp_get(None, None, None, None, None) == -1
     assert lib.pdlp_batch_get_schedule(None, None, None, None) == -1
+    cnt = C.c_int32()
+    assert lib.pdlp_variable_strategy(None, 1, 0, None, None, None, None, None, C.byref(cnt)) == -1
+    assert lib.pdlp_lp_fixing(None, None, None, None, None, None, None) == -1
     assert lib.pdlp_error_string(-2) == b"malformed CSR matrix"
 
 
