@@ -97,7 +97,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="zipf", choices=["zipf", "setcover", "energy", "batch"])
+    ap.add_argument("--workload", default="zipf", choices=["zipf", "setcover", "energy", "batch", "fixing"])
+    ap.add_argument("--fixing-lp", default="zipf", choices=["zipf", "energy"],
+                    help="with --workload fixing: the LP whose size the variable strategies run at")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--iter-limit", type=int, default=500_000)
@@ -126,6 +128,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "fixing":
+        return bench_fixing(args)
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -332,6 +336,74 @@ def bench_batch(args):
            "iterations_median": statistics.median(it), "sequential_s": round(seq, 3),
            "speedup_vs_sequential": round(seq / sec, 2), "create_s": round(create_s, 2)}
     print(json.dumps(out), flush=True)
+
+
+def bench_fixing(args):
+    """LP-based variable strategies and LP-based fixing at the size of a full LP: time per call with
+    the inputs resident in HBM (GPU tensors in and out: the figure reported as value), the same
+    calls with host arrays (PCIe included), and the oracle (numpy) on the same inputs."""
+    import numpy as np
+    import torch
+    from paper_2503_10344_amd import generators as g
+    from paper_2503_10344_amd import pdlp
+    import oracle.fix_oracle as fo
+    torch.cuda.set_device(0)
+    lp, desc = make_workload(args.fixing_lp, args.seed)
+    d = g.fixing_inputs(args.seed, lp)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in d.items()}
+    dl, du = torch.from_numpy(lp.l).cuda(), torch.from_numpy(lp.u).cuda()
+    k = int(np.sum(d["var_type"] != 0))
+    log(f"{desc}; {k} binary / integer variables (seeded types, point, duals, reduced costs)")
+    combos = {"frac": (pdlp.ORDER_FRAC, pdlp.ORDER_NONE), "redcost": (pdlp.ORDER_REDCOST, pdlp.ORDER_NONE),
+              "dual": (pdlp.ORDER_DUAL, pdlp.ORDER_NONE), "type": (pdlp.ORDER_TYPE, pdlp.ORDER_NONE),
+              "frac+dual": (pdlp.ORDER_FRAC, pdlp.ORDER_DUAL), "frac+redcost": (pdlp.ORDER_FRAC, pdlp.ORDER_REDCOST)}
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        ts, res = [], None
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return 1e3 * statistics.median(ts), res
+
+    out = {}
+    p = pdlp.Problem(lp, precision="fp32")
+    for name, (s_, t_) in combos.items():
+        ms_dev, got_dev = timed(lambda: p.variable_strategy(s_, dev["var_type"], x=dev["x"], y=dev["y"],
+                                                            rc=dev["rc"], tiebreak=t_))
+        ms_host, got = timed(lambda: p.variable_strategy(s_, d["var_type"], x=d["x"], y=d["y"], rc=d["rc"],
+                                                         tiebreak=t_))
+        t0 = time.perf_counter()
+        want = fo.variable_order(s_, t_, d["x"], d["y"], d["rc"], d["var_type"], lp.m, lp.n, lp.row_ptr, lp.col)
+        cpu = time.perf_counter() - t0
+        out[name] = {"ms": round(ms_dev, 3), "ms_host_arrays": round(ms_host, 3), "oracle_ms": round(1e3 * cpu, 1),
+                     "equal_to_oracle": bool(np.array_equal(got, want) and np.array_equal(got_dev.cpu().numpy(), want))}
+        log(f"{name}: {json.dumps(out[name])}")
+    ms_dev, vals_dev = timed(lambda: p.lp_fixing(dev["var_type"], dev["x"], dl, du, dev["uniform"]))
+    ms_host, vals = timed(lambda: p.lp_fixing(d["var_type"], d["x"], lp.l, lp.u, d["uniform"]))
+    t0 = time.perf_counter()
+    want = fo.lp_fixing(d["x"], d["var_type"], d["uniform"], lp.l, lp.u)
+    fix = {"ms": round(ms_dev, 3), "ms_host_arrays": round(ms_host, 3),
+           "oracle_ms": round(1e3 * (time.perf_counter() - t0), 1),
+           "equal_to_oracle": bool(np.array_equal(vals, want) and np.array_equal(vals_dev.cpu().numpy(), want))}
+    log(f"lp_fixing: {json.dumps(fix)}")
+    p.close()
+    res = {"metric": "LP-based variable strategy (Frac, ties by Dual) + LP-based fixing, time per call",
+           "value": round(out["frac+dual"]["ms"] + fix["ms"], 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(out["frac+dual"]["ms"] + fix["ms"], 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 keys, int32 indices", "data": "synthetic",
+           "config": {"workload": f"{desc}; {k} binary/integer variables",
+                      "inputs": "resident in HBM (GPU tensors); ms_host_arrays: host arrays, PCIe included"},
+           "orders": out, "lp_fixing": fix,
+           "cpu_baseline": {"value": round(out["frac+dual"]["oracle_ms"] + fix["oracle_ms"], 1), "unit": "ms",
+                            "cores": 1, "kind": "oracle",
+                            "sample": "numpy oracle (lexsort, one thread) on the same inputs, one call each"}}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -21,10 +21,12 @@
  * x_j. The samples are the caller's (any uniform source), so a run is reproducible.
  *
  * Conventions as in pdlp.h: return 0 or a negative PDLP_ERR_* code; vectors are in the caller's
- * numbering; pointers are host pointers, or device pointers when the handle was created with
- * pdlp_options.device_ptrs (then inputs are not checked and must be finite). Work runs on the
- * handle's stream and each call returns after it finished; results are bitwise reproducible (integer
- * work and comparisons only, no rounding).
+ * numbering. Each pointer may be host memory or device memory on the handle's GPU (told apart with
+ * hipPointerGetAttributes): device inputs are read in place and are not checked (they must be
+ * finite), device outputs are written in place, so a caller with resident data moves nothing over
+ * PCIe. Device workspace is kept in the handle between calls (grown on demand, counted against
+ * device_mem_limit, freed by pdlp_destroy). Work runs on the handle's stream and each call returns
+ * after it finished; results are bitwise reproducible (integer work and comparisons, no rounding).
  */
 #ifndef PDLP_FIX_H
 #define PDLP_FIX_H

@@ -17,21 +17,55 @@ static int fix_grid(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
 }
 
-// Device buffers of one call, released when it returns.
+// Device buffers kept in the handle between calls (fix-and-propagate asks for orders repeatedly):
+// slot i grows when a call needs more, and the arena frees everything with the handle.
+struct Cache {
+  std::vector<std::pair<void *, int64_t>> slot;
+};
 struct Work {
   Arena &mem;
-  std::vector<void *> held;
-  explicit Work(Arena &a) : mem(a) {}
+  Cache &c;
+  int next = 0;
+  Work(Arena &a, Cache &cache) : mem(a), c(cache) {}
   template <typename U>
   U *get(int64_t count) {
-    U *p = mem.alloc<U>(count);
-    held.push_back(p);
-    return p;
-  }
-  ~Work() {
-    for (void *p : held) mem.release(p);
+    const int64_t bytes = std::max<int64_t>(count, 1) * (int64_t)sizeof(U);
+    if ((int)c.slot.size() <= next) c.slot.push_back({nullptr, 0});
+    auto &e = c.slot[next++];
+    if (e.second < bytes) {
+      if (e.first) mem.release(e.first);
+      e.first = nullptr, e.second = 0;
+      e.first = mem.alloc<uint8_t>(bytes);
+      e.second = bytes;
+    }
+    return static_cast<U *>(e.first);
   }
 };
+template <typename T>
+Cache &cache_of(Solver<T> &s) {
+  if (!s.fix_cache) s.fix_cache = std::make_shared<Cache>();
+  return *static_cast<Cache *>(s.fix_cache.get());
+}
+
+// True for device (or managed) memory, false for ordinary host memory.
+static bool on_device(const void *p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// A device pointer to `count` values of `src`: src itself when it is device memory, else a copy.
+template <typename U>
+const U *device_input(Work &w, const U *src, int64_t count, hipStream_t st) {
+  U *buf = w.get<U>(count);  // taken in both cases so the slot numbering does not depend on it
+  if (!src || count == 0) return buf;
+  if (on_device(src)) return src;
+  HIPCHK(hipMemcpyAsync(buf, src, sizeof(U) * (size_t)count, hipMemcpyHostToDevice, st));
+  return buf;
+}
 
 // Stable LSD radix sort of (keys, vals) of n items by the low `digits` bytes of the keys. Buffers
 // ping-pong between (k0, v0) and (k1, v1); on return (k0, v0) hold the result.
@@ -73,6 +107,12 @@ static void strategy_keys(int s, std::vector<int> &keys) {
   }
 }
 
+static bool finite_host(const double *v, int64_t len) {
+  for (int64_t i = 0; i < len; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
 template <typename T>
 void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *var_type, const double *x,
                        const double *y, const double *rc, int32_t *order, int32_t *count) {
@@ -88,70 +128,68 @@ void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *
   if (!var_type || !order || !count || (need_x && !x) || (need_rc && !rc) || (need_y && !y))
     raise(PDLP_ERR_ARG, "NULL argument that the strategy needs");
   const int n = s.n, m = s.m;
-  const bool dev = s.opt.device_ptrs != 0;
-  if (!dev) {  // host inputs are checked here; device inputs must be finite
-    auto finite = [](const double *v, int len) {
-      for (int i = 0; i < len; ++i)
-        if (!std::isfinite(v[i])) return false;
-      return true;
-    };
-    if ((need_x && !finite(x, n)) || (need_rc && !finite(rc, n)) || (need_y && !finite(y, m)))
-      raise(PDLP_ERR_ARG, "x, y and red_cost must be finite");
-  }
+  // host inputs are checked here; device inputs must be finite
+  if ((need_x && !on_device(x) && !finite_host(x, n)) || (need_rc && !on_device(rc) && !finite_host(rc, n)) ||
+      (need_y && !on_device(y) && !finite_host(y, m)))
+    raise(PDLP_ERR_ARG, "x, y and red_cost must be finite");
   hipStream_t st = s.stream;
-  const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  const hipMemcpyKind kout = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  Work w(s.mem);
+  Work w(s.mem, cache_of(s));
   const int64_t big = std::max<int64_t>(std::max(n, m), 1);
-  uint8_t *d_vt = w.get<uint8_t>(n);
-  double *d_x = need_x ? w.get<double>(n) : nullptr;
-  double *d_rc = need_rc ? w.get<double>(n) : nullptr;
-  double *d_y = need_y ? w.get<double>(m) : nullptr;
-  if (n) HIPCHK(hipMemcpyAsync(d_vt, var_type, (size_t)n, kin, st));
-  if (d_x && n) HIPCHK(hipMemcpyAsync(d_x, x, sizeof(double) * (size_t)n, kin, st));
-  if (d_rc && n) HIPCHK(hipMemcpyAsync(d_rc, rc, sizeof(double) * (size_t)n, kin, st));
-  if (d_y && m) HIPCHK(hipMemcpyAsync(d_y, y, sizeof(double) * (size_t)m, kin, st));
+  const uint8_t *d_vt = device_input(w, var_type, n, st);
+  const double *d_x = device_input(w, need_x ? x : nullptr, need_x ? n : 0, st);
+  const double *d_rc = device_input(w, need_rc ? rc : nullptr, need_rc ? n : 0, st);
+  const double *d_y = device_input(w, need_y ? y : nullptr, need_y ? m : 0, st);
   uint32_t *k0 = w.get<uint32_t>(big), *k1 = w.get<uint32_t>(big);
   int32_t *v0 = w.get<int32_t>(big), *v1 = w.get<int32_t>(big);
   const int64_t max_tiles = (big + kSortTile - 1) / kSortTile;
+  const int64_t scan_len = std::max<int64_t>((int64_t)kDigits * max_tiles, big);
   RadixSort rs{st};
   rs.counts = w.get<int32_t>((int64_t)kDigits * max_tiles);
-  rs.offs = w.get<int32_t>(std::max<int64_t>((int64_t)kDigits * max_tiles, big));
-  rs.tsum = w.get<int32_t>(((std::max<int64_t>((int64_t)kDigits * max_tiles, big)) + kScanTile - 1) / kScanTile + 1);
+  rs.offs = w.get<int32_t>(scan_len);
+  rs.tsum = w.get<int32_t>((scan_len + kScanTile - 1) / kScanTile + 1);
+  uint32_t *d_group = w.get<uint32_t>(need_y ? n : 0);
+  int32_t *R0 = w.get<int32_t>(need_y ? m : 0), *R1 = w.get<int32_t>(need_y ? m : 0);
+  int32_t *rank = w.get<int32_t>(need_y ? m : 0);
+  int32_t *tail = w.get<int32_t>(2);
 
   // binary and integer variables, in index order
   int32_t k = 0;
   if (n) {
-    hipLaunchKernelGGL(k_int_flags, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, (const uint8_t *)d_vt, v1);
+    hipLaunchKernelGGL(k_int_flags, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, d_vt, v1);
     rs.scan(n, v1, rs.offs);
-    hipLaunchKernelGGL(k_int_compact, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, (const uint8_t *)d_vt,
-                       (const int32_t *)rs.offs, v0);
-    int32_t tail[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(&tail[0], rs.offs + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&tail[1], v1 + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_int_compact, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, d_vt, (const int32_t *)rs.offs,
+                       v0);
+    int32_t h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(tail, rs.offs + (n - 1), sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(tail + 1, v1 + (n - 1), sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(h, tail, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    k = tail[0] + tail[1];
+    k = h[0] + h[1];
   }
 
   // Dual: rank of each constraint in descending |y| (ties: lower index), then each variable's group
-  uint32_t *d_group = nullptr;
-  if (need_y && k > 0) {
-    d_group = w.get<uint32_t>(n);
-    int32_t *R0 = w.get<int32_t>(std::max(m, 1)), *R1 = w.get<int32_t>(std::max(m, 1));
-    int32_t *rank = w.get<int32_t>(std::max(m, 1));
+  if (need_y && k > 1) {
     if (m > 0) {
       hipLaunchKernelGGL(k_iota, dim3(fix_grid(m)), dim3(kSortBlock), 0, st, m, R0);
       for (int word = 0; word < 2; ++word) {
         hipLaunchKernelGGL(k_fix_key, dim3(fix_grid(m)), dim3(kSortBlock), 0, st, m, (const int32_t *)R0,
-                           (int)kKeyRowDual, word, (const double *)nullptr, (const double *)nullptr,
-                           (const double *)d_y, (const uint8_t *)nullptr, (const uint32_t *)nullptr, k0);
+                           (int)kKeyRowDual, word, (const double *)nullptr, (const double *)nullptr, d_y,
+                           (const uint8_t *)nullptr, (const uint32_t *)nullptr, k0);
         rs.sort(m, 4, k0, R0, k1, R1);
       }
       hipLaunchKernelGGL(k_rank, dim3(fix_grid(m)), dim3(kSortBlock), 0, st, m, (const int32_t *)R0, rank);
     }
-    hipLaunchKernelGGL(k_dual_group, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, m, (const int32_t *)s.t_rp,
-                       (const int32_t *)s.t_ci, (const int32_t *)s.d_perm_r, (const int32_t *)s.d_perm_c,
-                       (const uint8_t *)d_vt, (const int32_t *)rank, d_group);
+    // internal columns are sorted by descending length class: the long ones form a prefix
+    int nlong = 0;
+    while (nlong < n && s.h_trp[nlong + 1] - s.h_trp[nlong] >= kLongColumn) ++nlong;
+    if (nlong > 0)
+      hipLaunchKernelGGL(k_dual_group_long, dim3(fix_grid((int64_t)nlong * 64)), dim3(kSortBlock), 0, st, nlong, m,
+                         (const int32_t *)s.t_rp, (const int32_t *)s.t_ci, (const int32_t *)s.d_perm_r,
+                         (const int32_t *)s.d_perm_c, d_vt, (const int32_t *)rank, d_group);
+    if (nlong < n)
+      hipLaunchKernelGGL(k_dual_group, dim3(fix_grid(n - nlong)), dim3(kSortBlock), 0, st, nlong, n, m,
+                         (const int32_t *)s.t_rp, (const int32_t *)s.t_ci, (const int32_t *)s.d_perm_r,
+                         (const int32_t *)s.d_perm_c, d_vt, (const int32_t *)rank, d_group);
   }
 
   // stable sorts, least significant key first
@@ -162,13 +200,12 @@ void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *
     const int digits = wide ? 4 : kind == kKeyGroup ? group_digits : 1;
     for (int word = 0; word < (wide ? 2 : 1); ++word) {
       hipLaunchKernelGGL(k_fix_key, dim3(fix_grid(k)), dim3(kSortBlock), 0, st, k, (const int32_t *)v0, kind, word,
-                         (const double *)d_x, (const double *)d_rc, (const double *)nullptr,
-                         (const uint8_t *)d_vt, (const uint32_t *)d_group, k0);
+                         d_x, d_rc, (const double *)nullptr, d_vt, (const uint32_t *)d_group, k0);
       rs.sort(k, digits, k0, v0, k1, v1);
     }
   }
   HIPCHK(hipGetLastError());
-  if (k > 0) HIPCHK(hipMemcpyAsync(order, v0, sizeof(int32_t) * (size_t)k, kout, st));
+  if (k > 0) HIPCHK(hipMemcpyAsync(order, v0, sizeof(int32_t) * (size_t)k, hipMemcpyDefault, st));
   HIPCHK(hipStreamSynchronize(st));
   *count = k;
 }
@@ -179,29 +216,24 @@ void lp_fixing(Solver<T> &s, const uint8_t *var_type, const double *x, const dou
   if (!var_type || !x || !l || !u || !uniform || !value) raise(PDLP_ERR_ARG, "NULL argument to pdlp_lp_fixing");
   if (s.K != 1) raise(PDLP_ERR_ARG, "LP-based fixing takes a single-problem handle");
   const int n = s.n;
-  const bool dev = s.opt.device_ptrs != 0;
-  if (!dev) {
+  if (!on_device(x) && !finite_host(x, n)) raise(PDLP_ERR_ARG, "x must be finite");
+  for (const double *b : {l, u})
+    if (!on_device(b))
+      for (int j = 0; j < n; ++j)
+        if (std::isnan(b[j])) raise(PDLP_ERR_ARG, "bounds must not be NaN");
+  if (!on_device(uniform))
     for (int j = 0; j < n; ++j)
-      if (!std::isfinite(x[j]) || std::isnan(l[j]) || std::isnan(u[j]) || !(uniform[j] > 0.0 && uniform[j] < 1.0))
-        raise(PDLP_ERR_ARG, "x must be finite, bounds not NaN and samples in (0, 1)");
-  }
+      if (!(uniform[j] > 0.0 && uniform[j] < 1.0)) raise(PDLP_ERR_ARG, "samples must lie in (0, 1)");
   if (n == 0) return;
   hipStream_t st = s.stream;
-  const hipMemcpyKind kin = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  const hipMemcpyKind kout = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  Work w(s.mem);
-  uint8_t *d_vt = w.get<uint8_t>(n);
-  double *d_x = w.get<double>(n), *d_l = w.get<double>(n), *d_u = w.get<double>(n), *d_s = w.get<double>(n);
-  double *d_out = w.get<double>(n);
-  HIPCHK(hipMemcpyAsync(d_vt, var_type, (size_t)n, kin, st));
-  HIPCHK(hipMemcpyAsync(d_x, x, sizeof(double) * (size_t)n, kin, st));
-  HIPCHK(hipMemcpyAsync(d_l, l, sizeof(double) * (size_t)n, kin, st));
-  HIPCHK(hipMemcpyAsync(d_u, u, sizeof(double) * (size_t)n, kin, st));
-  HIPCHK(hipMemcpyAsync(d_s, uniform, sizeof(double) * (size_t)n, kin, st));
-  hipLaunchKernelGGL(k_lp_fixing, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, (const double *)d_x,
-                     (const double *)d_l, (const double *)d_u, (const uint8_t *)d_vt, (const double *)d_s, d_out);
+  Work w(s.mem, cache_of(s));
+  const uint8_t *d_vt = device_input(w, var_type, n, st);
+  const double *d_x = device_input(w, x, n, st), *d_l = device_input(w, l, n, st);
+  const double *d_u = device_input(w, u, n, st), *d_s = device_input(w, uniform, n, st);
+  double *d_out = on_device(value) ? value : w.get<double>(n);
+  hipLaunchKernelGGL(k_lp_fixing, dim3(fix_grid(n)), dim3(kSortBlock), 0, st, n, d_x, d_l, d_u, d_vt, d_s, d_out);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(value, d_out, sizeof(double) * (size_t)n, kout, st));
+  if (d_out != value) HIPCHK(hipMemcpyAsync(value, d_out, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
 }
 

@@ -80,25 +80,35 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(int n, const uint32_t
 
 // Stable scatter of one digit. offs = exclusive scan of the digit-major counts (the first output slot
 // of each (digit, tile)). Within a round, items of a wave with equal digits are ranked by lane with
-// eight ballots; waves follow in order, rounds follow in order, so the tile's order is kept.
+// eight ballots; waves follow in order, rounds follow in order, so the tile's order is kept. All of
+// the tile's keys are loaded up front (one memory latency, not one per round), and the per-wave digit
+// counts alternate between two buffers so that a round needs two barriers.
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(int n, int shift, int nb,
                                                               const uint32_t *__restrict__ kin,
                                                               const int32_t *__restrict__ vin,
                                                               const int32_t *__restrict__ offs,
                                                               uint32_t *__restrict__ kout, int32_t *__restrict__ vout) {
   __shared__ int32_t run[kDigits];
-  __shared__ int32_t wcnt[kSortWaves][kDigits];
+  __shared__ int32_t wcnt[2][kSortWaves][kDigits];
   const int t = (int)threadIdx.x, lane = t & 63, w = t >> 6;
-  run[t] = offs[(int64_t)t * nb + blockIdx.x];
   const int64_t t0 = (int64_t)blockIdx.x * kSortTile;
+  uint32_t kr[kSortRounds];
+  int32_t vr[kSortRounds];
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
-    for (int i = t; i < kSortWaves * kDigits; i += kSortBlock) (&wcnt[0][0])[i] = 0;
-    __syncthreads();
     const int64_t p = t0 + (int64_t)r * kSortBlock + t;
-    const bool valid = p < n;
-    const uint32_t key = valid ? kin[p] : 0u;
-    const int32_t val = valid ? vin[p] : 0;
-    const int dig = (int)((key >> shift) & 255u);
+    kr[r] = p < n ? kin[p] : 0u;
+    vr[r] = p < n ? vin[p] : 0;
+  }
+  run[t] = offs[(int64_t)t * nb + blockIdx.x];
+#pragma unroll
+  for (int v = 0; v < kSortWaves; ++v) wcnt[0][v][t] = 0, wcnt[1][v][t] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    int32_t(*cnt)[kDigits] = wcnt[r & 1];
+    const bool valid = t0 + (int64_t)r * kSortBlock + t < n;
+    const int dig = (int)((kr[r] >> shift) & 255u);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -107,23 +117,22 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(int n, int shift, 
       peers &= bit ? ones : ~ones;
     }
     const int rank = __popcll(peers & ((1ull << lane) - 1ull));
-    if (valid && rank == 0) wcnt[w][dig] = __popcll(peers);
-    __syncthreads();
+    if (valid && rank == 0) cnt[w][dig] = __popcll(peers);
+    __syncthreads();  // this round's counts are complete; run[] holds the previous rounds
     if (valid) {
       int before = 0;
-      for (int v = 0; v < w; ++v) before += wcnt[v][dig];
+      for (int v = 0; v < w; ++v) before += cnt[v][dig];
       const int64_t dst = (int64_t)run[dig] + before + rank;
       if (dst < n) {
-        kout[dst] = key;
-        vout[dst] = val;
+        kout[dst] = kr[r];
+        vout[dst] = vr[r];
       }
     }
-    __syncthreads();
+    __syncthreads();  // every read of run[] and of this round's counts is done
     int add = 0;
 #pragma unroll
-    for (int v = 0; v < kSortWaves; ++v) add += wcnt[v][t];
-    run[t] += add;
-    __syncthreads();
+    for (int v = 0; v < kSortWaves; ++v) add += cnt[v][t], cnt[v][t] = 0;
+    run[t] += add;  // read by others only after the next round's first barrier
   }
 }
 
@@ -219,15 +228,40 @@ __global__ __launch_bounds__(kSortBlock) void k_rank(int m, const int32_t *__res
 }
 
 // Dual grouping over the stored transpose (internal numbering): a binary or integer variable's group
-// is the smallest rank of a constraint holding it, m when its column is empty.
-__global__ __launch_bounds__(kSortBlock) void k_dual_group(int n, int m, const int32_t *__restrict__ t_rp,
+// is the smallest rank of a constraint holding it, m when its column is empty. Long columns (the
+// first internal columns: columns are sorted by descending length class) take one wave each, the
+// rest one thread each; the minimum does not depend on the order it is taken in.
+constexpr int kLongColumn = 32;
+__global__ __launch_bounds__(kSortBlock) void k_dual_group_long(int ncols, int m, const int32_t *__restrict__ t_rp,
+                                                                const int32_t *__restrict__ t_ci,
+                                                                const int32_t *__restrict__ perm_r,
+                                                                const int32_t *__restrict__ perm_c,
+                                                                const uint8_t *__restrict__ vt,
+                                                                const int32_t *__restrict__ rank,
+                                                                uint32_t *__restrict__ group) {
+  const int lane = (int)threadIdx.x & 63;
+  const int64_t wave0 = ((int64_t)blockIdx.x * kSortBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kSortBlock) >> 6;
+  for (int64_t jj = wave0; jj < ncols; jj += nwaves) {
+    const int32_t j = perm_c[jj];
+    if (!vt[j]) continue;  // uniform over the wave
+    int32_t g = m;
+    for (int32_t e = t_rp[jj] + lane; e < t_rp[jj + 1]; e += 64) g = min(g, rank[perm_r[t_ci[e]]]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) g = min(g, __shfl_xor(g, o, 64));
+    if (lane == 0) group[j] = (uint32_t)g;
+  }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_dual_group(int first, int n, int m, const int32_t *__restrict__ t_rp,
                                                            const int32_t *__restrict__ t_ci,
                                                            const int32_t *__restrict__ perm_r,
                                                            const int32_t *__restrict__ perm_c,
                                                            const uint8_t *__restrict__ vt,
                                                            const int32_t *__restrict__ rank,
                                                            uint32_t *__restrict__ group) {
-  for (int64_t jj = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; jj < n; jj += (int64_t)gridDim.x * kSortBlock) {
+  for (int64_t jj = (int64_t)first + (int64_t)blockIdx.x * kSortBlock + threadIdx.x; jj < n;
+       jj += (int64_t)gridDim.x * kSortBlock) {
     const int32_t j = perm_c[jj];
     if (!vt[j]) continue;
     int32_t g = m;

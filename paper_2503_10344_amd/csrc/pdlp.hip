@@ -240,6 +240,7 @@ struct Solver {
   int64_t t_launches[2] = {0, 0};
   double t_ms[2] = {0.0, 0.0};
   Iter<T> P{};
+  std::shared_ptr<void> fix_cache;  // workspace of the LP-based variable strategies, kept between calls
   bool solved = false;
   std::vector<pdlp_result> last;
 

@@ -159,6 +159,22 @@ def _check(rc: int):
         raise PDLPError(rc, lib.pdlp_last_error().decode())
 
 
+def _torch():
+    import torch
+    return torch
+
+
+def _is_cuda(a):
+    return getattr(a, "is_cuda", False)
+
+
+def _dptr(a):
+    """Device pointer of a contiguous GPU torch tensor."""
+    if not (_is_cuda(a) and a.is_contiguous()):
+        raise ValueError("expected a contiguous torch tensor on the GPU")
+    return C.c_void_p(a.data_ptr())
+
+
 def _ptr(a):
     """Pointer of a numpy array or a torch tensor (None stays None)."""
     if a is None:
@@ -299,23 +315,36 @@ class Problem:
     def device_bytes(self) -> int:
         return int(load().pdlp_device_bytes(self.h))
 
-    def variable_strategy(self, strategy, var_type, x=None, y=None, rc=None, tiebreak=ORDER_NONE) -> np.ndarray:
-        """Indices of the binary and integer variables in fixing order (see include/pdlp_fix.h)."""
-        vt = np.ascontiguousarray(var_type, np.uint8)
-        arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (x, y, rc)]
-        order = np.zeros(max(self.n, 1), np.int32)
+    def variable_strategy(self, strategy, var_type, x=None, y=None, rc=None, tiebreak=ORDER_NONE):
+        """Indices of the binary and integer variables in fixing order (see include/pdlp_fix.h).
+        Inputs are numpy arrays, or contiguous torch tensors on the GPU (uint8 types, float64 values):
+        then the result is a torch int32 tensor on the GPU and nothing crosses PCIe."""
+        if _is_cuda(var_type):
+            _torch().cuda.current_stream().synchronize()  # inputs written on torch's stream are complete
+            order = _torch().empty(max(self.n, 1), dtype=_torch().int32, device=var_type.device)
+            args = [_dptr(var_type)] + [None if a is None else _dptr(a) for a in (x, y, rc)] + [_dptr(order)]
+        else:
+            vt = np.ascontiguousarray(var_type, np.uint8)
+            arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (x, y, rc)]
+            order = np.zeros(max(self.n, 1), np.int32)
+            args = [_ptr(vt)] + [None if a is None else _ptr(a) for a in arrs] + [_ptr(order)]
         cnt = C.c_int32()
-        _check(load().pdlp_variable_strategy(self.h, int(strategy), int(tiebreak), _ptr(vt),
-                                             *[None if a is None else _ptr(a) for a in arrs], _ptr(order),
-                                             C.byref(cnt)))
-        return order[:cnt.value].copy()
+        _check(load().pdlp_variable_strategy(self.h, int(strategy), int(tiebreak), *args, C.byref(cnt)))
+        return order[:cnt.value].clone() if _is_cuda(order) else order[:cnt.value].copy()
 
-    def lp_fixing(self, var_type, x, l, u, uniform) -> np.ndarray:
-        """Fixing value of every variable under LP-based fixing (continuous ones keep x)."""
-        a = [np.ascontiguousarray(v, np.float64) for v in (x, l, u, uniform)]
-        vt = np.ascontiguousarray(var_type, np.uint8)
-        out = np.zeros(self.n)
-        _check(load().pdlp_lp_fixing(self.h, _ptr(vt), *[_ptr(v) for v in a], _ptr(out)))
+    def lp_fixing(self, var_type, x, l, u, uniform):
+        """Fixing value of every variable under LP-based fixing (continuous ones keep x); numpy
+        arrays in and out, or GPU torch tensors in and out."""
+        if _is_cuda(var_type):
+            _torch().cuda.current_stream().synchronize()
+            out = _torch().empty(self.n, dtype=_torch().float64, device=var_type.device)
+            args = [_dptr(v) for v in (var_type, x, l, u, uniform, out)]
+        else:
+            a = [np.ascontiguousarray(v, np.float64) for v in (x, l, u, uniform)]
+            vt = np.ascontiguousarray(var_type, np.uint8)
+            out = np.zeros(self.n)
+            args = [_ptr(vt)] + [_ptr(v) for v in a] + [_ptr(out)]
+        _check(load().pdlp_lp_fixing(self.h, *args))
         return out
 
     def close(self):

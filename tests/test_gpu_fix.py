@@ -103,6 +103,23 @@ def test_edge_cases(pdlp):
     assert np.array_equal(got, _oracle_order(box, db, fo.DUAL, fo.NONE))
 
 
+def test_device_resident_inputs_give_the_same_results(pdlp):
+    """GPU tensors in and out (no PCIe): the same order and values as the host path."""
+    import torch
+    lp = g.general_sparse(6, m=8000, n=20000, cap=300)
+    d = g.fixing_inputs(13, lp)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in d.items()}
+    lo, up = torch.from_numpy(lp.l).cuda(), torch.from_numpy(lp.u).cuda()
+    with pdlp.Problem(lp, precision="fp32") as p:
+        for s, t in ((fo.FRAC, fo.DUAL), (fo.DUAL, fo.NONE), (fo.TYPE, fo.REDCOST)):
+            host = p.variable_strategy(s, d["var_type"], x=d["x"], y=d["y"], rc=d["rc"], tiebreak=t)
+            on_gpu = p.variable_strategy(s, dev["var_type"], x=dev["x"], y=dev["y"], rc=dev["rc"], tiebreak=t)
+            assert on_gpu.is_cuda and np.array_equal(on_gpu.cpu().numpy(), host), (s, t)
+        vals = p.lp_fixing(dev["var_type"], dev["x"], lo, up, dev["uniform"])
+    assert vals.is_cuda
+    np.testing.assert_array_equal(vals.cpu().numpy(), fo.lp_fixing(d["x"], d["var_type"], d["uniform"], lp.l, lp.u))
+
+
 def test_order_of_a_solved_lp_is_sorted_by_its_keys(pdlp):
     """Chained on the device's own solution: the Frac order is a permutation of the binaries whose
     fractionality never decreases, ties in index order (a property, so no oracle input comes from
