@@ -12,6 +12,8 @@ follow the published PDLP method; every constant is a reading):
   scale     -- Ruiz inf-norm passes then one Pock-Chambolle alpha = 1 pass
   pdhg_step -- one PDHG step on an unscaled LP
   spmv, transpose -- plain CSR product and counting-sort transpose
+  propagate -- linear-constraint bound propagation in Jacobi rounds (prop_oracle.c; the paper uses
+               the framework's linear-constraint propagator without defining it: a reading)
 """
 from __future__ import annotations
 
@@ -204,3 +206,46 @@ def transpose(m: int, n: int, row_ptr, col, val, lib_path: str = LIB):
 
 def num_threads(lib_path: str = LIB) -> int:
     return int(load(lib_path).orc_num_threads())
+
+
+# ---- linear-constraint propagation (prop_oracle.c, a library of its own) ----
+PROP_SRC = os.path.join(_HERE, "prop_oracle.c")
+PROP_LIB = os.path.join(_HERE, "liboracle_prop.so")
+PROP_FIXPOINT, PROP_INFEASIBLE, PROP_ROUND_LIMIT = 0, 1, 2
+
+
+def build_prop(src: str = PROP_SRC, out: str = PROP_LIB) -> str:
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off", src, "-o", out, "-lm"],
+                   check=True)
+    return out
+
+
+def load_prop(path: str = PROP_LIB):
+    if path in _lib_cache:
+        return _lib_cache[path]
+    if path == PROP_LIB and (not os.path.exists(PROP_LIB) or os.path.getmtime(PROP_LIB) < os.path.getmtime(PROP_SRC)):
+        build_prop()
+    lib = C.CDLL(path)
+    lib.orc_propagate.restype = C.c_int
+    _lib_cache[path] = lib
+    return lib
+
+
+def propagate(lp, var_type, l, u, max_rounds: int = 100, lib_path: str = PROP_LIB):
+    """Bounds after linear-constraint propagation in Jacobi rounds (prop_oracle.c states the rule).
+    Returns (l, u, status, rounds)."""
+    lib = load_prop(lib_path)
+    rp = np.ascontiguousarray(lp.row_ptr, np.int32)
+    ci = np.ascontiguousarray(lp.col, np.int32)
+    v = np.ascontiguousarray(lp.val, np.float64)
+    b = np.ascontiguousarray(lp.b, np.float64)
+    sn = np.ascontiguousarray(lp.sense, np.uint8)
+    vt = np.ascontiguousarray(var_type, np.uint8)
+    lo = np.array(l, np.float64, copy=True)
+    hi = np.array(u, np.float64, copy=True)
+    rounds = C.c_int32()
+    st = lib.orc_propagate(C.c_int32(lp.m), C.c_int32(lp.n), _p(rp), _p(ci), _p(v), _p(b), _p(sn), _p(vt), _p(lo),
+                           _p(hi), C.c_int32(max_rounds), C.byref(rounds))
+    if st < 0:
+        raise MemoryError("oracle propagation failed to allocate")
+    return lo, hi, int(st), int(rounds.value)

@@ -90,3 +90,16 @@ def lp_fixing(x, var_type, uniform, l, u):
     a = np.where(np.asarray(uniform, np.float64) > d, lo, hi)
     a = np.clip(a, np.ceil(np.asarray(l, np.float64)), np.floor(np.asarray(u, np.float64)))
     return np.where(np.asarray(var_type) == CONTINUOUS, x, a)
+
+
+def branching(l, u, a, c):
+    """Bound changes (lower, upper) of the integer-aware branching rule (section 2, Alg. 1), in
+    increasing priority (the last is explored first). With the fixing value a strictly inside
+    [l, u]: the restriction away from the objective direction, the one towards it, then x = a
+    (c > 0 prefers smaller values). With a on a bound: the other bound, then a."""
+    if l < a < u:
+        up, down, fix = (a + 1, u), (l, a - 1), (a, a)
+        return [up, down, fix] if c > 0 else [down, up, fix]
+    if a == l:
+        return [(u, u), (l, l)]
+    return [(l, l), (u, u)]
