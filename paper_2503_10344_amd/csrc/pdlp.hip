@@ -1314,3 +1314,4 @@ void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }
 
 #include "gnn_host.h"
 #include "fix_host.h"
+#include "prop_host.h"

@@ -1,0 +1,165 @@
+// Device kernels of linear-constraint bound propagation (the propagator fix-and-propagate applies
+// after each fixing; section 2 of the paper names it without defining it, so this is the standard
+// activity-based bound strengthening, run in Jacobi rounds).
+//
+// One round: every row reads the bounds of the round's start (l, u), forms its minimum and maximum
+// activity in row order (finite part plus a count of infinite terms) and proposes, for each of its
+// variables, the bound the other terms leave room for; a bound takes the tightest accepted proposal
+// (atomic min / max on the bit pattern, so the result does not depend on the order rows finish in).
+// Integer variables round proposals inward within 1e-6 and take any strict gain; continuous ones
+// take a gain above 1e-3 max(1, |bound|). A second kernel then records whether a bound moved and
+// whether some lower bound passed its upper bound.
+//
+// Products and sums round separately: every function below switches floating-point contraction
+// off (HIP contracts a * b + c into a fused multiply-add by default, and that rounds once instead of
+// twice), so a row's activity is the same double as a plain sequential sum.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pdlp {
+namespace prop {
+
+constexpr int kPropBlock = 256;
+constexpr double kFeasTol = 1e-6;
+constexpr double kContTol = 1e-3;
+
+__device__ __forceinline__ void atomic_min_double(double *addr, double v) {
+  unsigned long long *a = reinterpret_cast<unsigned long long *>(addr);
+  unsigned long long old = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (v < __longlong_as_double((long long)old)) {
+    const unsigned long long seen = atomicCAS(a, old, (unsigned long long)__double_as_longlong(v));
+    if (seen == old) break;
+    old = seen;
+  }
+}
+__device__ __forceinline__ void atomic_max_double(double *addr, double v) {
+  unsigned long long *a = reinterpret_cast<unsigned long long *>(addr);
+  unsigned long long old = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (v > __longlong_as_double((long long)old)) {
+    const unsigned long long seen = atomicCAS(a, old, (unsigned long long)__double_as_longlong(v));
+    if (seen == old) break;
+    old = seen;
+  }
+}
+
+// New upper bound from a proposal p, or `cur` when it is not taken.
+__device__ __forceinline__ double tighten_upper(double cur, double p, bool integral) {
+#pragma clang fp contract(off)
+  if (integral) {
+    const double q = floor((p + kFeasTol));
+    return q < cur ? q : cur;
+  }
+  if (isinf(cur)) return isinf(p) ? cur : p;
+  return p < (cur - (kContTol * fmax(1.0, fabs(cur)))) ? p : cur;
+}
+__device__ __forceinline__ double tighten_lower(double cur, double p, bool integral) {
+#pragma clang fp contract(off)
+  if (integral) {
+    const double q = ceil((p - kFeasTol));
+    return q > cur ? q : cur;
+  }
+  if (isinf(cur)) return isinf(p) ? cur : p;
+  return p > (cur + (kContTol * fmax(1.0, fabs(cur)))) ? p : cur;
+}
+
+// flags[1] = 1 when a row cannot be satisfied within the bounds (finite activity past b by more than
+// 1e-6 max(1, |b|)).
+__global__ __launch_bounds__(kPropBlock) void k_prop_round(int m, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const double *__restrict__ val,
+                                                           const double *__restrict__ b,
+                                                           const uint8_t *__restrict__ sense,
+                                                           const uint8_t *__restrict__ vt,
+                                                           const double *__restrict__ l, const double *__restrict__ u,
+                                                           double *ln, double *un, int32_t *flags) {
+#pragma clang fp contract(off)
+  for (int64_t i = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kPropBlock) {
+    const int32_t k0 = rp[i], k1 = rp[i + 1];
+    double minf = 0.0, maxf = 0.0;
+    int mininf = 0, maxinf = 0;
+    for (int32_t k = k0; k < k1; ++k) {
+      const double a = val[k];
+      if (a == 0.0) continue;
+      const int32_t j = ci[k];
+      const double lo = l[j], hi = u[j];
+      const double tmin = a > 0.0 ? lo : hi, tmax = a > 0.0 ? hi : lo;
+      if (isinf(tmin)) ++mininf;
+      else minf = (minf + (a * tmin));
+      if (isinf(tmax)) ++maxinf;
+      else maxf = (maxf + (a * tmax));
+    }
+    const double bi = b[i];
+    const double tolb = (kFeasTol * fmax(1.0, fabs(bi)));
+    const uint8_t s = sense[i];
+    const bool le = s == 'L' || s == 'E', ge = s == 'G' || s == 'E';
+    if ((le && mininf == 0 && minf > (bi + tolb)) || (ge && maxinf == 0 && maxf < (bi - tolb)))
+      atomicOr(&flags[1], 1);
+    for (int32_t k = k0; k < k1; ++k) {
+      const double a = val[k];
+      if (a == 0.0) continue;
+      const int32_t j = ci[k];
+      const double lo = l[j], hi = u[j];
+      const bool integral = vt[j] != 0;
+      if (le) {
+        const double t = a > 0.0 ? lo : hi;
+        bool ok = true;
+        double res = 0.0;
+        if (mininf == 0) res = (minf - (a * t));
+        else if (mininf == 1 && isinf(t)) res = minf;
+        else ok = false;
+        if (ok) {
+          const double p = (bi - res) / a;
+          if (a > 0.0) {
+            const double q = tighten_upper(hi, p, integral);
+            if (q < hi) atomic_min_double(&un[j], q);
+          } else {
+            const double q = tighten_lower(lo, p, integral);
+            if (q > lo) atomic_max_double(&ln[j], q);
+          }
+        }
+      }
+      if (ge) {
+        const double t = a > 0.0 ? hi : lo;
+        bool ok = true;
+        double res = 0.0;
+        if (maxinf == 0) res = (maxf - (a * t));
+        else if (maxinf == 1 && isinf(t)) res = maxf;
+        else ok = false;
+        if (ok) {
+          const double p = (bi - res) / a;
+          if (a > 0.0) {
+            const double q = tighten_lower(lo, p, integral);
+            if (q > lo) atomic_max_double(&ln[j], q);
+          } else {
+            const double q = tighten_upper(hi, p, integral);
+            if (q < hi) atomic_min_double(&un[j], q);
+          }
+        }
+      }
+    }
+  }
+}
+
+// After a round: flags[0] = 1 if a bound moved, flags[2] = 1 if some l > u + 1e-6; then the round's
+// result becomes the current bounds (l, u = ln, un), so both copies agree for the next round.
+__global__ __launch_bounds__(kPropBlock) void k_prop_finish(int n, double *__restrict__ l, double *__restrict__ u,
+                                                            const double *__restrict__ ln,
+                                                            const double *__restrict__ un, int32_t *flags) {
+#pragma clang fp contract(off)
+  bool moved = false, crossed = false;
+  for (int64_t j = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kPropBlock) {
+    const double a = ln[j], c = un[j];
+    moved |= a != l[j] || c != u[j];
+    crossed |= a > (c + kFeasTol);
+    l[j] = a;
+    u[j] = c;
+  }
+  if (moved) atomicOr(&flags[0], 1);
+  if (crossed) atomicOr(&flags[2], 1);
+}
+
+}  // namespace prop
+}  // namespace pdlp

@@ -200,7 +200,7 @@ def general_sparse(seed: int, m: int = 500_000, n: int = 1_000_000, exponent: fl
     aty0 = A.T @ y0
     c = np.where(boxed, rng.standard_normal(n), aty0)
     return LP(m, n, rp, ci, vals, c, b, sense, lo, hi,
-              name=f"zipf[{seed}] {m}x{n}", meta={"exponent": exponent, "cap": cap})
+              name=f"zipf[{seed}] {m}x{n}", meta={"exponent": exponent, "cap": cap, "x0": x0})
 
 
 # ----------------------------------------------------------------------------------------------
@@ -365,3 +365,25 @@ def fixing_inputs(seed: int, lp: LP, int_share: float = 0.6, tie_share: float = 
     rc = np.where(rgrid, rng.choice([-1.0, 0.0, 0.0, 0.25, 1.0], n), rc)
     uniform = (rng.integers(0, 2**53, n, dtype=np.int64).astype(np.float64) + 0.5) * 2.0**-53
     return dict(var_type=vtype, x=x, y=y, rc=rc, uniform=uniform)
+
+
+def feasible_binary_point(seed: int, lp: LP) -> np.ndarray:
+    """A random 0/1 point satisfying every row of a set-cover (>= 1) or multi-knapsack (<=) LP: a
+    random cover (one random column of each row set to 1), or items added in random order while
+    every row stays within its capacity."""
+    rng = np.random.default_rng([17, seed])
+    x = np.zeros(lp.n)
+    if np.all(lp.sense == G_):
+        for i in rng.permutation(lp.m):
+            cols = lp.col[lp.row_ptr[i]:lp.row_ptr[i + 1]]
+            if not np.any(x[cols] > 0):
+                x[rng.choice(cols)] = 1.0
+        return x
+    At = lp.to_scipy().T.tocsr()
+    load = np.zeros(lp.m)
+    for j in rng.permutation(lp.n):
+        rows, a = At.indices[At.indptr[j]:At.indptr[j + 1]], At.data[At.indptr[j]:At.indptr[j + 1]]
+        if np.all(load[rows] + a <= lp.b[rows]):
+            load[rows] += a
+            x[j] = 1.0
+    return x

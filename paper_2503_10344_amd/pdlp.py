@@ -21,6 +21,7 @@ STATUS = {0: "none", 1: "optimal", 2: "iteration_limit", 3: "numerical"}
 OPTIMAL, ITER_LIMIT, NUMERICAL = 1, 2, 3
 VAR_CONTINUOUS, VAR_BINARY, VAR_INTEGER = 0, 1, 2
 ORDER_NONE, ORDER_FRAC, ORDER_REDCOST, ORDER_DUAL, ORDER_TYPE = 0, 1, 2, 3, 4
+PROP_FIXPOINT, PROP_INFEASIBLE, PROP_ROUND_LIMIT = 0, 1, 2
 ERR = {-1: "PDLP_ERR_ARG", -2: "PDLP_ERR_CSR", -3: "PDLP_ERR_OOM", -4: "PDLP_ERR_HIP", -5: "PDLP_ERR_STATE"}
 
 
@@ -62,7 +63,7 @@ EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdl
            "pdlp_get_scaling", "pdlp_get_internal", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
            "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy", "pdlp_variable_strategy",
-           "pdlp_lp_fixing"]
+           "pdlp_lp_fixing", "pdlp_prop_create", "pdlp_propagate", "pdlp_prop_destroy", "pdlp_branching"]
 
 _lib = None
 
@@ -149,6 +150,15 @@ def load(path: str = LIB_PATH):
     lib.pdlp_variable_strategy.restype = C.c_int
     lib.pdlp_lp_fixing.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.pdlp_lp_fixing.restype = C.c_int
+    # linear-constraint propagation and branching
+    lib.pdlp_prop_create.argtypes = [C.POINTER(vp), i32, i32, i64, vp, vp, vp, vp, vp, vp, C.POINTER(Options)]
+    lib.pdlp_prop_create.restype = C.c_int
+    lib.pdlp_propagate.argtypes = [vp, vp, vp, i32, C.POINTER(i32), C.POINTER(i32)]
+    lib.pdlp_propagate.restype = C.c_int
+    lib.pdlp_prop_destroy.argtypes = [vp]
+    lib.pdlp_prop_destroy.restype = None
+    lib.pdlp_branching.argtypes = [dp, dp, dp, dp, vp, vp, C.POINTER(i32)]
+    lib.pdlp_branching.restype = C.c_int
     _lib = lib
     return lib
 
@@ -566,3 +576,57 @@ class WarmStartNet:
             self.close()
         except Exception:
             pass
+
+
+class Propagator:
+    """Linear-constraint propagation over the rows of an LP / MIP (see include/pdlp_prop.h)."""
+
+    def __init__(self, lp, var_type, stream=None, device_mem_limit=0):
+        self.n = int(lp.n)
+        self.arr = _lp_arrays(lp)
+        self.vt = np.ascontiguousarray(var_type, np.uint8)
+        self.opt = options(stream=stream, device_mem_limit=device_mem_limit)
+        a = self.arr
+        h = C.c_void_p()
+        _check(load().pdlp_prop_create(C.byref(h), int(lp.m), self.n, int(a["row_ptr"][-1]), _ptr(a["row_ptr"]),
+                                       _ptr(a["col"]), _ptr(a["val"]), _ptr(a["b"]), _ptr(a["sense"]), _ptr(self.vt),
+                                       C.byref(self.opt)))
+        self.h = h
+
+    def propagate(self, l, u, max_rounds=100):
+        """Propagated copies of the bounds, the status (PROP_*) and the rounds run. numpy arrays, or
+        GPU torch float64 tensors (propagated in place and returned)."""
+        if _is_cuda(l):
+            _torch().cuda.current_stream().synchronize()
+            lo, hi, pl, pu = l, u, _dptr(l), _dptr(u)
+        else:
+            lo = np.array(l, np.float64, copy=True)
+            hi = np.array(u, np.float64, copy=True)
+            pl, pu = _ptr(lo), _ptr(hi)
+        r, st = C.c_int32(), C.c_int32()
+        _check(load().pdlp_propagate(self.h, pl, pu, int(max_rounds), C.byref(r), C.byref(st)))
+        return lo, hi, st.value, r.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pdlp_prop_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def branching(l, u, a, c):
+    """Bound changes of the integer-aware branching rule, in increasing priority: [(lower, upper), ...]."""
+    lo, hi, k = (C.c_double * 3)(), (C.c_double * 3)(), C.c_int32()
+    _check(load().pdlp_branching(float(l), float(u), float(a), float(c), lo, hi, C.byref(k)))
+    return [(lo[i], hi[i]) for i in range(k.value)]

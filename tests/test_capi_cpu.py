@@ -9,7 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pdlp.h")
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("pdlp.h", "pdlp_gnn.h", "pdlp_fix.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("pdlp.h", "pdlp_gnn.h", "pdlp_fix.h", "pdlp_prop.h")]
 
 
 @pytest.fixture(scope="module")
@@ -153,6 +153,22 @@ def test_null_arguments(lib):
     cnt = C.c_int32()
     assert lib.pdlp_variable_strategy(None, 1, 0, None, None, None, None, None, C.byref(cnt)) == -1
     assert lib.pdlp_lp_fixing(None, None, None, None, None, None, None) == -1
+    assert lib.pdlp_prop_create(None, 1, 1, 0, None, None, None, None, None, None, None) == -1
+    assert lib.pdlp_propagate(None, None, None, 10, None, None) == -1
+
+
+def test_branching_rule_matches_oracle(lib):
+    """pdlp_branching is host code: checked here against the oracle on every case of small domains."""
+    from oracle import fix_oracle as fo
+    from paper_2503_10344_amd import pdlp
+    for l in range(-2, 3):
+        for u in range(l, l + 4):
+            for a in range(l, u + 1):
+                for c in (-1.5, 0.0, 2.0):
+                    assert pdlp.branching(l, u, a, c) == fo.branching(l, u, a, c), (l, u, a, c)
+    for bad in ((0, 5, 6, 1.0), (0, 5, 2.5, 1.0), (0, 5, float("nan"), 1.0)):
+        with pytest.raises(pdlp.PDLPError):
+            pdlp.branching(*bad)
     assert lib.pdlp_error_string(-2) == b"malformed CSR matrix"
 
 
