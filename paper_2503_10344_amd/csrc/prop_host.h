@@ -16,6 +16,8 @@ struct pdlp_prop {
   int32_t m = 0, n = 0;
   int64_t nnz = 0;
   int32_t *rp = nullptr, *ci = nullptr;
+  int32_t *long_rows = nullptr;  // rows of at least kLongRow entries (one wave each)
+  int32_t nlong = 0;
   double *val = nullptr, *b = nullptr;
   uint8_t *sense = nullptr, *vt = nullptr;
   double *l = nullptr, *u = nullptr, *ln = nullptr, *un = nullptr;  // current and next bounds
@@ -87,6 +89,11 @@ int pdlp_prop_create(pdlp_prop **out, int32_t m, int32_t n, int64_t nnz, const i
     HIPCHK(hipHostMalloc((void **)&p->h_flags, 3 * sizeof(int32_t), hipHostMallocDefault));
     p->m = m, p->n = n, p->nnz = nnz;
     p->rp = pdlp::prop::upload_new(*p, H.rp);
+    std::vector<int32_t> lr;
+    for (int32_t i = 0; i < m; ++i)
+      if (H.rp[i + 1] - H.rp[i] >= pdlp::prop::kLongRow) lr.push_back(i);
+    p->nlong = (int32_t)lr.size();
+    p->long_rows = pdlp::prop::upload_new(*p, lr);
     p->ci = pdlp::prop::upload_new(*p, H.ci);
     p->val = pdlp::prop::upload_new(*p, H.val);
     p->b = pdlp::prop::upload_new(*p, H.b);
@@ -131,6 +138,12 @@ int pdlp_propagate(pdlp_prop *p, double *l, double *u, int32_t max_rounds, int32
                            (const int32_t *)p->ci, (const double *)p->val, (const double *)p->b,
                            (const uint8_t *)p->sense, (const uint8_t *)p->vt, (const double *)p->l,
                            (const double *)p->u, p->ln, p->un, p->flags);
+      if (p->nlong > 0)
+        hipLaunchKernelGGL(k_prop_round_long, dim3(prop_grid((int64_t)p->nlong * 64)), dim3(kPropBlock), 0, st,
+                           p->nlong, (const int32_t *)p->long_rows, (const int32_t *)p->rp, (const int32_t *)p->ci,
+                           (const double *)p->val, (const double *)p->b, (const uint8_t *)p->sense,
+                           (const uint8_t *)p->vt, (const double *)p->l, (const double *)p->u, p->ln, p->un,
+                           p->flags);
       if (n > 0)
         hipLaunchKernelGGL(k_prop_finish, dim3(prop_grid(n)), dim3(kPropBlock), 0, st, n, p->l, p->u,
                            (const double *)p->ln, (const double *)p->un, p->flags);

@@ -65,8 +65,136 @@ __device__ __forceinline__ double tighten_lower(double cur, double p, bool integ
   return p > (cur + (kContTol * fmax(1.0, fabs(cur)))) ? p : cur;
 }
 
-// flags[1] = 1 when a row cannot be satisfied within the bounds (finite activity past b by more than
-// 1e-6 max(1, |b|)).
+constexpr int kLongRow = 128;  // rows at least this long are handled by a whole wave
+
+struct Activity {
+  double minf, maxf;   // finite parts of the minimum / maximum activity, summed in row order
+  int mininf, maxinf;  // infinite terms
+};
+
+// Activities of row [k0, k1) by one thread: the plain sequential sum.
+__device__ __forceinline__ Activity activity_seq(int32_t k0, int32_t k1, const int32_t *__restrict__ ci,
+                                                 const double *__restrict__ val, const double *__restrict__ l,
+                                                 const double *__restrict__ u) {
+#pragma clang fp contract(off)
+  Activity A{0.0, 0.0, 0, 0};
+  for (int32_t k = k0; k < k1; ++k) {
+    const double a = val[k];
+    if (a == 0.0) continue;
+    const int32_t j = ci[k];
+    const double lo = l[j], hi = u[j];
+    const double tmin = a > 0.0 ? lo : hi, tmax = a > 0.0 ? hi : lo;
+    if (isinf(tmin)) ++A.mininf;
+    else A.minf = (A.minf + (a * tmin));
+    if (isinf(tmax)) ++A.maxinf;
+    else A.maxf = (A.maxf + (a * tmax));
+  }
+  return A;
+}
+
+// The same sum by a wave: each 64-element segment is loaded and multiplied by the lanes in parallel,
+// then every lane adds the segment's terms in row order (broadcast one lane at a time), so all lanes
+// end with the sequential sum's exact value without waiting on one gather per element.
+__device__ __forceinline__ Activity activity_wave(int32_t k0, int32_t k1, int lane, const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ val, const double *__restrict__ l,
+                                                  const double *__restrict__ u) {
+#pragma clang fp contract(off)
+  Activity A{0.0, 0.0, 0, 0};
+  for (int32_t seg = k0; seg < k1; seg += 64) {
+    const int32_t k = seg + lane;
+    double pmin = 0.0, pmax = 0.0;
+    int code = 0;  // bit 0: a term exists (nonzero coefficient), bit 1: infinite min term, bit 2: infinite max term
+    if (k < k1) {
+      const double a = val[k];
+      if (a != 0.0) {
+        const int32_t j = ci[k];
+        const double lo = l[j], hi = u[j];
+        const double tmin = a > 0.0 ? lo : hi, tmax = a > 0.0 ? hi : lo;
+        code = 1 | (isinf(tmin) ? 2 : 0) | (isinf(tmax) ? 4 : 0);
+        if (!isinf(tmin)) pmin = a * tmin;
+        if (!isinf(tmax)) pmax = a * tmax;
+      }
+    }
+    const int cnt = min(64, k1 - seg);
+    for (int t = 0; t < cnt; ++t) {
+      const int c = __shfl(code, t, 64);
+      const double qmin = __shfl(pmin, t, 64), qmax = __shfl(pmax, t, 64);
+      if (c & 1) {
+        if (c & 2) ++A.mininf;
+        else A.minf = (A.minf + qmin);
+        if (c & 4) ++A.maxinf;
+        else A.maxf = (A.maxf + qmax);
+      }
+    }
+  }
+  return A;
+}
+
+// Proposals of one row from its activities, split over the lanes (first = lane, stride = lanes);
+// flags[1] = 1 (from the first lane) when the row cannot be satisfied within the bounds: a finite
+// activity past b by more than 1e-6 max(1, |b|).
+__device__ __forceinline__ void prop_row(int64_t i, const Activity &A, int first, int stride,
+                                         const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                         const double *__restrict__ val, const double *__restrict__ b,
+                                         const uint8_t *__restrict__ sense, const uint8_t *__restrict__ vt,
+                                         const double *__restrict__ l, const double *__restrict__ u, double *ln,
+                                         double *un, int32_t *flags) {
+#pragma clang fp contract(off)
+  const int32_t k0 = rp[i], k1 = rp[i + 1];
+  const double minf = A.minf, maxf = A.maxf;
+  const int mininf = A.mininf, maxinf = A.maxinf;
+  const double bi = b[i];
+  const double tolb = (kFeasTol * fmax(1.0, fabs(bi)));
+  const uint8_t s = sense[i];
+  const bool le = s == 'L' || s == 'E', ge = s == 'G' || s == 'E';
+  if (first == 0 && ((le && mininf == 0 && minf > (bi + tolb)) || (ge && maxinf == 0 && maxf < (bi - tolb))))
+    atomicOr(&flags[1], 1);
+  for (int32_t k = k0 + first; k < k1; k += stride) {
+    const double a = val[k];
+    if (a == 0.0) continue;
+    const int32_t j = ci[k];
+    const double lo = l[j], hi = u[j];
+    const bool integral = vt[j] != 0;
+    if (le) {
+      const double t = a > 0.0 ? lo : hi;
+      bool ok = true;
+      double res = 0.0;
+      if (mininf == 0) res = (minf - (a * t));
+      else if (mininf == 1 && isinf(t)) res = minf;
+      else ok = false;
+      if (ok) {
+        const double p = (bi - res) / a;
+        if (a > 0.0) {
+          const double q = tighten_upper(hi, p, integral);
+          if (q < hi) atomic_min_double(&un[j], q);
+        } else {
+          const double q = tighten_lower(lo, p, integral);
+          if (q > lo) atomic_max_double(&ln[j], q);
+        }
+      }
+    }
+    if (ge) {
+      const double t = a > 0.0 ? hi : lo;
+      bool ok = true;
+      double res = 0.0;
+      if (maxinf == 0) res = (maxf - (a * t));
+      else if (maxinf == 1 && isinf(t)) res = maxf;
+      else ok = false;
+      if (ok) {
+        const double p = (bi - res) / a;
+        if (a > 0.0) {
+          const double q = tighten_lower(lo, p, integral);
+          if (q > lo) atomic_max_double(&ln[j], q);
+        } else {
+          const double q = tighten_upper(hi, p, integral);
+          if (q < hi) atomic_min_double(&un[j], q);
+        }
+      }
+    }
+  }
+}
+
+// Rows shorter than kLongRow: one thread each.
 __global__ __launch_bounds__(kPropBlock) void k_prop_round(int m, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ ci,
                                                            const double *__restrict__ val,
@@ -75,71 +203,32 @@ __global__ __launch_bounds__(kPropBlock) void k_prop_round(int m, const int32_t 
                                                            const uint8_t *__restrict__ vt,
                                                            const double *__restrict__ l, const double *__restrict__ u,
                                                            double *ln, double *un, int32_t *flags) {
-#pragma clang fp contract(off)
   for (int64_t i = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kPropBlock) {
     const int32_t k0 = rp[i], k1 = rp[i + 1];
-    double minf = 0.0, maxf = 0.0;
-    int mininf = 0, maxinf = 0;
-    for (int32_t k = k0; k < k1; ++k) {
-      const double a = val[k];
-      if (a == 0.0) continue;
-      const int32_t j = ci[k];
-      const double lo = l[j], hi = u[j];
-      const double tmin = a > 0.0 ? lo : hi, tmax = a > 0.0 ? hi : lo;
-      if (isinf(tmin)) ++mininf;
-      else minf = (minf + (a * tmin));
-      if (isinf(tmax)) ++maxinf;
-      else maxf = (maxf + (a * tmax));
-    }
-    const double bi = b[i];
-    const double tolb = (kFeasTol * fmax(1.0, fabs(bi)));
-    const uint8_t s = sense[i];
-    const bool le = s == 'L' || s == 'E', ge = s == 'G' || s == 'E';
-    if ((le && mininf == 0 && minf > (bi + tolb)) || (ge && maxinf == 0 && maxf < (bi - tolb)))
-      atomicOr(&flags[1], 1);
-    for (int32_t k = k0; k < k1; ++k) {
-      const double a = val[k];
-      if (a == 0.0) continue;
-      const int32_t j = ci[k];
-      const double lo = l[j], hi = u[j];
-      const bool integral = vt[j] != 0;
-      if (le) {
-        const double t = a > 0.0 ? lo : hi;
-        bool ok = true;
-        double res = 0.0;
-        if (mininf == 0) res = (minf - (a * t));
-        else if (mininf == 1 && isinf(t)) res = minf;
-        else ok = false;
-        if (ok) {
-          const double p = (bi - res) / a;
-          if (a > 0.0) {
-            const double q = tighten_upper(hi, p, integral);
-            if (q < hi) atomic_min_double(&un[j], q);
-          } else {
-            const double q = tighten_lower(lo, p, integral);
-            if (q > lo) atomic_max_double(&ln[j], q);
-          }
-        }
-      }
-      if (ge) {
-        const double t = a > 0.0 ? hi : lo;
-        bool ok = true;
-        double res = 0.0;
-        if (maxinf == 0) res = (maxf - (a * t));
-        else if (maxinf == 1 && isinf(t)) res = maxf;
-        else ok = false;
-        if (ok) {
-          const double p = (bi - res) / a;
-          if (a > 0.0) {
-            const double q = tighten_lower(lo, p, integral);
-            if (q > lo) atomic_max_double(&ln[j], q);
-          } else {
-            const double q = tighten_upper(hi, p, integral);
-            if (q < hi) atomic_min_double(&un[j], q);
-          }
-        }
-      }
-    }
+    if (k1 - k0 >= kLongRow) continue;
+    const Activity A = activity_seq(k0, k1, ci, val, l, u);
+    prop_row(i, A, 0, 1, rp, ci, val, b, sense, vt, l, u, ln, un, flags);
+  }
+}
+
+// Rows of at least kLongRow entries (listed in `rows`): one wave each.
+__global__ __launch_bounds__(kPropBlock) void k_prop_round_long(int nlong, const int32_t *__restrict__ rows,
+                                                                const int32_t *__restrict__ rp,
+                                                                const int32_t *__restrict__ ci,
+                                                                const double *__restrict__ val,
+                                                                const double *__restrict__ b,
+                                                                const uint8_t *__restrict__ sense,
+                                                                const uint8_t *__restrict__ vt,
+                                                                const double *__restrict__ l,
+                                                                const double *__restrict__ u, double *ln, double *un,
+                                                                int32_t *flags) {
+  const int lane = (int)threadIdx.x & 63;
+  const int64_t wave0 = ((int64_t)blockIdx.x * kPropBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kPropBlock) >> 6;
+  for (int64_t w = wave0; w < nlong; w += nwaves) {
+    const int64_t i = rows[w];
+    const Activity A = activity_wave(rp[i], rp[i + 1], lane, ci, val, l, u);
+    prop_row(i, A, lane, 64, rp, ci, val, b, sense, vt, l, u, ln, un, flags);
   }
 }
 
