@@ -215,6 +215,16 @@ int pdlp_batch_solve(pdlp_batch *bt, double tol, int64_t iter_limit, const doubl
 int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_cost,
                    pdlp_result *res);
 
+/* Re-solves after fixings (the paper's fix-and-propagate changes bounds, then may solve the LP
+ * again; section 2, "Fix-and-Propagate Using Low-Precision LP Solutions"): replace the column bounds
+ * l [n], u [n] (caller's numbering, validated as in pdlp_create; device pointers when the handle has
+ * device_ptrs) of a handle, or of instance i of a batch. Matrix, costs, scaling and the SpMV
+ * schedule are kept, so this costs one small upload instead of a new handle; a following solve is
+ * bitwise the one a new handle created with these bounds would give (same options and chunk size),
+ * and may be warm-started from the previous solution (x0/y0 of pdlp_solve / pdlp_batch_solve). */
+int pdlp_update_bounds(pdlp_problem *p, const double *l, const double *u);
+int pdlp_batch_update_bounds(pdlp_batch *bt, int32_t i, const double *l, const double *u);
+
 /* SpMV schedule of the batch, as pdlp_get_schedule (chunk counts over all instances). An
  * instance's chunks and work blocks depend on the instance and the chunk size alone, so a single
  * problem created with pdlp_options.tile_nnz set to this chunk size (and the same other options)

@@ -993,6 +993,40 @@ struct Solver {
     sync();
   }
 
+  // New bounds for instance q (caller's numbering): validated like create's, scaled and renumbered
+  // into the iteration copies exactly as create does, so a later solve behaves as on a new handle
+  // made with these bounds. Matrix, costs, scaling and schedule are kept.
+  void update_bounds(int q, const double *l, const double *u) {
+    if (q < 0 || q >= K) raise(PDLP_ERR_ARG, "instance index out of range");
+    const int32_t c0 = h_col0[q], nq = h_col0[q + 1] - c0;
+    if (nq == 0) return;
+    if (!l || !u) raise(PDLP_ERR_ARG, "NULL bounds");
+    std::vector<double> lh((size_t)nq), uh((size_t)nq);
+    if (opt.device_ptrs) {
+      HIPCHK(hipMemcpy(lh.data(), l, sizeof(double) * (size_t)nq, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(uh.data(), u, sizeof(double) * (size_t)nq, hipMemcpyDeviceToHost));
+    } else {
+      std::copy(l, l + nq, lh.begin());
+      std::copy(u, u + nq, uh.begin());
+    }
+    std::vector<double> li((size_t)nq), ui((size_t)nq);
+    for (int32_t j = 0; j < nq; ++j) {
+      if (std::isnan(lh[j]) || std::isnan(uh[j])) raise(PDLP_ERR_ARG, "bounds must not be NaN");
+      if (lh[j] > uh[j]) raise(PDLP_ERR_ARG, "l > u at column " + std::to_string(j));
+      if (lh[j] == INFINITY || uh[j] == -INFINITY) raise(PDLP_ERR_ARG, "l = +inf or u = -inf");
+      const int32_t ji = h_inv_c[(size_t)(c0 + j)] - c0;
+      li[(size_t)ji] = lh[j], ui[(size_t)ji] = uh[j];
+    }
+    double *dl = mem.alloc<double>(nq), *du = mem.alloc<double>(nq);
+    upload(dl, li.data(), nq);
+    upload(du, ui.data(), nq);
+    hipLaunchKernelGGL(k_scale_bounds<T>, dim3(grid_for(nq)), dim3(kBlock), 0, stream, nq, c0, (const double *)dl,
+                       (const double *)du, (const double *)Dc, l64, u64, lT, uT);
+    HIPCHK(hipGetLastError());
+    sync();
+    mem.release(dl), mem.release(du);
+  }
+
   // Scaling in the caller's numbering: Dr [m], Dc [n], scaled values in the caller's CSR order.
   void get_scaling(double *dr, double *dc, double *sv) {
     std::vector<double> hr((size_t)m), hc((size_t)n), hv;
@@ -1306,6 +1340,22 @@ int pdlp_batch_get_schedule(pdlp_batch *bt, int32_t *tile_nnz, int32_t *tiles_a,
       if (tiles_at) *tiles_at = s.t_nchunks;
     });
   });
+}
+
+int pdlp_update_bounds(pdlp_problem *p, const double *l, const double *u) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { s.update_bounds(0, l, u); }); });
+}
+
+int pdlp_batch_update_bounds(pdlp_batch *bt, int32_t i, const double *l, const double *u) {
+  if (!bt) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { bt->s.visit([&](auto &s) { s.update_bounds(i, l, u); }); });
 }
 
 void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }

@@ -1089,6 +1089,22 @@ __global__ __launch_bounds__(kBlock) void k_scale_vectors(int m, int n, const do
   }
 }
 
+// New bounds of one instance (columns c0 .. c0 + nq - 1 in internal numbering), scaled exactly as
+// k_scale_vectors scales them at create time.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_bounds(int nq, int c0, const double *__restrict__ l,
+                                                         const double *__restrict__ u, const double *__restrict__ Dc,
+                                                         double *__restrict__ l64, double *__restrict__ u64,
+                                                         T *__restrict__ lT, T *__restrict__ uT) {
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < nq; k += gridDim.x * kBlock) {
+    const int j = c0 + k;
+    const double ls = isfinite(l[k]) ? l[k] / Dc[j] : l[k];
+    const double us = isfinite(u[k]) ? u[k] / Dc[j] : u[k];
+    l64[j] = ls, u64[j] = us;
+    lT[j] = T(ls), uT[j] = T(us);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_convert(int64_t n, const double *__restrict__ s, T *__restrict__ d) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) d[i] = T(s[i]);

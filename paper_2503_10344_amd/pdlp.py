@@ -62,7 +62,8 @@ class ProblemDesc(C.Structure):
 EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_spmv",
            "pdlp_get_scaling", "pdlp_get_internal", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
-           "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy", "pdlp_variable_strategy",
+           "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy", "pdlp_update_bounds",
+           "pdlp_batch_update_bounds", "pdlp_variable_strategy",
            "pdlp_lp_fixing", "pdlp_prop_create", "pdlp_propagate", "pdlp_prop_destroy", "pdlp_branching"]
 
 _lib = None
@@ -100,6 +101,10 @@ def load(path: str = LIB_PATH):
     lib.pdlp_get_schedule.restype = C.c_int
     lib.pdlp_batch_get_schedule.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.pdlp_batch_get_schedule.restype = C.c_int
+    lib.pdlp_update_bounds.argtypes = [vp, vp, vp]
+    lib.pdlp_update_bounds.restype = C.c_int
+    lib.pdlp_batch_update_bounds.argtypes = [vp, i32, vp, vp]
+    lib.pdlp_batch_update_bounds.restype = C.c_int
     lib.pdlp_kernel_stats.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(dp)]
     lib.pdlp_kernel_stats.restype = C.c_int
     lib.pdlp_device_bytes.argtypes = [vp]
@@ -313,6 +318,11 @@ class Problem:
         _check(load().pdlp_get_schedule(self.h, C.byref(tn), C.byref(ta), C.byref(tt)))
         return dict(tile_nnz=tn.value, tiles_a=ta.value, tiles_at=tt.value)
 
+    def update_bounds(self, l, u):
+        """New column bounds (after fixings) for the next solve; see pdlp_update_bounds."""
+        lo, hi = np.ascontiguousarray(l, np.float64), np.ascontiguousarray(u, np.float64)
+        _check(load().pdlp_update_bounds(self.h, _ptr(lo), _ptr(hi)))
+
     def kernel_stats(self) -> dict:
         out = {}
         for k, name in ((0, "dual"), (1, "primal")):
@@ -443,6 +453,11 @@ class Batch:
         x, y, rc = np.zeros(n), np.zeros(m), np.zeros(n)
         r = pdlp_batch_get(self.h, i, x, y, rc)
         return Solution(x, y, rc, r.as_dict())
+
+    def update_bounds(self, i, l, u):
+        """New column bounds of instance i for the next batched solve."""
+        lo, hi = np.ascontiguousarray(l, np.float64), np.ascontiguousarray(u, np.float64)
+        _check(load().pdlp_batch_update_bounds(self.h, int(i), _ptr(lo), _ptr(hi)))
 
     def schedule(self) -> dict:
         tn, ta, tt = C.c_int32(), C.c_int32(), C.c_int32()

@@ -150,6 +150,8 @@ def test_null_arguments(lib):
     assert lib.pdlp_solve(None, 1e-4, 10, None, None, 0.0) == -1
     assert lib.pdlp_get(None, None, None, None, None) == -1
     assert lib.pdlp_batch_get_schedule(None, None, None, None) == -1
+    assert lib.pdlp_update_bounds(None, None, None) == -1
+    assert lib.pdlp_batch_update_bounds(None, 0, None, None) == -1
     cnt = C.c_int32()
     assert lib.pdlp_variable_strategy(None, 1, 0, None, None, None, None, None, C.byref(cnt)) == -1
     assert lib.pdlp_lp_fixing(None, None, None, None, None, None, None) == -1
