@@ -215,8 +215,8 @@ int pdlp_batch_solve(pdlp_batch *bt, double tol, int64_t iter_limit, const doubl
 int pdlp_batch_get(pdlp_batch *bt, int32_t i, double *x, double *y, double *red_cost,
                    pdlp_result *res);
 
-/* Re-solves after fixings (the paper's fix-and-propagate changes bounds, then may solve the LP
- * again; section 2, "Fix-and-Propagate Using Low-Precision LP Solutions"): replace the column bounds
+/* Re-solves after fixings (fix-and-propagate changes bounds and solves a final LP on them; the paper
+ * does that with an IPM and names PDLP for it as future work; section 2 and the conclusion): replace the column bounds
  * l [n], u [n] (caller's numbering, validated as in pdlp_create; device pointers when the handle has
  * device_ptrs) of a handle, or of instance i of a batch. Matrix, costs, scaling and the SpMV
  * schedule are kept, so this costs one small upload instead of a new handle; a following solve is
