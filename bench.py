@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "ed65b2c7f2a8adfeb2042adb2e12ed3bbb5ef8d4"): 454_690_163,
-    ("energy", "ed65b2c7f2a8adfeb2042adb2e12ed3bbb5ef8d4"): 467_401_474,
+    ("zipf", "cc4c1c5daaac105c656eebfa0e9f9f40df162627"): 455_899_663,
+    ("energy", "cc4c1c5daaac105c656eebfa0e9f9f40df162627"): 466_785_957,
 }
 
 
