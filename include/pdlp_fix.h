@@ -45,7 +45,7 @@ enum { PDLP_ORDER_NONE = 0, PDLP_ORDER_FRAC = 1, PDLP_ORDER_REDCOST = 2, PDLP_OR
 /* Order of the binary and integer variables under `strategy`, ties broken by `tiebreak`.
  *   var_type [n]  PDLP_VAR_* per variable
  *   x [n]         needed by FRAC; y [m] by DUAL; red_cost [n] by REDCOST and DUAL (others may be NULL)
- *   order [n]     receives the *count variable indices, first to fix first
+ *   order [n]     receives the *count variable indices, first to fix first (count: host memory)
  * PDLP_ERR_ARG for a NULL handle or needed pointer, an unknown strategy, a batch handle, or (host
  * inputs) non-finite values. */
 int pdlp_variable_strategy(pdlp_problem *p, int32_t strategy, int32_t tiebreak, const uint8_t *var_type,

@@ -47,7 +47,8 @@ int pdlp_prop_create(pdlp_prop **out, int32_t m, int32_t n, int64_t nnz, const i
                      const uint8_t *var_type, const pdlp_options *opt);
 
 /* Propagate bounds l [n], u [n] in place (+-HUGE_VAL allowed, no NaN) for at most max_rounds (>= 1)
- * rounds. *rounds receives the rounds run, *status a PDLP_PROP_* code (either may be NULL). On
+ * rounds. *rounds receives the rounds run, *status a PDLP_PROP_* code (host memory; either may be
+ * NULL). On
  * PDLP_PROP_INFEASIBLE the bounds are those after the round that showed it. */
 int pdlp_propagate(pdlp_prop *p, double *l, double *u, int32_t max_rounds, int32_t *rounds, int32_t *status);
 
