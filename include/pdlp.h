@@ -78,7 +78,7 @@ typedef struct pdlp_options {
                               pdlp_kernel_stats (default 0) */
   int32_t work_blocks;     /* most blocks per SpMV kernel for one instance (each block owns a
                               contiguous run of chunks; an instance gets one block per 1024 nonzeros
-                              + rows up to this count); 0 = 8192 (default 0) */
+                              + rows up to this count); 0 = 16384 (default 0) */
   int32_t reserved[5];
 } pdlp_options;
 

@@ -201,7 +201,7 @@ struct Solver {
   int32_t *d_ev0 = nullptr, *d_ev_inst = nullptr;
   int32_t *d_a_bchunk = nullptr, *d_t_bchunk = nullptr;  // first chunk of each work block
   int ab_blocks = 1, tb_blocks = 1, ev_blocks = 1;
-  int work_blocks = 8192;  // most work blocks per side of one instance
+  int work_blocks = 16384;  // most work blocks per side of one instance
   // matrix
   int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr, *perm = nullptr;
   int32_t *a_chunk_row = nullptr, *t_chunk_row = nullptr;
