@@ -117,7 +117,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the PDLP solve on a single MI355X and has no "
+        print("bench.py measures one GPU: the library runs the PDLP solve on a single MI355X and has no "
               "multi-GPU path; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

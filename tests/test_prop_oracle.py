@@ -48,8 +48,8 @@ def pin_hand_example(lib=oracle.PROP_LIB):
              [L_, G_, E_], [1, 0, 0, 0, 0, 1], [1, 1, 2, 2, 5, 3])
     vt = np.array([1, 1, 2, 2, 0, 0], np.uint8)
     l, u, st, r = _run(lib, lp, vt)
-    # round 1: u1 = (1 - 1)/1 = 0; l2 = ceil((7 - 6)/2) = 1, l3 = ceil((7 - 4)/3) = 1;
-    # u4 = 0 - (-3) = 3, l4 = 0 - (-1) = 1; round 2 changes nothing
+    # first round: u1 = (1 - 1)/1 = 0; l2 = ceil((7 - 6)/2) = 1, l3 = ceil((7 - 4)/3) = 1;
+    # u4 = 0 - (-3) = 3, l4 = 0 - (-1) = 1; the second round changes nothing
     assert list(l) == [1, 0, 1, 1, 1, 1] and list(u) == [1, 0, 2, 2, 3, 3], (l, u)
     assert (st, r) == (oracle.PROP_FIXPOINT, 2)
 
