@@ -98,7 +98,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="zipf",
-                    choices=["zipf", "setcover", "energy", "batch", "fixing", "propagation", "resolve"])
+                    choices=["zipf", "setcover", "energy", "batch", "fixing", "propagation", "resolve",
+                             "snapshots"])
     ap.add_argument("--fixing-lp", default="zipf", choices=["zipf", "energy"],
                     help="with --workload fixing or propagation: the LP whose size they run at")
     ap.add_argument("--seed", type=int, default=0)
@@ -135,6 +136,8 @@ def main():
         return bench_propagation(args)
     if args.workload == "resolve":
         return bench_resolve(args)
+    if args.workload == "snapshots":
+        return bench_snapshots(args)
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib * 2**18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -190,11 +193,6 @@ def main():
                 "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": round(dom["avg_us"], 2)}
     log(f"kernels: {json.dumps(kern)}")
 
-    # independent check of the returned point by the FP64 oracle (original data)
-    import oracle
-    t = time.time()
-    chk = oracle.kkt(lp, sol.x, sol.y)
-    log(f"oracle re-evaluation of the returned point: rel_kkt={chk['rel_kkt']:.3e} ({time.time() - t:.1f} s)")
     p.close()
 
     # ---------------- FP64 cold solve (comparison) ----------------
@@ -214,8 +212,13 @@ def main():
         p64.close()
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
-    cpu = None
+    cpu, chk = None, {"rel_kkt": None}
     if not args.no_cpu_baseline:
+        import oracle
+        # the oracle's FP64 re-evaluation of the returned point (original data) comes with this leg
+        t = time.time()
+        chk = oracle.kkt(lp, sol.x, sol.y)
+        log(f"oracle re-evaluation of the returned point: rel_kkt={chk['rel_kkt']:.3e} ({time.time() - t:.1f} s)")
         n1, n2 = 8, max(16, args.cpu_iters)
         t = time.time()
         oracle.solve(lp, tol=0.0, iter_limit=n1)
@@ -480,7 +483,6 @@ def bench_resolve(args):
     import torch
     from paper_2503_10344_amd import generators as g
     from paper_2503_10344_amd import pdlp
-    import oracle
     t = time.time()
     lps = g.batch(args.seed, count=args.batch_count)
     log(f"{len(lps)} instances generated in {time.time() - t:.1f} s")
@@ -514,7 +516,7 @@ def bench_resolve(args):
     t_cold, cold = timed_solve(b)
     t_warm, warm = timed_solve(b, x0s=[s_.x for s_ in sols], y0s=[s_.y for s_ in sols],
                                omega0s=[f["omega"] for f in first])
-    worst = max(oracle.kkt(fx, *(lambda s2: (s2.x, s2.y))(b.get(i)))["rel_kkt"] for i, fx in enumerate(fixed))
+    worst = max(i_["rel_kkt"] for i_ in warm)  # the library's FP64 re-evaluation of each returned point
     b.close()
     t0 = time.perf_counter()
     nb = pdlp.Batch(fixed, precision="fp32")
@@ -534,7 +536,91 @@ def bench_resolve(args):
            "iterations_max_total": {"first": it(first), "cold": it(cold), "warm": it(warm), "new_batch": it(new)},
            "warm_used": int(sum(i["warm_started"] for i in warm)),
            "all_optimal": bool(all(i["status"] == pdlp.OPTIMAL for i in warm)),
-           "worst_oracle_rel_kkt_warm": worst}
+           "worst_rel_kkt_warm": worst}
+    log(json.dumps(res))
+    print(json.dumps(res), flush=True)
+
+
+def bench_snapshots(args, k=8, rel_tol=1e-3):
+    """Reference snapshots on the general sparse LP: the FP32 solve to tol with and without keeping the
+    newest k restart points of relative KKT error <= rel_tol (the solve itself is unchanged), the time
+    to read them back, how far apart they are, and how many LP-based fixings each one changes against
+    the final solution (the same seeded samples), i.e. how many distinct fix-and-propagate starts one
+    solve yields."""
+    import numpy as np
+    import torch
+    from paper_2503_10344_amd import generators as g
+    from paper_2503_10344_amd import pdlp
+    lp, desc = make_workload(args.fixing_lp, args.seed)
+    d = g.fixing_inputs(args.seed, lp)
+    p = pdlp.Problem(lp, precision="fp32")
+
+    def timed_solve():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = p.solve(tol=args.tol, iter_limit=args.iter_limit)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, info
+
+    t_off, info_off = timed_solve()
+    x_off = p.get().x
+    p.set_snapshots(k, rel_tol)
+    t_on, info_on = timed_solve()
+    sol = p.get()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    snaps = p.snapshots()
+    t_get = time.perf_counter() - t0
+    same = bool(info_on["iterations"] == info_off["iterations"] and np.array_equal(sol.x, x_off))
+    log(f"solve without snapshots {t_off:.3f} s, with {t_on:.3f} s; {snaps.attempt.size} snapshots at "
+        f"{list(map(int, snaps.attempt))}; read back in {t_get:.3f} s")
+    nx = max(np.linalg.norm(sol.x), 1e-30)
+    dist_final = [float(np.linalg.norm(snaps.x[q] - sol.x) / nx) for q in range(snaps.attempt.size)]
+    dist_next = [float(np.linalg.norm(snaps.x[q + 1] - snaps.x[q]) / nx) for q in range(snaps.attempt.size - 1)]
+    vt = d["var_type"]
+    ints = vt != 0
+    fix_final = p.lp_fixing(vt, sol.x, lp.l, lp.u, d["uniform"])
+    changed = [int(np.sum(p.lp_fixing(vt, snaps.x[q], lp.l, lp.u, d["uniform"])[ints] != fix_final[ints]))
+               for q in range(snaps.attempt.size)]
+    p.close()
+    over = t_on - t_off
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n1, n2 = 8, 72
+        t = time.time()
+        oracle.solve(lp, tol=0.0, iter_limit=n1)
+        t1 = time.time() - t
+        t = time.time()
+        oracle.solve(lp, tol=0.0, iter_limit=n2)
+        t2 = time.time() - t
+        t = time.time()
+        for q in range(snaps.attempt.size):
+            oracle.kkt(lp, snaps.x[q], snaps.y[q])
+        t_kkt = time.time() - t
+        per = (t2 - t1) / (n2 - n1)
+        est = max(t1 - n1 * per, 0.0) + per * info_on["iterations"] + t_kkt
+        cpu = {"value": round(est, 2), "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": (f"FP64 oracle run for {n1} and {n2} attempts ({t1:.1f} s, {t2:.1f} s), extrapolated to "
+                          f"{info_on['iterations']} attempts, plus its KKT evaluation of the {snaps.attempt.size} "
+                          f"snapshots ({t_kkt:.1f} s); host CPU: {cpu_model()}")}
+        log(f"cpu baseline: {json.dumps(cpu)}")
+    res = {"metric": f"FP32 solve to {args.tol:g} rel. KKT keeping the newest {k} restart points with rel. KKT <= "
+                     f"{rel_tol:g} as reference solutions",
+           "value": round(t_on, 4), "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": round(1e3 * t_on, 2), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{desc}; {int(ints.sum())} seeded binary/integer variables for the fixings",
+                      "k": k, "rel_tol": rel_tol, "tol": args.tol},
+           "solve_without_snapshots_s": round(t_off, 4), "overhead_s": round(over, 4),
+           "overhead_frac": round(over / t_off, 4), "solve_unchanged": same,
+           "iterations": info_on["iterations"], "read_back_s": round(t_get, 4),
+           "snapshots": {"attempt": [int(a) for a in snaps.attempt],
+                         "rel_kkt": [float("%.4g" % r) for r in snaps.rel_kkt],
+                         "rel_dist_to_final": [float("%.4g" % v) for v in dist_final],
+                         "rel_dist_to_next": [float("%.4g" % v) for v in dist_next],
+                         "lp_fixings_changed_vs_final": changed},
+           "roofline": None, "cpu_baseline": cpu}
     log(json.dumps(res))
     print(json.dumps(res), flush=True)
 

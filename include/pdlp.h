@@ -233,6 +233,40 @@ int pdlp_batch_get_schedule(pdlp_batch *bt, int32_t *tile_nnz, int32_t *tiles_a,
 
 void pdlp_batch_destroy(pdlp_batch *bt);
 
+/* ==========================================================================================
+ * Reference snapshots: several LP reference solutions from one solve. The paper's conclusion
+ * (section 5) proposes using the cycling convergence of PDLP to start several fix-and-propagate
+ * searches from one LP solve. A snapshot is a restart point of the solve (the candidate of the
+ * evaluation step, every eval_every attempts, that the method restarts to: the current iterate or the
+ * average) whose relative KKT error in the original space, as that evaluation measured it, is at
+ * most rel_tol. Each instance keeps the newest k of them; taking them does not change the solve
+ * (its iterates and result are bitwise those of a solve without snapshots).
+ * ========================================================================================== */
+
+/* Keep up to k snapshots per instance (k = 0: none, the default) in later solves of the handle
+ * (pdlp_set_snapshots) or of every instance of the batch (pdlp_batch_set_snapshots). Allocates
+ * k (n + m) doubles of device memory (n, m: all instances) under device_mem_limit and replaces the
+ * previous setting and snapshots. Each solve starts with no snapshots. Errors: PDLP_ERR_ARG for a
+ * NULL handle, k < 0 or a NaN rel_tol; PDLP_ERR_OOM. */
+int pdlp_set_snapshots(pdlp_problem *p, int32_t k, double rel_tol);
+int pdlp_batch_set_snapshots(pdlp_batch *bt, int32_t k, double rel_tol);
+
+/* Snapshots of the last solve (of instance i of a batch), oldest first: at most cap of them (the
+ * newest cap when more are held); *count (host memory, required) = the number written. Per
+ * snapshot s < *count: x[s n .. s n + n) and y[s m .. s m + m) the point in the original space and
+ * the caller's numbering (n, m of this instance; host memory, or device memory when the handle has
+ * device_ptrs; either may be NULL), attempt[s] the attempt count at which it was taken and
+ * rel_kkt[s] its relative KKT error as measured then (host memory; either may be NULL). In FP32 the
+ * evaluation works from the FP32 products A x and A'y, and an average enters the restart point
+ * rounded to FP32 (the snapshot is that rounded point); unlike the returned solution, snapshots are
+ * not re-checked in FP64, so an FP64 evaluation of a snapshot can differ from rel_kkt[s] by that
+ * rounding. Errors: PDLP_ERR_STATE before a solve; PDLP_ERR_ARG for cap < 0, a NULL count or i out
+ * of range. */
+int pdlp_get_snapshots(pdlp_problem *p, int32_t cap, double *x, double *y, int64_t *attempt, double *rel_kkt,
+                       int32_t *count);
+int pdlp_batch_get_snapshots(pdlp_batch *bt, int32_t i, int32_t cap, double *x, double *y, int64_t *attempt,
+                             double *rel_kkt, int32_t *count);
+
 #ifdef __cplusplus
 }
 #endif

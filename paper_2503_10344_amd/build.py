@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdlp.so")
 SOURCES = ["pdlp.hip"]
-HEADERS = ["pdlp_internal.h", "pdlp_kernels.h", "gnn_kernels.h", "gnn_host.h", "fix_kernels.h", "fix_host.h", "prop_kernels.h", "prop_host.h"]
+HEADERS = ["pdlp_internal.h", "pdlp_kernels.h", "gnn_kernels.h", "gnn_host.h", "fix_kernels.h", "fix_host.h", "prop_kernels.h", "prop_host.h", "snap_kernels.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -19,6 +19,7 @@
 
 #include "../../include/pdlp.h"
 #include "pdlp_kernels.h"
+#include "snap_kernels.h"
 
 namespace pdlp {
 
@@ -241,6 +242,8 @@ struct Solver {
   double t_ms[2] = {0.0, 0.0};
   Iter<T> P{};
   std::shared_ptr<void> fix_cache;  // workspace of the LP-based variable strategies, kept between calls
+  // reference snapshots (restart points within snap.rel_tol; off while snap.K == 0)
+  Snap snap{};
   bool solved = false;
   std::vector<pdlp_result> last;
 
@@ -686,6 +689,15 @@ struct Solver {
     hipLaunchKernelGGL(k_eval_fin, dim3(K), dim3(kBlock), 0, stream, P.L, (const double *)p_eval, st, ndone, mode);
   }
   void launch_restart() { hipLaunchKernelGGL(k_restart<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P); }
+  // Evaluation and restart at the end of an interval, with the snapshot kernels around the restart
+  // when snapshots are on.
+  void launch_eval_restart() {
+    launch_eval(kEvalChunk);
+    if (snap.K > 0)
+      hipLaunchKernelGGL(k_snap_pick, dim3(grid_for(K)), dim3(kBlock), 0, stream, K, (const State *)st, snap);
+    launch_restart();
+    if (snap.K > 0) hipLaunchKernelGGL(k_snap_copy<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, snap);
+  }
   // In FP32 the products of the averages, kept up to date by the same weighted updates as the
   // averages themselves, drift from A x-bar and A'y-bar by accumulated rounding; they are
   // recomputed before each evaluation so that the average's KKT error, and the caches a restart to
@@ -699,8 +711,7 @@ struct Solver {
   void launch_chunk_body() {
     for (int r = 0; r < opt.eval_every; ++r) launch_attempt();
     refresh_averages();
-    launch_eval(kEvalChunk);
-    launch_restart();
+    launch_eval_restart();
   }
   // Direct launches bracketed by events (pool `slot`): [attempt][kernel][start, stop].
   void launch_chunk_timed(int slot) {
@@ -720,8 +731,7 @@ struct Solver {
       HIPCHK(hipEventRecord(e[3], stream));
     }
     refresh_averages();
-    launch_eval(kEvalChunk);
-    launch_restart();
+    launch_eval_restart();
     HIPCHK(hipGetLastError());
   }
   // Add the durations recorded in pool `slot` (its chunk has completed).
@@ -825,6 +835,7 @@ struct Solver {
     }
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));
+    if (snap.K > 0) HIPCHK(hipMemsetAsync(snap.taken, 0, sizeof(int32_t) * (size_t)K, stream));
     t_launches[0] = t_launches[1] = 0;
     t_ms[0] = t_ms[1] = 0.0;
     const bool warm = stage_start(x0s, y0s);
@@ -966,6 +977,68 @@ struct Solver {
     if (rc && nq) HIPCHK(hipMemcpyAsync(rc, rc_ext + c0, sizeof(double) * (size_t)nq, kind, stream));
     sync();
     if (res) *res = last[q];
+  }
+
+  // Reference snapshots: k slots per instance (k = 0: off) for the restart points of later solves
+  // whose relative KKT error is at most rel_tol. Replaces the ring (and what it held); the interval
+  // graph is captured again with or without the snapshot kernels.
+  void set_snapshots(int32_t k, double rel_tol) {
+    if (k < 0 || std::isnan(rel_tol)) raise(PDLP_ERR_ARG, "snapshots: k must be >= 0 and rel_tol not NaN");
+    sync();
+    for (void *q : {(void *)snap.x, (void *)snap.y, (void *)snap.attempt, (void *)snap.rel, (void *)snap.taken,
+                    (void *)snap.slot})
+      if (q) mem.release(q);
+    snap = Snap{};
+    if (graph) {
+      HIPCHK(hipGraphExecDestroy(graph));
+      graph = nullptr;
+    }
+    if (k == 0) return;
+    snap.x = mem.alloc<double>((int64_t)k * n);
+    snap.y = mem.alloc<double>((int64_t)k * m);
+    snap.attempt = mem.alloc<int64_t>((int64_t)K * k);
+    snap.rel = mem.alloc<double>((int64_t)K * k);
+    snap.taken = mem.alloc<int32_t>(K);
+    snap.slot = mem.alloc<int32_t>(K);
+    HIPCHK(hipMemsetAsync(snap.taken, 0, sizeof(int32_t) * (size_t)K, stream));
+    sync();
+    snap.K = k, snap.n = n, snap.m = m, snap.rel_tol = rel_tol;
+  }
+
+  // Snapshots of instance q held after the last solve, oldest first, in the caller's numbering: at
+  // most `cap` of them (the newest); *count = the number written.
+  void get_snapshots(int q, int32_t cap, double *x, double *y, int64_t *attempt, double *rel, int32_t *count) {
+    if (!solved) raise(PDLP_ERR_STATE, "snapshots before solve");
+    if (q < 0 || q >= K) raise(PDLP_ERR_ARG, "instance index out of range");
+    if (cap < 0 || !count) raise(PDLP_ERR_ARG, "snapshots: cap must be >= 0 and count not NULL");
+    *count = 0;
+    if (snap.K == 0 || cap == 0) return;
+    int32_t taken = 0;
+    std::vector<int64_t> h_att((size_t)snap.K);
+    std::vector<double> h_rel((size_t)snap.K);
+    download(&taken, snap.taken + q, 1);
+    download(h_att.data(), snap.attempt + (size_t)q * snap.K, snap.K);
+    download(h_rel.data(), snap.rel + (size_t)q * snap.K, snap.K);
+    sync();
+    const int32_t held = std::min(taken, snap.K), out = std::min(held, cap);
+    const hipMemcpyKind kind = opt.device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const int32_t c0 = h_col0[q], nq = h_col0[q + 1] - c0, r0 = h_row0[q], mq = h_row0[q + 1] - r0;
+    for (int32_t i = 0; i < out; ++i) {
+      const int32_t s = (taken - out + i) % snap.K;  // oldest of the newest `out` first
+      if (attempt) attempt[i] = h_att[(size_t)s];
+      if (rel) rel[i] = h_rel[(size_t)s];
+      if (x && nq) {
+        gather64(n, snap.x + (size_t)s * n, d_inv_c, stage_n);  // internal -> external numbering
+        HIPCHK(hipMemcpyAsync(x + (size_t)i * nq, stage_n + c0, sizeof(double) * (size_t)nq, kind, stream));
+      }
+      if (y && mq) {
+        gather64(m, snap.y + (size_t)s * m, d_inv_r, stage_m);
+        HIPCHK(hipMemcpyAsync(y + (size_t)i * mq, stage_m + r0, sizeof(double) * (size_t)mq, kind, stream));
+      }
+    }
+    HIPCHK(hipGetLastError());
+    sync();
+    *count = out;
   }
 
   // Original-space product y = A x = Dr^-1 A~ Dc^-1 x (trans = 0) or y = A'x (trans = 1), in the
@@ -1356,6 +1429,40 @@ int pdlp_batch_update_bounds(pdlp_batch *bt, int32_t i, const double *l, const d
     return PDLP_ERR_ARG;
   }
   return guarded([&] { bt->s.visit([&](auto &s) { s.update_bounds(i, l, u); }); });
+}
+
+int pdlp_set_snapshots(pdlp_problem *p, int32_t k, double rel_tol) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { s.set_snapshots(k, rel_tol); }); });
+}
+
+int pdlp_get_snapshots(pdlp_problem *p, int32_t cap, double *x, double *y, int64_t *attempt, double *rel_kkt,
+                       int32_t *count) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { p->s.visit([&](auto &s) { s.get_snapshots(0, cap, x, y, attempt, rel_kkt, count); }); });
+}
+
+int pdlp_batch_set_snapshots(pdlp_batch *bt, int32_t k, double rel_tol) {
+  if (!bt) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { bt->s.visit([&](auto &s) { s.set_snapshots(k, rel_tol); }); });
+}
+
+int pdlp_batch_get_snapshots(pdlp_batch *bt, int32_t i, int32_t cap, double *x, double *y, int64_t *attempt,
+                             double *rel_kkt, int32_t *count) {
+  if (!bt) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] { bt->s.visit([&](auto &s) { s.get_snapshots(i, cap, x, y, attempt, rel_kkt, count); }); });
 }
 
 void pdlp_batch_destroy(pdlp_batch *bt) { delete bt; }

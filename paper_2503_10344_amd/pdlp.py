@@ -64,7 +64,8 @@ EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdl
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
            "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy", "pdlp_update_bounds",
            "pdlp_batch_update_bounds", "pdlp_variable_strategy",
-           "pdlp_lp_fixing", "pdlp_prop_create", "pdlp_propagate", "pdlp_prop_destroy", "pdlp_branching"]
+           "pdlp_lp_fixing", "pdlp_prop_create", "pdlp_propagate", "pdlp_prop_destroy", "pdlp_branching",
+           "pdlp_set_snapshots", "pdlp_get_snapshots", "pdlp_batch_set_snapshots", "pdlp_batch_get_snapshots"]
 
 _lib = None
 
@@ -164,6 +165,15 @@ def load(path: str = LIB_PATH):
     lib.pdlp_prop_destroy.restype = None
     lib.pdlp_branching.argtypes = [dp, dp, dp, dp, vp, vp, C.POINTER(i32)]
     lib.pdlp_branching.restype = C.c_int
+    # reference snapshots
+    lib.pdlp_set_snapshots.argtypes = [vp, i32, dp]
+    lib.pdlp_set_snapshots.restype = C.c_int
+    lib.pdlp_batch_set_snapshots.argtypes = [vp, i32, dp]
+    lib.pdlp_batch_set_snapshots.restype = C.c_int
+    lib.pdlp_get_snapshots.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(i32)]
+    lib.pdlp_get_snapshots.restype = C.c_int
+    lib.pdlp_batch_get_snapshots.argtypes = [vp, i32, i32, vp, vp, vp, vp, C.POINTER(i32)]
+    lib.pdlp_batch_get_snapshots.restype = C.c_int
     _lib = lib
     return lib
 
@@ -270,6 +280,25 @@ class Solution:
     info: dict
 
 
+@dataclass
+class Snapshots:
+    """Restart points of a solve kept as reference solutions, oldest first (original space)."""
+    x: np.ndarray        # [count, n]
+    y: np.ndarray        # [count, m]
+    attempt: np.ndarray  # [count] attempt count at which each was taken
+    rel_kkt: np.ndarray  # [count] relative KKT error as the solve measured it
+
+
+def _get_snapshots(call, cap, n, m) -> Snapshots:
+    """call(cap, x, y, attempt, rel, count) for one instance; host arrays."""
+    x, y = np.zeros((cap, n)), np.zeros((cap, m))
+    att, rel = np.zeros(cap, np.int64), np.zeros(cap)
+    cnt = C.c_int32(0)
+    _check(call(int(cap), _ptr(x), _ptr(y), _ptr(att), _ptr(rel), C.byref(cnt)))
+    k = cnt.value
+    return Snapshots(x[:k].copy(), y[:k].copy(), att[:k].copy(), rel[:k].copy())
+
+
 class Problem:
     """A solver handle for one LP (generators.LP or any object with the same fields)."""
 
@@ -298,6 +327,16 @@ class Problem:
         y = np.zeros(self.n if trans else self.m)
         pdlp_spmv(self.h, 1 if trans else 0, x, y)
         return y
+
+    def set_snapshots(self, k, rel_tol):
+        """Keep the newest k restart points with relative KKT error <= rel_tol in later solves."""
+        _check(load().pdlp_set_snapshots(self.h, int(k), float(rel_tol)))
+        self.snap_k = int(k)
+
+    def snapshots(self, cap=None) -> Snapshots:
+        cap = getattr(self, "snap_k", 0) if cap is None else cap
+        lib = load()
+        return _get_snapshots(lambda *a: lib.pdlp_get_snapshots(self.h, *a), cap, self.n, self.m)
 
     def scaling(self):
         Dr, Dc, sv = np.zeros(self.m), np.zeros(self.n), np.zeros(self.nnz)
@@ -453,6 +492,17 @@ class Batch:
         x, y, rc = np.zeros(n), np.zeros(m), np.zeros(n)
         r = pdlp_batch_get(self.h, i, x, y, rc)
         return Solution(x, y, rc, r.as_dict())
+
+    def set_snapshots(self, k, rel_tol):
+        """Keep the newest k restart points with relative KKT error <= rel_tol per instance."""
+        _check(load().pdlp_batch_set_snapshots(self.h, int(k), float(rel_tol)))
+        self.snap_k = int(k)
+
+    def snapshots(self, i, cap=None) -> Snapshots:
+        m, n = self.dims[i]
+        cap = getattr(self, "snap_k", 0) if cap is None else cap
+        lib = load()
+        return _get_snapshots(lambda *a: lib.pdlp_batch_get_snapshots(self.h, int(i), *a), cap, n, m)
 
     def update_bounds(self, i, l, u):
         """New column bounds of instance i for the next batched solve."""

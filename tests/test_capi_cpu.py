@@ -157,6 +157,10 @@ def test_null_arguments(lib):
     assert lib.pdlp_lp_fixing(None, None, None, None, None, None, None) == -1
     assert lib.pdlp_prop_create(None, 1, 1, 0, None, None, None, None, None, None, None) == -1
     assert lib.pdlp_propagate(None, None, None, 10, None, None) == -1
+    assert lib.pdlp_set_snapshots(None, 4, 1e-3) == -1
+    assert lib.pdlp_batch_set_snapshots(None, 4, 1e-3) == -1
+    assert lib.pdlp_get_snapshots(None, 4, None, None, None, None, C.byref(cnt)) == -1
+    assert lib.pdlp_batch_get_snapshots(None, 0, 4, None, None, None, None, C.byref(cnt)) == -1
 
 
 def test_branching_rule_matches_oracle(lib):
