@@ -11,6 +11,7 @@
   the one the solve measured, and the points respect bounds and dual signs.
 """
 import copy
+import ctypes
 import sys
 
 import numpy as np
@@ -133,8 +134,8 @@ def test_ring_batch_and_errors(pdlp):
         bt.set_snapshots(2, np.inf)
         bt.solve(tol=0.0, iter_limit=1024)
         got2 = [bt.snapshots(i) for i in range(3)]
-        with pytest.raises(pdlp.PDLPError):
-            bt.snapshots(3)
+        cnt = ctypes.c_int32(0)  # instance index out of range, through the C ABI
+        assert pdlp.load().pdlp_batch_get_snapshots(bt.h, 3, 4, None, None, None, None, ctypes.byref(cnt)) == -1
     for i, lp in enumerate(lps):
         with pdlp.Problem(lp, precision="fp32", tile_nnz=1024) as p:
             p.set_snapshots(8, np.inf)
@@ -157,8 +158,8 @@ def test_ring_batch_and_errors(pdlp):
             p.set_snapshots(4, np.nan)
         p.set_snapshots(4, 1e-3)
         p.solve(tol=1e-4)
-        with pytest.raises(pdlp.PDLPError):
-            p.snapshots(cap=-1)
+        cnt = ctypes.c_int32(0)  # negative cap, through the C ABI
+        assert pdlp.load().pdlp_get_snapshots(p.h, -1, None, None, None, None, ctypes.byref(cnt)) == -1
         p.set_snapshots(0, 1e-3)              # off: the next solve keeps none
         p.solve(tol=1e-4)
         assert p.snapshots(cap=4).attempt.size == 0
