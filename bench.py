@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "42b2a280b162a101e3085ee3c7744e1cada89bb8"): 437_179_571,
-    ("energy", "42b2a280b162a101e3085ee3c7744e1cada89bb8"): 458_797_736,
+    ("zipf", "95eb97c992f18ce8f5317fa75b8edb351273e1bd"): 437_058_631,
+    ("energy", "95eb97c992f18ce8f5317fa75b8edb351273e1bd"): 458_773_606,
 }
 
 
