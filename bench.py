@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "95eb97c992f18ce8f5317fa75b8edb351273e1bd"): 437_058_631,
-    ("energy", "95eb97c992f18ce8f5317fa75b8edb351273e1bd"): 458_773_606,
+    ("zipf", "cd28d62c27391b2e4e2536f56998838b16028e40"): 436_938_071,
+    ("energy", "cd28d62c27391b2e4e2536f56998838b16028e40"): 460_385_529,
 }
 
 
@@ -52,15 +52,18 @@ def algorithmic_bytes(kernel, m, n, nnz, tb):
     dual   (A x' + dual update): A values + columns, row offsets, gather of x', read y, ax, b and
            the row senses, write y' and ax'.
     primal (A'y' + primal update + averages, accepted attempt): A' values + columns, row offsets,
-           gather of y', write A'y', read x, c, l, u, write x', read+write x-bar, read y and
-           read+write y-bar (the averages are FP64, 8 bytes, in both precisions); in FP64 also
-           read+write A'y-bar and A x-bar and read A x (FP32 recomputes those two products before
-           each evaluation instead).
+           gather of y', write A'y', read x, c, l, u, write x', and the FP64 averages. FP32 pairs
+           the average updates of consecutive accepted attempts: one attempt of a pair leaves them
+           alone, the other reads the older x and y and reads + writes x-bar and y-bar once, i.e.
+           per accepted attempt (16 + 4) / 2 = 10 bytes per column and (16 + 2 * 4) / 2 = 12 per
+           row. FP64 updates every attempt (read+write x-bar, read y, read+write y-bar) and also
+           reads+writes A'y-bar and A x-bar and reads A x (FP32 recomputes those two products
+           before each evaluation instead).
     """
     if kernel == "dual":
         return nnz * (tb + 4) + 4 * (m + 1) + tb * n + m * (5 * tb + 1)
     if tb == 4:
-        return nnz * (tb + 4) + 4 * (n + 1) + tb * m + (6 * tb + 16) * n + (tb + 16) * m
+        return nnz * (tb + 4) + 4 * (n + 1) + tb * m + (6 * tb + 10) * n + 12 * m
     return nnz * (tb + 4) + 4 * (n + 1) + tb * m + 10 * tb * n + 6 * tb * m
 
 

@@ -698,12 +698,14 @@ struct Solver {
     launch_restart();
     if (snap.K > 0) hipLaunchKernelGGL(k_snap_copy<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P, snap);
   }
-  // In FP32 the products of the averages, kept up to date by the same weighted updates as the
-  // averages themselves, drift from A x-bar and A'y-bar by accumulated rounding; they are
-  // recomputed before each evaluation so that the average's KKT error, and the caches a restart to
-  // the average hands on, are those of the averaged point itself. (FP64 keeps the updates.)
+  // Before each evaluation: the average update an accepted attempt may have left pending (paired
+  // updates), then, in FP32, the products of the averages. Kept up to date by the same weighted
+  // updates as the averages themselves, they would drift from A x-bar and A'y-bar by accumulated
+  // rounding; recomputed, the average's KKT error and the caches a restart to the average hands on
+  // are those of the averaged point itself. (FP64 keeps the updates.)
   void refresh_averages() {
     if constexpr (sizeof(T) == sizeof(float)) {
+      hipLaunchKernelGGL(k_avg_flush<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P);
       spmv_chunks<T, double, T, T>(0, xbar, axbar);
       spmv_chunks<T, double, T, T>(1, ybar, atybar);
     }
@@ -832,6 +834,9 @@ struct Solver {
       s.iter_limit = iter_limit;
       s.eval_every = opt.eval_every;
       s.restart_mode = kToCurrent;
+      // FP32 pairs the average updates of consecutive accepted attempts (FP64 also updates the
+      // averages' products in k_primal and keeps one update per attempt)
+      s.pair_avg = sizeof(T) == sizeof(float) ? 1 : 0;
     }
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));

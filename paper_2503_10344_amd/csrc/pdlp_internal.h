@@ -22,6 +22,11 @@ constexpr int kEvalSpan = 2048;    // elements per evaluation block (target)
 
 enum RestartMode : int32_t { kNoRestart = 0, kToCurrent = 1, kToAverage = 2 };
 enum EvalMode : int32_t { kEvalInit = 0, kEvalChunk = 1, kEvalPoint = 2 };
+// What k_primal does to the running averages on an accepted attempt. With paired updates (FP32),
+// every other accepted attempt leaves its update pending and the next one applies both in one pass
+// over x-bar and y-bar (the older iterate is still in the other buffer then); the operations and
+// their order are those of two single updates, so the averages are bitwise the same.
+enum AvgMode : int32_t { kAvgOne = 0, kAvgDefer = 1, kAvgPair = 2 };
 
 // Per-instance solver state on the device. Written only by the last block of an instance in a
 // kernel (or by the host between solves); read by every block of that instance at kernel start.
@@ -29,7 +34,9 @@ struct State {
   double eta;         // step size of the next attempt (scaled space)
   double omega;       // primal weight
   double wsum;        // sum of accepted step sizes since the last restart
-  double avg_w;       // weight eta/wsum of the pending average update
+  double avg_w;       // weight eta/wsum of the newest accepted attempt's average update
+  double avg_w1;      // paired update: weight of the older accepted attempt (applied first)
+  double pend_w;      // paired updates: weight of an accepted attempt whose update waits (0: none)
   double dx2;         // |x' - x|^2 of the pending primal candidate
   double kkt_anchor;  // weighted KKT error of the last restart point
   double kkt_prev;    // weighted KKT error of the previous restart candidate
@@ -49,6 +56,8 @@ struct State {
   int32_t restarts;
   int32_t restart_mode;
   int32_t eval_every;
+  int32_t avg_mode;   // AvgMode of the last accepted attempt
+  int32_t pair_avg;   // 1: pair the average updates of consecutive accepted attempts
   int32_t pad_;
 };
 

@@ -377,7 +377,14 @@ __device__ inline void step_size_rule(State *st, int32_t *ndone, double dx2, dou
   if (eta <= eta_bar) {
     st->cur ^= 1;
     st->wsum += eta;
-    st->avg_w = eta / st->wsum;
+    const double w = eta / st->wsum;
+    if (!st->pair_avg) {
+      st->avg_w = w, st->avg_mode = kAvgOne;
+    } else if (st->pend_w > 0.0) {
+      st->avg_w1 = st->pend_w, st->avg_w = w, st->pend_w = 0.0, st->avg_mode = kAvgPair;
+    } else {
+      st->pend_w = w, st->avg_mode = kAvgDefer;
+    }
     st->commit = 1;
   } else {
     st->commit = 0;
@@ -463,6 +470,10 @@ __global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__r
 // A'y_bar over the block's columns; y_bar, A x_bar over its share of the rows); then the primal
 // candidate of the next attempt x' = proj_[l,u](x - tau (c - A'y)), tau = eta / omega, and its
 // |x' - x|^2 partial sum. Grid: the A'-side work blocks of all instances.
+// With paired averages (avg_mode) a deferred attempt leaves x_bar / y_bar alone, and the next
+// accepted one applies the older update (its iterate is still in the other buffer: rejected
+// candidates never overwrite the committed iterate) and then its own, per element, before the
+// candidate of the next attempt overwrites that buffer.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
@@ -472,7 +483,9 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   const int cur = st->cur, commit = st->commit, stop = st->stop;
   const T tau = T(st->eta / st->omega);
   const T wa = T(st->avg_w);
-  const double wad = st->avg_w;
+  const double wad = st->avg_w, wd1 = st->avg_w1;
+  const int amode = st->avg_mode;
+  const bool avg_now = commit && amode != kAvgDefer;  // x_bar / y_bar change in this launch
   const T *__restrict__ xc = P.x[cur];
   T *__restrict__ xnx = P.x[cur ^ 1];
   const T *__restrict__ yc = P.y[cur];
@@ -491,10 +504,17 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   // FP64 keeps A'y-bar and A x-bar current with the averages' weighted updates; FP32 recomputes
   // both before each evaluation (the only readers), so it skips them here.
   constexpr bool kTrack = sizeof(T) == sizeof(double);
-  auto fetch = [&](int j) { return PrimalPre{xc[j], c[j], lo[j], hi[j], xbar[j], kTrack ? atybar[j] : T(0)}; };
+  auto fetch = [&](int j) {
+    return PrimalPre{xc[j], c[j], lo[j], hi[j], avg_now ? xbar[j] : 0.0, kTrack ? atybar[j] : T(0)};
+  };
   auto primal = [&](int j, T atyj, const PrimalPre &q) {
     if (commit) {
-      xbar[j] = q.xbar + wad * (double(q.x) - q.xbar);
+      if (amode == kAvgOne) {
+        xbar[j] = q.xbar + wad * (double(q.x) - q.xbar);
+      } else if (amode == kAvgPair) {
+        const double t = q.xbar + wd1 * (double(xnx[j]) - q.xbar);
+        xbar[j] = t + wad * (double(q.x) - t);
+      }
       if (kTrack) atybar[j] = q.atybar + wa * (atyj - q.atybar);
     }
     if (!stop) {
@@ -513,13 +533,21 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
                             primal(j, s, q);
                           });
     const T *__restrict__ axc = P.ax[cur];
+    const T *__restrict__ yprev = P.y[cur ^ 1];  // the older accepted y of a paired update
     double *__restrict__ ybar = P.ybar;
     T *__restrict__ axbar = P.axbar;
     int rb, re;
     share(P.L.row0[w.inst], P.L.row0[w.inst + 1] - P.L.row0[w.inst], w.lb, w.nb, &rb, &re);
-    for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-      ybar[i] += wad * (double(yc[i]) - ybar[i]);
-      if (kTrack) axbar[i] += wa * (axc[i] - axbar[i]);
+    if (avg_now || kTrack) {
+      for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
+        if (amode == kAvgOne) {
+          ybar[i] += wad * (double(yc[i]) - ybar[i]);
+        } else if (amode == kAvgPair) {
+          const double t = ybar[i] + wd1 * (double(yprev[i]) - ybar[i]);
+          ybar[i] = t + wad * (double(yc[i]) - t);
+        }
+        if (kTrack) axbar[i] += wa * (axc[i] - axbar[i]);
+      }
     }
   } else if (!stop && ce > cb) {
     const int j0 = P.t_chunk_row[cb], j1 = P.t_chunk_row[ce];
@@ -689,7 +717,30 @@ __global__ __launch_bounds__(kBlock) void k_eval_fin(Layout L, const double *__r
   if (st->done) return;
   double tot[kEvalNV];
   final_sum<kEvalNV>(p_eval, L.ev_blk0[blockIdx.x], L.ev_blk0[blockIdx.x + 1], tot);
-  if (threadIdx.x == 0) eval_logic(st, ndone, tot, mode);
+  if (threadIdx.x == 0) {
+    st->pend_w = 0.0;  // k_avg_flush has applied a pending average update before this evaluation
+    eval_logic(st, ndone, tot, mode);
+  }
+}
+
+// Before an evaluation reads the averages: apply the update an accepted attempt left pending
+// (paired averages). No accepted attempt followed it, so its iterate is the committed one.
+// Grid: the evaluation blocks.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_avg_flush(Iter<T> P) {
+  const EvBlock E = ev_block(P.L);
+  const State *st = P.st + E.inst;
+  if (st->done) return;
+  const double w = st->pend_w;
+  if (!(w > 0.0)) return;
+  const int cur = st->cur;
+  const T *__restrict__ xc = P.x[cur];
+  const T *__restrict__ yc = P.y[cur];
+  const int gs = E.nlb * kBlock, off = E.lb * kBlock + (int)threadIdx.x;
+  for (int j = P.L.col0[E.inst] + off; j < P.L.col0[E.inst + 1]; j += gs)
+    P.xbar[j] = P.xbar[j] + w * (double(xc[j]) - P.xbar[j]);
+  for (int i = P.L.row0[E.inst] + off; i < P.L.row0[E.inst + 1]; i += gs)
+    P.ybar[i] += w * (double(yc[i]) - P.ybar[i]);
 }
 
 // ----------------------------------------------------------------------------------------------
