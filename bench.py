@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "cd28d62c27391b2e4e2536f56998838b16028e40"): 436_938_071,
-    ("energy", "cd28d62c27391b2e4e2536f56998838b16028e40"): 460_385_529,
+    ("zipf", "559c26fcdb22bba819dd3cee4d0cf2d8a84f9d53"): 437_886_088,
+    ("energy", "559c26fcdb22bba819dd3cee4d0cf2d8a84f9d53"): 458_645_003,
 }
 
 

@@ -403,6 +403,9 @@ __device__ inline void step_size_rule(State *st, int32_t *ndone, double dx2, dou
 // q in [a_lo, a_hi), and |dx|^2 over p_dx[q], q in [t_lo, t_hi). Each sum keeps the order of a
 // single strided reduction (four accumulators per thread over q, q + B, q + 2B, q + 3B, a wave
 // tree, then the waves in order), so the three loads chains overlap without changing any result.
+// The partials were written by blocks on every XCD, so each load goes to memory: a thread first
+// issues sixteen strides' loads and only then adds them, in the same order (accumulator u takes
+// strides u, u + 4, u + 8, u + 12), to pay one round trip per sixteen strides instead of per four.
 // Results valid in thread 0.
 constexpr int kStepBlock = 1024;
 __device__ __forceinline__ void step_sums(const double *__restrict__ p_dual, int a_lo, int a_hi,
@@ -411,6 +414,17 @@ __device__ __forceinline__ void step_sums(const double *__restrict__ p_dual, int
   constexpr int B = kStepBlock;
   double a[3][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
   int q = a_lo + (int)threadIdx.x;
+  for (; q + 15 * B < a_hi; q += 16 * B) {
+    double v0[16], v1[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      v0[t] = p_dual[2 * (size_t)(q + t * B)];
+      v1[t] = p_dual[2 * (size_t)(q + t * B) + 1];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load above the first add
+#pragma unroll
+    for (int t = 0; t < 16; ++t) a[0][t & 3] += v0[t], a[1][t & 3] += v1[t];
+  }
   for (; q + 3 * B < a_hi; q += 4 * B) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -420,6 +434,14 @@ __device__ __forceinline__ void step_sums(const double *__restrict__ p_dual, int
   }
   for (; q < a_hi; q += B) a[0][0] += p_dual[2 * (size_t)q], a[1][0] += p_dual[2 * (size_t)q + 1];
   q = t_lo + (int)threadIdx.x;
+  for (; q + 15 * B < t_hi; q += 16 * B) {
+    double v2[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v2[t] = p_dx[q + t * B];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) a[2][t & 3] += v2[t];
+  }
   for (; q + 3 * B < t_hi; q += 4 * B) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) a[2][u] += p_dx[q + u * B];
