@@ -28,8 +28,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # its launch configuration are built from; any change to them makes the figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "559c26fcdb22bba819dd3cee4d0cf2d8a84f9d53"): 437_886_088,
-    ("energy", "559c26fcdb22bba819dd3cee4d0cf2d8a84f9d53"): 458_645_003,
+    ("zipf", "00dca0defda824aa8625a8477725300a5fb560d4"): 436_974_037,
+    ("energy", "00dca0defda824aa8625a8477725300a5fb560d4"): 460_483_544,
 }
 
 

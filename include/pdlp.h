@@ -79,7 +79,10 @@ typedef struct pdlp_options {
   int32_t work_blocks;     /* most blocks per SpMV kernel for one instance (each block owns a
                               contiguous run of chunks; an instance gets one block per 1024 nonzeros
                               + rows up to this count); 0 = 16384 (default 0) */
-  int32_t reserved[5];
+  int32_t single_avg_updates; /* FP32 pairs the running-average updates of consecutive accepted
+                              attempts (one pass over x-bar and y-bar for two updates); 1 = update on
+                              every accepted attempt instead. Both give the same bits (default 0) */
+  int32_t reserved[4];
 } pdlp_options;
 
 typedef struct pdlp_result {

@@ -836,7 +836,7 @@ struct Solver {
       s.restart_mode = kToCurrent;
       // FP32 pairs the average updates of consecutive accepted attempts (FP64 also updates the
       // averages' products in k_primal and keeps one update per attempt)
-      s.pair_avg = sizeof(T) == sizeof(float) ? 1 : 0;
+      s.pair_avg = (sizeof(T) == sizeof(float) && !opt.single_avg_updates) ? 1 : 0;
     }
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));

@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("pock_chambolle", C.c_int32), ("use_graphs", C.c_int32), ("device_ptrs", C.c_int32),
                 ("tile_nnz", C.c_int32), ("verbose", C.c_int32), ("device_mem_limit", C.c_int64),
                 ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("kernel_timing", C.c_int32),
-                ("work_blocks", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("work_blocks", C.c_int32), ("single_avg_updates", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Result(C.Structure):
@@ -211,7 +211,7 @@ def _ptr(a):
 
 def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
             device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
-            warm_fallback=True, kernel_timing=False, work_blocks=0) -> Options:
+            warm_fallback=True, kernel_timing=False, work_blocks=0, single_avg_updates=False) -> Options:
     o = Options()
     load().pdlp_options_default(C.byref(o))
     o.precision = FP64 if str(precision).lower() in ("fp64", "f64", "double", "1") else FP32
@@ -226,6 +226,7 @@ def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True,
     o.warm_fallback = 1 if warm_fallback else 0
     o.kernel_timing = 1 if kernel_timing else 0
     o.work_blocks = work_blocks
+    o.single_avg_updates = 1 if single_avg_updates else 0
     if stream is None:
         try:
             import torch

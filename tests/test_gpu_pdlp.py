@@ -306,6 +306,38 @@ def test_determinism(pdlp):
     assert a.info["iterations"] == b.info["iterations"]
 
 
+def test_paired_average_updates_are_bitwise_single_updates(pdlp):
+    """FP32 pairs the running-average updates of consecutive accepted attempts (one pass for two,
+    the older iterate read from the other buffer, a pending one applied before each evaluation);
+    the same operations in the same order must give the same bits as one update per attempt: to
+    tolerance (averages returned on some), at an iteration limit inside an evaluation interval
+    (an update left pending), and for a batch."""
+    cases = [(g.general_sparse(7, m=3000, n=6000, cap=1000), 1e-4, 400_000),
+             (g.energy(4, T=96, N=8, K=6, E=16), 1e-4, 400_000),
+             (g.multi_knapsack(1, m=150, n=400), 1e-6, 400_000),
+             (g.energy(1, T=24, N=5, K=3, E=8), 0.0, 1037)]
+    for lp, tol, lim in cases:
+        got = []
+        for single in (False, True):
+            with pdlp.Problem(lp, precision="fp32", single_avg_updates=single) as p:
+                info = p.solve(tol=tol, iter_limit=lim)
+                got.append((p.get(), info))
+        (a, ia), (b, ib) = got
+        say("paired vs single updates:", lp.name, ia["iterations"], ib["iterations"], "average returned",
+            ia["used_average"])
+        assert (ia["iterations"], ia["restarts"], ia["used_average"]) == (ib["iterations"], ib["restarts"], ib["used_average"])
+        assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y) and np.array_equal(a.rc, b.rc)
+    lps = g.batch(3, count=16)
+    out = []
+    for single in (False, True):
+        with pdlp.Batch(lps, precision="fp32", single_avg_updates=single) as bt:
+            infos = bt.solve(tol=1e-4)
+            out.append(([bt.get(i) for i in range(len(lps))], [f["iterations"] for f in infos]))
+    assert out[0][1] == out[1][1]
+    for sa, sb in zip(out[0][0], out[1][0]):
+        assert np.array_equal(sa.x, sb.x) and np.array_equal(sa.y, sb.y)
+
+
 def test_graphs_match_direct_launches(pdlp):
     lp = g.set_cover(2, m=800, n=2000)
     out = []
