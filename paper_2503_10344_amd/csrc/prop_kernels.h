@@ -92,9 +92,20 @@ __device__ __forceinline__ Activity activity_seq(int32_t k0, int32_t k1, const i
   return A;
 }
 
+// Lane t's value of v, for every lane (t uniform across the wave): a scalar read of that lane's
+// register, without the LDS permute a general shuffle takes.
+__device__ __forceinline__ int lane_value(int v, int t) { return __builtin_amdgcn_readlane(v, t); }
+__device__ __forceinline__ double lane_value(double v, int t) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned int lo = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)b, t);
+  const unsigned int hi = (unsigned int)__builtin_amdgcn_readlane((int)(unsigned int)(b >> 32), t);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // The same sum by a wave: each 64-element segment is loaded and multiplied by the lanes in parallel,
-// then every lane adds the segment's terms in row order (broadcast one lane at a time), so all lanes
-// end with the sequential sum's exact value without waiting on one gather per element.
+// then every lane adds the segment's terms in row order (broadcast one lane at a time by a scalar
+// read of that lane), so all lanes end with the sequential sum's exact value without waiting on one
+// gather per element.
 __device__ __forceinline__ Activity activity_wave(int32_t k0, int32_t k1, int lane, const int32_t *__restrict__ ci,
                                                   const double *__restrict__ val, const double *__restrict__ l,
                                                   const double *__restrict__ u) {
@@ -117,13 +128,12 @@ __device__ __forceinline__ Activity activity_wave(int32_t k0, int32_t k1, int la
     }
     const int cnt = min(64, k1 - seg);
     for (int t = 0; t < cnt; ++t) {
-      const int c = __shfl(code, t, 64);
-      const double qmin = __shfl(pmin, t, 64), qmax = __shfl(pmax, t, 64);
+      const int c = lane_value(code, t);
       if (c & 1) {
         if (c & 2) ++A.mininf;
-        else A.minf = (A.minf + qmin);
+        else A.minf = (A.minf + lane_value(pmin, t));
         if (c & 4) ++A.maxinf;
-        else A.maxf = (A.maxf + qmax);
+        else A.maxf = (A.maxf + lane_value(pmax, t));
       }
     }
   }
