@@ -20,7 +20,8 @@ struct pdlp_prop {
   int32_t nlong = 0;
   double *val = nullptr, *b = nullptr;
   uint8_t *sense = nullptr, *vt = nullptr;
-  double *l = nullptr, *u = nullptr, *ln = nullptr, *un = nullptr;  // current and next bounds
+  double *l = nullptr, *u = nullptr;  // the caller's bounds staged on the device
+  pdlp::prop::Bounds *lu = nullptr, *lun = nullptr;  // current and next bounds, by column
   int32_t *flags = nullptr;       // device: moved, row infeasible, bound crossed
   int32_t *h_flags = nullptr;     // pinned host copy
   ~pdlp_prop() {
@@ -100,7 +101,9 @@ int pdlp_prop_create(pdlp_prop **out, int32_t m, int32_t n, int64_t nnz, const i
     std::vector<uint8_t> sn(H.sense.begin(), H.sense.end());
     p->sense = pdlp::prop::upload_new(*p, sn);
     p->vt = pdlp::prop::upload_new(*p, vt);
-    for (double **q : {&p->l, &p->u, &p->ln, &p->un}) *q = p->mem.alloc<double>(n);
+    for (double **q : {&p->l, &p->u}) *q = p->mem.alloc<double>(n);
+    p->lu = p->mem.alloc<pdlp::prop::Bounds>(n);
+    p->lun = p->mem.alloc<pdlp::prop::Bounds>(n);
     p->flags = p->mem.alloc<int32_t>(3);
     HIPCHK(hipStreamSynchronize(p->stream));
     *out = p.release();
@@ -123,12 +126,14 @@ int pdlp_propagate(pdlp_prop *p, double *l, double *u, int32_t max_rounds, int32
     if (!dev_u)
       for (int j = 0; j < n; ++j)
         if (std::isnan(u[j])) pdlp::raise(PDLP_ERR_ARG, "bounds must not be NaN");
+    // device bounds are read and written in place; host bounds go through the staging arrays
+    double *dl = dev_l ? l : p->l, *du = dev_u ? u : p->u;
     if (n > 0) {
       const size_t bytes = sizeof(double) * (size_t)n;
-      HIPCHK(hipMemcpyAsync(p->l, l, bytes, dev_l ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(p->u, u, bytes, dev_u ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(p->ln, p->l, bytes, hipMemcpyDeviceToDevice, st));
-      HIPCHK(hipMemcpyAsync(p->un, p->u, bytes, hipMemcpyDeviceToDevice, st));
+      if (!dev_l) HIPCHK(hipMemcpyAsync(p->l, l, bytes, hipMemcpyHostToDevice, st));
+      if (!dev_u) HIPCHK(hipMemcpyAsync(p->u, u, bytes, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_prop_pack, dim3(prop_grid(n)), dim3(kPropBlock), 0, st, n, (const double *)dl,
+                         (const double *)du, p->lu, p->lun);
     }
     int32_t r = 0, stat = PDLP_PROP_ROUND_LIMIT;
     while (r < max_rounds) {
@@ -136,17 +141,16 @@ int pdlp_propagate(pdlp_prop *p, double *l, double *u, int32_t max_rounds, int32
       if (m > 0)
         hipLaunchKernelGGL(k_prop_round, dim3(prop_grid(m)), dim3(kPropBlock), 0, st, m, (const int32_t *)p->rp,
                            (const int32_t *)p->ci, (const double *)p->val, (const double *)p->b,
-                           (const uint8_t *)p->sense, (const uint8_t *)p->vt, (const double *)p->l,
-                           (const double *)p->u, p->ln, p->un, p->flags);
+                           (const uint8_t *)p->sense, (const uint8_t *)p->vt, (const Bounds *)p->lu, p->lun,
+                           p->flags);
       if (p->nlong > 0)
         hipLaunchKernelGGL(k_prop_round_long, dim3(prop_grid((int64_t)p->nlong * 64)), dim3(kPropBlock), 0, st,
                            p->nlong, (const int32_t *)p->long_rows, (const int32_t *)p->rp, (const int32_t *)p->ci,
                            (const double *)p->val, (const double *)p->b, (const uint8_t *)p->sense,
-                           (const uint8_t *)p->vt, (const double *)p->l, (const double *)p->u, p->ln, p->un,
-                           p->flags);
+                           (const uint8_t *)p->vt, (const Bounds *)p->lu, p->lun, p->flags);
       if (n > 0)
-        hipLaunchKernelGGL(k_prop_finish, dim3(prop_grid(n)), dim3(kPropBlock), 0, st, n, p->l, p->u,
-                           (const double *)p->ln, (const double *)p->un, p->flags);
+        hipLaunchKernelGGL(k_prop_finish, dim3(prop_grid(n)), dim3(kPropBlock), 0, st, n, p->lu,
+                           (const Bounds *)p->lun, p->flags);
       HIPCHK(hipGetLastError());
       HIPCHK(hipMemcpyAsync(p->h_flags, p->flags, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -162,8 +166,11 @@ int pdlp_propagate(pdlp_prop *p, double *l, double *u, int32_t max_rounds, int32
     }
     if (n > 0) {
       const size_t bytes = sizeof(double) * (size_t)n;
-      HIPCHK(hipMemcpyAsync(l, p->l, bytes, dev_l ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(u, p->u, bytes, dev_u ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+      hipLaunchKernelGGL(k_prop_unpack, dim3(prop_grid(n)), dim3(kPropBlock), 0, st, n, (const Bounds *)p->lu, dl,
+                         du);
+      HIPCHK(hipGetLastError());
+      if (!dev_l) HIPCHK(hipMemcpyAsync(l, p->l, bytes, hipMemcpyDeviceToHost, st));
+      if (!dev_u) HIPCHK(hipMemcpyAsync(u, p->u, bytes, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipStreamSynchronize(st));
     if (rounds) *rounds = r;

@@ -10,6 +10,9 @@
 // take a gain above 1e-3 max(1, |bound|). A second kernel then records whether a bound moved and
 // whether some lower bound passed its upper bound.
 //
+// A column's two bounds are kept together (Bounds, 16 bytes): a row reads both bounds of each of its
+// columns, so one 16-byte gather per nonzero replaces two 8-byte ones.
+//
 // Products and sums round separately: every function below switches floating-point contraction
 // off (HIP contracts a * b + c into a fused multiply-add by default, and that rounds once instead of
 // twice), so a row's activity is the same double as a plain sequential sum.
@@ -67,6 +70,10 @@ __device__ __forceinline__ double tighten_lower(double cur, double p, bool integ
 
 constexpr int kLongRow = 128;  // rows at least this long are handled by a whole wave
 
+struct alignas(16) Bounds {
+  double lo, hi;
+};
+
 struct Activity {
   double minf, maxf;   // finite parts of the minimum / maximum activity, summed in row order
   int mininf, maxinf;  // infinite terms
@@ -74,15 +81,16 @@ struct Activity {
 
 // Activities of row [k0, k1) by one thread: the plain sequential sum.
 __device__ __forceinline__ Activity activity_seq(int32_t k0, int32_t k1, const int32_t *__restrict__ ci,
-                                                 const double *__restrict__ val, const double *__restrict__ l,
-                                                 const double *__restrict__ u) {
+                                                 const double *__restrict__ val,
+                                                 const Bounds *__restrict__ lu) {
 #pragma clang fp contract(off)
   Activity A{0.0, 0.0, 0, 0};
   for (int32_t k = k0; k < k1; ++k) {
     const double a = val[k];
     if (a == 0.0) continue;
     const int32_t j = ci[k];
-    const double lo = l[j], hi = u[j];
+    const Bounds bj = lu[j];
+    const double lo = bj.lo, hi = bj.hi;
     const double tmin = a > 0.0 ? lo : hi, tmax = a > 0.0 ? hi : lo;
     if (isinf(tmin)) ++A.mininf;
     else A.minf = (A.minf + (a * tmin));
@@ -107,8 +115,8 @@ __device__ __forceinline__ double lane_value(double v, int t) {
 // read of that lane), so all lanes end with the sequential sum's exact value without waiting on one
 // gather per element.
 __device__ __forceinline__ Activity activity_wave(int32_t k0, int32_t k1, int lane, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ val, const double *__restrict__ l,
-                                                  const double *__restrict__ u) {
+                                                  const double *__restrict__ val,
+                                                  const Bounds *__restrict__ lu) {
 #pragma clang fp contract(off)
   Activity A{0.0, 0.0, 0, 0};
   for (int32_t seg = k0; seg < k1; seg += 64) {
@@ -119,7 +127,8 @@ __device__ __forceinline__ Activity activity_wave(int32_t k0, int32_t k1, int la
       const double a = val[k];
       if (a != 0.0) {
         const int32_t j = ci[k];
-        const double lo = l[j], hi = u[j];
+        const Bounds bj = lu[j];
+        const double lo = bj.lo, hi = bj.hi;
         const double tmin = a > 0.0 ? lo : hi, tmax = a > 0.0 ? hi : lo;
         code = 1 | (isinf(tmin) ? 2 : 0) | (isinf(tmax) ? 4 : 0);
         if (!isinf(tmin)) pmin = a * tmin;
@@ -147,8 +156,7 @@ __device__ __forceinline__ void prop_row(int64_t i, const Activity &A, int first
                                          const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                          const double *__restrict__ val, const double *__restrict__ b,
                                          const uint8_t *__restrict__ sense, const uint8_t *__restrict__ vt,
-                                         const double *__restrict__ l, const double *__restrict__ u, double *ln,
-                                         double *un, int32_t *flags) {
+                                         const Bounds *__restrict__ lu, Bounds *lun, int32_t *flags) {
 #pragma clang fp contract(off)
   const int32_t k0 = rp[i], k1 = rp[i + 1];
   const double minf = A.minf, maxf = A.maxf;
@@ -163,7 +171,8 @@ __device__ __forceinline__ void prop_row(int64_t i, const Activity &A, int first
     const double a = val[k];
     if (a == 0.0) continue;
     const int32_t j = ci[k];
-    const double lo = l[j], hi = u[j];
+    const Bounds bj = lu[j];
+    const double lo = bj.lo, hi = bj.hi;
     const bool integral = vt[j] != 0;
     if (le) {
       const double t = a > 0.0 ? lo : hi;
@@ -176,10 +185,10 @@ __device__ __forceinline__ void prop_row(int64_t i, const Activity &A, int first
         const double p = (bi - res) / a;
         if (a > 0.0) {
           const double q = tighten_upper(hi, p, integral);
-          if (q < hi) atomic_min_double(&un[j], q);
+          if (q < hi) atomic_min_double(&lun[j].hi, q);
         } else {
           const double q = tighten_lower(lo, p, integral);
-          if (q > lo) atomic_max_double(&ln[j], q);
+          if (q > lo) atomic_max_double(&lun[j].lo, q);
         }
       }
     }
@@ -194,10 +203,10 @@ __device__ __forceinline__ void prop_row(int64_t i, const Activity &A, int first
         const double p = (bi - res) / a;
         if (a > 0.0) {
           const double q = tighten_lower(lo, p, integral);
-          if (q > lo) atomic_max_double(&ln[j], q);
+          if (q > lo) atomic_max_double(&lun[j].lo, q);
         } else {
           const double q = tighten_upper(hi, p, integral);
-          if (q < hi) atomic_min_double(&un[j], q);
+          if (q < hi) atomic_min_double(&lun[j].hi, q);
         }
       }
     }
@@ -211,13 +220,13 @@ __global__ __launch_bounds__(kPropBlock) void k_prop_round(int m, const int32_t 
                                                            const double *__restrict__ b,
                                                            const uint8_t *__restrict__ sense,
                                                            const uint8_t *__restrict__ vt,
-                                                           const double *__restrict__ l, const double *__restrict__ u,
-                                                           double *ln, double *un, int32_t *flags) {
+                                                           const Bounds *__restrict__ lu, Bounds *lun,
+                                                           int32_t *flags) {
   for (int64_t i = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kPropBlock) {
     const int32_t k0 = rp[i], k1 = rp[i + 1];
     if (k1 - k0 >= kLongRow) continue;
-    const Activity A = activity_seq(k0, k1, ci, val, l, u);
-    prop_row(i, A, 0, 1, rp, ci, val, b, sense, vt, l, u, ln, un, flags);
+    const Activity A = activity_seq(k0, k1, ci, val, lu);
+    prop_row(i, A, 0, 1, rp, ci, val, b, sense, vt, lu, lun, flags);
   }
 }
 
@@ -229,35 +238,57 @@ __global__ __launch_bounds__(kPropBlock) void k_prop_round_long(int nlong, const
                                                                 const double *__restrict__ b,
                                                                 const uint8_t *__restrict__ sense,
                                                                 const uint8_t *__restrict__ vt,
-                                                                const double *__restrict__ l,
-                                                                const double *__restrict__ u, double *ln, double *un,
+                                                                const Bounds *__restrict__ lu, Bounds *lun,
                                                                 int32_t *flags) {
   const int lane = (int)threadIdx.x & 63;
   const int64_t wave0 = ((int64_t)blockIdx.x * kPropBlock + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * kPropBlock) >> 6;
   for (int64_t w = wave0; w < nlong; w += nwaves) {
     const int64_t i = rows[w];
-    const Activity A = activity_wave(rp[i], rp[i + 1], lane, ci, val, l, u);
-    prop_row(i, A, lane, 64, rp, ci, val, b, sense, vt, l, u, ln, un, flags);
+    const Activity A = activity_wave(rp[i], rp[i + 1], lane, ci, val, lu);
+    prop_row(i, A, lane, 64, rp, ci, val, b, sense, vt, lu, lun, flags);
   }
 }
 
 // After a round: flags[0] = 1 if a bound moved, flags[2] = 1 if some l > u + 1e-6; then the round's
-// result becomes the current bounds (l, u = ln, un), so both copies agree for the next round.
-__global__ __launch_bounds__(kPropBlock) void k_prop_finish(int n, double *__restrict__ l, double *__restrict__ u,
-                                                            const double *__restrict__ ln,
-                                                            const double *__restrict__ un, int32_t *flags) {
+// result becomes the current bounds (lu = lun), so both copies agree for the next round.
+__global__ __launch_bounds__(kPropBlock) void k_prop_finish(int n, Bounds *__restrict__ lu,
+                                                            const Bounds *__restrict__ lun, int32_t *flags) {
 #pragma clang fp contract(off)
   bool moved = false, crossed = false;
   for (int64_t j = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kPropBlock) {
-    const double a = ln[j], c = un[j];
-    moved |= a != l[j] || c != u[j];
-    crossed |= a > (c + kFeasTol);
-    l[j] = a;
-    u[j] = c;
+    const Bounds nx = lun[j], cu = lu[j];
+    moved |= nx.lo != cu.lo || nx.hi != cu.hi;
+    crossed |= nx.lo > (nx.hi + kFeasTol);
+    lu[j] = nx;
   }
-  if (moved) atomicOr(&flags[0], 1);
-  if (crossed) atomicOr(&flags[2], 1);
+  // one atomic per block at most (and none once the flag is set): a round that moves millions of
+  // bounds would otherwise queue one atomic per wave on the same address
+  const int any_moved = __syncthreads_or(moved ? 1 : 0), any_crossed = __syncthreads_or(crossed ? 1 : 0);
+  if (threadIdx.x == 0) {
+    if (any_moved && __hip_atomic_load(&flags[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      atomicOr(&flags[0], 1);
+    if (any_crossed) atomicOr(&flags[2], 1);
+  }
+}
+
+// Both bound copies from the caller's l, u at the start of a call, and back at its end.
+__global__ __launch_bounds__(kPropBlock) void k_prop_pack(int n, const double *__restrict__ l,
+                                                          const double *__restrict__ u, Bounds *__restrict__ lu,
+                                                          Bounds *__restrict__ lun) {
+  for (int64_t j = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kPropBlock) {
+    const Bounds v{l[j], u[j]};
+    lu[j] = v;
+    lun[j] = v;
+  }
+}
+__global__ __launch_bounds__(kPropBlock) void k_prop_unpack(int n, const Bounds *__restrict__ lu,
+                                                            double *__restrict__ l, double *__restrict__ u) {
+  for (int64_t j = (int64_t)blockIdx.x * kPropBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kPropBlock) {
+    const Bounds v = lu[j];
+    l[j] = v.lo;
+    u[j] = v.hi;
+  }
 }
 
 }  // namespace prop
