@@ -11,6 +11,9 @@ follow the published PDLP method; every constant is a reading):
   kkt       -- relative primal / dual / gap errors of a point on the unscaled LP (termination test)
   scale     -- Ruiz inf-norm passes then one Pock-Chambolle alpha = 1 pass
   pdhg_step -- one PDHG step on an unscaled LP
+  step_rule, restart_rule, primal_weight, kkt_weighted, initial_weight, initial_step -- the scalar
+               rules of the method (adaptive step, restart test, primal weight update, weighted KKT
+               error, start values), exactly the functions the solve calls
   spmv, transpose -- plain CSR product and counting-sort transpose
   propagate -- linear-constraint bound propagation in Jacobi rounds (prop_oracle.c; the paper uses
                the framework's linear-constraint propagator without defining it: a reading)
@@ -52,14 +55,15 @@ class _Opts(C.Structure):
                 ("x0", C.c_void_p), ("y0", C.c_void_p), ("omega0", C.c_double),
                 ("trace_x", C.c_void_p), ("trace_y", C.c_void_p), ("trace_eta", C.c_void_p),
                 ("trace_omega", C.c_void_p), ("trace_flags", C.c_void_p), ("trace_margin", C.c_void_p),
-                ("trace_cond", C.c_void_p)]
+                ("trace_cond", C.c_void_p), ("sum_order", C.c_int32), ("pad_", C.c_int32)]
 
 
 class _Res(C.Structure):
     _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
                 ("rel_p", C.c_double), ("rel_d", C.c_double), ("rel_gap", C.c_double),
                 ("pobj", C.c_double), ("dobj", C.c_double), ("omega", C.c_double),
-                ("eta", C.c_double), ("which", C.c_int32), ("pad", C.c_int32)]
+                ("eta", C.c_double), ("which", C.c_int32), ("pad", C.c_int32),
+                ("omega_init", C.c_double), ("eta_init", C.c_double)]
 
 
 _lib_cache: dict = {}
@@ -71,8 +75,11 @@ def load(path: str = LIB):
     if path == LIB and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
         build()
     lib = C.CDLL(path)
-    for name in ("orc_solve", "orc_kkt", "orc_scale", "orc_pdhg_step", "orc_num_threads"):
+    for name in ("orc_solve", "orc_kkt", "orc_scale", "orc_pdhg_step", "orc_num_threads", "orc_step_rule",
+                 "orc_restart_rule"):
         getattr(lib, name).restype = C.c_int
+    for name in ("orc_primal_weight", "orc_kkt_weighted", "orc_initial_weight", "orc_initial_step"):
+        getattr(lib, name).restype = C.c_double
     lib.orc_spmv.restype = None
     lib.orc_transpose.restype = None
     _lib_cache[path] = lib
@@ -111,6 +118,8 @@ class Result:
     y: np.ndarray
     rc: np.ndarray
     trace: dict | None = None
+    omega_init: float = 0.0
+    eta_init: float = 0.0
 
     @property
     def rel_kkt(self) -> float:
@@ -119,7 +128,9 @@ class Result:
 
 def solve(lp, tol: float = 1e-4, iter_limit: int = 1_000_000, ruiz_iters: int = 10,
           pock_chambolle: bool = True, eval_every: int = 64, x0=None, y0=None, omega0: float = 0.0,
-          trace_len: int = 0, lib_path: str = LIB) -> Result:
+          trace_len: int = 0, sum_order: int = 0, lib_path: str = LIB) -> Result:
+    """sum_order 1 takes every sum of the method in reverse index order (a different, equally valid
+    rounding of the same arithmetic)."""
     lib = load(lib_path)
     s, keep = _arrays(lp)
     x = np.zeros(lp.n)
@@ -135,13 +146,52 @@ def solve(lp, tol: float = 1e-4, iter_limit: int = 1_000_000, ruiz_iters: int = 
                   cond=np.ones(trace_len))
     o = _Opts(tol, iter_limit, ruiz_iters, 1 if pock_chambolle else 0, eval_every, trace_len,
               _p(x0a), _p(y0a), omega0,
-              *([_p(tr[k]) for k in ("x", "y", "eta", "omega", "flags", "margin", "cond")] if tr else [None] * 7))
+              *([_p(tr[k]) for k in ("x", "y", "eta", "omega", "flags", "margin", "cond")] if tr else [None] * 7),
+              int(sum_order), 0)
     r = _Res()
     rc_ = lib.orc_solve(C.byref(s), C.byref(o), _p(x), _p(y), _p(rc), C.byref(r))
     if rc_ != 0:
         raise MemoryError("oracle solve failed to allocate")
     return Result(r.status, r.iterations, r.restarts, r.rel_p, r.rel_d, r.rel_gap, r.pobj, r.dobj,
-                  r.omega, r.eta, r.which, x, y, rc, tr)
+                  r.omega, r.eta, r.which, x, y, rc, tr, r.omega_init, r.eta_init)
+
+
+def step_rule(omega, dx2, dy2, inter, eta, k, lib_path: str = LIB):
+    """The adaptive step-size rule after attempt k: (accepted, eta_bar, eta_new)."""
+    lib = load(lib_path)
+    eb, en = C.c_double(), C.c_double()
+    acc = lib.orc_step_rule(C.c_double(omega), C.c_double(dx2), C.c_double(dy2), C.c_double(inter),
+                            C.c_double(eta), C.c_int64(k), C.byref(eb), C.byref(en))
+    return bool(acc), eb.value, en.value
+
+
+def restart_rule(kkt_cur, kkt_avg, kkt_anchor, kkt_prev, t_since, k, lib_path: str = LIB):
+    """The restart decision at an evaluation: (restart, use_average, candidate KKT)."""
+    lib = load(lib_path)
+    ua, kc = C.c_int32(), C.c_double()
+    r = lib.orc_restart_rule(C.c_double(kkt_cur), C.c_double(kkt_avg), C.c_double(kkt_anchor),
+                             C.c_double(kkt_prev), C.c_int64(t_since), C.c_int64(k), C.byref(ua), C.byref(kc))
+    return bool(r), bool(ua.value), kc.value
+
+
+def primal_weight(omega, dx, dy, lib_path: str = LIB) -> float:
+    """The primal weight after a restart whose point lies dx, dy from the anchor."""
+    return float(load(lib_path).orc_primal_weight(C.c_double(omega), C.c_double(dx), C.c_double(dy)))
+
+
+def kkt_weighted(omega, rp2, rd2, gap, lib_path: str = LIB) -> float:
+    return float(load(lib_path).orc_kkt_weighted(C.c_double(omega), C.c_double(rp2), C.c_double(rd2),
+                                                 C.c_double(gap)))
+
+
+def initial_weight(omega0, norm_c_scaled, norm_b_scaled, lib_path: str = LIB) -> float:
+    return float(load(lib_path).orc_initial_weight(C.c_double(omega0), C.c_double(norm_c_scaled),
+                                                   C.c_double(norm_b_scaled)))
+
+
+def initial_step(scaled_val, lib_path: str = LIB) -> float:
+    v = np.ascontiguousarray(scaled_val, np.float64)
+    return float(load(lib_path).orc_initial_step(_p(v), C.c_int64(v.size)))
 
 
 def kkt(lp, x, y, lib_path: str = LIB) -> dict:

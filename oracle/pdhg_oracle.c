@@ -69,6 +69,11 @@ typedef struct {
   double *trace_margin; /* [trace_len] smallest relative margin of a discrete decision at attempt k */
   double *trace_cond;   /* [trace_len] 1 + |x|/|dx| + |y|/|dy| of attempt k (scaled space): the factor
                            by which relative errors of the iterates enter the step-size ratio */
+  int32_t sum_order;    /* 0: every sum in index order; 1: every sum (matrix rows, reductions, norms,
+                           scaling sums) in reverse index order. Any order is a valid evaluation of
+                           the same formulas; comparing the two measures how far rounding alone moves
+                           the iterates. */
+  int32_t pad_;
 } orc_opts;
 
 typedef struct {
@@ -78,6 +83,7 @@ typedef struct {
   double rel_p, rel_d, rel_gap, pobj, dobj, omega, eta;
   int32_t which;    /* 0 current iterate returned, 1 average */
   int32_t pad;
+  double omega_init, eta_init; /* primal weight and step size the first attempt started from (O2) */
 } orc_result;
 
 enum { ORC_OPTIMAL = 1, ORC_ITER_LIMIT = 2, ORC_NUMERICAL = 3 };
@@ -86,15 +92,28 @@ enum { ORC_OPTIMAL = 1, ORC_ITER_LIMIT = 2, ORC_NUMERICAL = 3 };
 /* Sparse helpers                                                                               */
 /* ------------------------------------------------------------------------------------------- */
 
-/* y = A x for A in CSR */
-void orc_spmv(int32_t m, const int32_t *rp, const int32_t *ci, const double *v, const double *x,
-              double *y) {
+/* Position t of a sum over [0, len) in index order (rev == 0) or in reverse order (rev == 1). */
+static int32_t ord(int32_t t, int32_t len, int rev) { return rev ? len - 1 - t : t; }
+
+/* y = A x for A in CSR; each row sum in the order `rev` selects */
+static void spmv_ord(int32_t m, const int32_t *rp, const int32_t *ci, const double *v, const double *x,
+                     double *y, int rev) {
 #pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < m; ++i) {
     double s = 0.0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * x[ci[k]];
+    const int32_t len = rp[i + 1] - rp[i];
+    for (int32_t t = 0; t < len; ++t) {
+      const int32_t k = rp[i] + ord(t, len, rev);
+      s += v[k] * x[ci[k]];
+    }
     y[i] = s;
   }
+}
+
+/* y = A x for A in CSR */
+void orc_spmv(int32_t m, const int32_t *rp, const int32_t *ci, const double *v, const double *x,
+              double *y) {
+  spmv_ord(m, rp, ci, v, x, y, 0);
 }
 
 /* CSR of A^T by counting sort: entries of each transposed row come in increasing row order of A. */
@@ -124,12 +143,14 @@ void orc_transpose(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci, c
  * 1-norm if use_sum == 1) of the current matrix, both taken before any entry changes.
  * Empty rows/columns use 1. Dr and Dc accumulate the divisions. */
 static void equilibrate_pass(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci, double *sv,
-                             double *Dr, double *Dc, int use_sum, double *rho, double *kap) {
+                             double *Dr, double *Dc, int use_sum, double *rho, double *kap, int rev) {
   int32_t nnz = rp[m];
   for (int32_t i = 0; i < m; ++i) rho[i] = 0.0;
   for (int32_t j = 0; j < n; ++j) kap[j] = 0.0;
-  for (int32_t i = 0; i < m; ++i)
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+  for (int32_t ti = 0; ti < m; ++ti)
+    for (int32_t tk = 0; tk < rp[ord(ti, m, rev) + 1] - rp[ord(ti, m, rev)]; ++tk) {
+      const int32_t i = ord(ti, m, rev);
+      const int32_t k = rp[i] + ord(tk, rp[i + 1] - rp[i], rev);
       double a = fabs(sv[k]);
       int32_t j = ci[k];
       if (use_sum) {
@@ -151,8 +172,8 @@ static void equilibrate_pass(int32_t m, int32_t n, const int32_t *rp, const int3
 
 /* Ruiz passes then (optionally) one Pock-Chambolle pass with alpha = 1.
  * Outputs Dr[m], Dc[n] and the scaled values sv[nnz] (A~ = Dr A Dc in the CSR pattern of A). */
-int orc_scale(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
-              int32_t ruiz_iters, int32_t pock_chambolle, double *Dr, double *Dc, double *sv) {
+static int scale_ord(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                     int32_t ruiz_iters, int32_t pock_chambolle, double *Dr, double *Dc, double *sv, int rev) {
   int32_t nnz = rp[m];
   double *rho = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
   double *kap = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -164,11 +185,16 @@ int orc_scale(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci, const 
   memcpy(sv, v, sizeof(double) * (size_t)nnz);
   for (int32_t i = 0; i < m; ++i) Dr[i] = 1.0;
   for (int32_t j = 0; j < n; ++j) Dc[j] = 1.0;
-  for (int32_t it = 0; it < ruiz_iters; ++it) equilibrate_pass(m, n, rp, ci, sv, Dr, Dc, 0, rho, kap);
-  if (pock_chambolle) equilibrate_pass(m, n, rp, ci, sv, Dr, Dc, 1, rho, kap);
+  for (int32_t it = 0; it < ruiz_iters; ++it) equilibrate_pass(m, n, rp, ci, sv, Dr, Dc, 0, rho, kap, rev);
+  if (pock_chambolle) equilibrate_pass(m, n, rp, ci, sv, Dr, Dc, 1, rho, kap, rev);
   free(rho);
   free(kap);
   return 0;
+}
+
+int orc_scale(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              int32_t ruiz_iters, int32_t pock_chambolle, double *Dr, double *Dc, double *sv) {
+  return scale_ord(m, n, rp, ci, v, ruiz_iters, pock_chambolle, Dr, Dc, sv, 0);
 }
 
 /* ------------------------------------------------------------------------------------------- */
@@ -202,9 +228,9 @@ static void pdhg_step(int32_t m, int32_t n, const int32_t *rp, const int32_t *ci
                       const double *c, const double *b, const uint8_t *sense, const double *l,
                       const double *u, const double *x, const double *y, const double *ax,
                       const double *aty, double tau, double sigma, double *xn, double *yn,
-                      double *axn) {
+                      double *axn, int rev) {
   for (int32_t j = 0; j < n; ++j) xn[j] = clip(x[j] - tau * (c[j] - aty[j]), l[j], u[j]);
-  orc_spmv(m, rp, ci, v, xn, axn);
+  spmv_ord(m, rp, ci, v, xn, axn, rev);
   for (int32_t i = 0; i < m; ++i) yn[i] = proj_y(y[i] + sigma * (b[i] - 2.0 * axn[i] + ax[i]), sense[i]);
 }
 
@@ -222,7 +248,7 @@ int orc_pdhg_step(const orc_lp *lp, const double *x, const double *y, double tau
   orc_spmv(m, lp->row_ptr, lp->col, lp->val, x, ax);
   orc_spmv(n, trp, tci, tv, y, aty);
   pdhg_step(m, n, lp->row_ptr, lp->col, lp->val, lp->c, lp->b, lp->sense, lp->l, lp->u, x, y, ax,
-            aty, tau, sigma, xn, yn, axn);
+            aty, tau, sigma, xn, yn, axn, 0);
   free(trp);
   free(tci);
   free(tv);
@@ -246,10 +272,11 @@ typedef struct {
 static residuals eval_residuals(int32_t m, int32_t n, const double *c, const double *b,
                                 const uint8_t *sense, const double *l, const double *u,
                                 const double *x, const double *y, const double *ax,
-                                const double *aty, const double *Dr, const double *Dc) {
+                                const double *aty, const double *Dr, const double *Dc, int rev) {
   residuals r = {0, 0, 0, 0, 0, 0};
   double by = 0.0, bound_terms = 0.0, cx = 0.0;
-  for (int32_t i = 0; i < m; ++i) {
+  for (int32_t ti = 0; ti < m; ++ti) {
+    const int32_t i = ord(ti, m, rev);
     double t = b[i] - ax[i];
     if (sense[i] == 'G') t = t > 0.0 ? t : 0.0;
     else if (sense[i] == 'L') t = t < 0.0 ? t : 0.0;
@@ -258,7 +285,8 @@ static residuals eval_residuals(int32_t m, int32_t n, const double *c, const dou
     r.rp2_orig += to * to;
     by += b[i] * y[i];
   }
-  for (int32_t j = 0; j < n; ++j) {
+  for (int32_t tj = 0; tj < n; ++tj) {
+    const int32_t j = ord(tj, n, rev);
     double g = c[j] - aty[j];
     double lam = proj_lambda(g, l[j], u[j]);
     double rd = g - lam;
@@ -274,9 +302,14 @@ static residuals eval_residuals(int32_t m, int32_t n, const double *c, const dou
   return r;
 }
 
+/* O4: KKT error weighted by the primal weight, sqrt(w^2 |r_p|^2 + |r_d|^2 / w^2 + gap^2), from the
+ * squared residual norms and the gap pobj - dobj (scaled space). */
+double orc_kkt_weighted(double omega, double rp2, double rd2, double gap) {
+  return sqrt(omega * omega * rp2 + rd2 / (omega * omega) + gap * gap);
+}
+
 static double kkt_weighted(const residuals *r, double omega) {
-  double gap = r->pobj - r->dobj;
-  return sqrt(omega * omega * r->rp2 + r->rd2 / (omega * omega) + gap * gap);
+  return orc_kkt_weighted(omega, r->rp2, r->rd2, r->pobj - r->dobj);
 }
 
 static void relative_errors(const residuals *r, double nb, double nc, double *rel_p, double *rel_d,
@@ -286,11 +319,12 @@ static void relative_errors(const residuals *r, double nb, double nc, double *re
   *rel_gap = fabs(r->pobj - r->dobj) / (1.0 + fabs(r->pobj) + fabs(r->dobj));
 }
 
-static double norm2(const double *v, int32_t len) {
+static double norm2_ord(const double *v, int32_t len, int rev) {
   double s = 0.0;
-  for (int32_t i = 0; i < len; ++i) s += v[i] * v[i];
+  for (int32_t t = 0; t < len; ++t) s += v[ord(t, len, rev)] * v[ord(t, len, rev)];
   return sqrt(s);
 }
+static double norm2(const double *v, int32_t len) { return norm2_ord(v, len, 0); }
 
 /* Relative errors of (x, y) on the unscaled problem:
  * out = {rel_p, rel_d, rel_gap, pobj, dobj, |r_p|, |r_d|}. */
@@ -304,7 +338,7 @@ int orc_kkt(const orc_lp *lp, const double *x, const double *y, double *out) {
   orc_transpose(m, n, lp->row_ptr, lp->col, lp->val, trp, tci, tv);
   orc_spmv(m, lp->row_ptr, lp->col, lp->val, x, ax);
   orc_spmv(n, trp, tci, tv, y, aty);
-  residuals r = eval_residuals(m, n, lp->c, lp->b, lp->sense, lp->l, lp->u, x, y, ax, aty, NULL, NULL);
+  residuals r = eval_residuals(m, n, lp->c, lp->b, lp->sense, lp->l, lp->u, x, y, ax, aty, NULL, NULL, 0);
   relative_errors(&r, norm2(lp->b, m), norm2(lp->c, n), &out[0], &out[1], &out[2]);
   out[3] = r.pobj;
   out[4] = r.dobj;
@@ -316,6 +350,67 @@ int orc_kkt(const orc_lp *lp, const double *x, const double *y, double *out) {
   free(ax);
   free(aty);
   return 0;
+}
+
+/* ------------------------------------------------------------------------------------------- */
+/* The scalar rules of PDLP, one function each (the solve below calls exactly these)            */
+/* ------------------------------------------------------------------------------------------- */
+
+/* O2: the initial primal weight. omega0 > 0 is taken as given; otherwise |c~|_2 / |b~|_2 of the
+ * scaled cost and right-hand side when both norms exceed 1e-10, else 1. */
+double orc_initial_weight(double omega0, double norm_c_scaled, double norm_b_scaled) {
+  if (omega0 > 0.0) return omega0;
+  if (norm_c_scaled > 1e-10 && norm_b_scaled > 1e-10) return norm_c_scaled / norm_b_scaled;
+  return 1.0;
+}
+
+/* O2: the initial step size 1 / max |a~_ij| over the scaled matrix (1 when it has no nonzero). */
+double orc_initial_step(const double *sv, int64_t nnz) {
+  double amax = 0.0;
+  for (int64_t k = 0; k < nnz; ++k)
+    if (fabs(sv[k]) > amax) amax = fabs(sv[k]);
+  return amax > 0.0 ? 1.0 / amax : 1.0;
+}
+
+/* O3: the adaptive step-size rule after attempt k (k counts this attempt) that used step eta and
+ * primal weight omega, from |dx|^2, |dy|^2 and the interaction dy'(A~ dx):
+ *   eta_bar = (omega |dx|^2 + |dy|^2 / omega) / (2 |dy'(A~ dx)|), +inf when the interaction is 0;
+ *   eta_new = min((1 - (k+1)^-0.3) eta_bar, (1 + (k+1)^-0.6) eta).
+ * Returns 1 when the attempt is accepted (eta <= eta_bar, inclusive), else 0. */
+int orc_step_rule(double omega, double dx2, double dy2, double inter, double eta, int64_t k,
+                  double *eta_bar_out, double *eta_new_out) {
+  double denom = 2.0 * fabs(inter);
+  double eta_bar = denom > 0.0 ? (omega * dx2 + dy2 / omega) / denom : INFINITY;
+  double kk = (double)(k + 1);
+  *eta_new_out = fmin((1.0 - pow(kk, -0.3)) * eta_bar, (1.0 + pow(kk, -0.6)) * eta);
+  *eta_bar_out = eta_bar;
+  return eta <= eta_bar;
+}
+
+/* O4: the restart decision at an evaluation. The candidate is the average when its weighted KKT
+ * error is strictly smaller than the current iterate's (ties go to the current iterate). With
+ * KKT_c the candidate's error, KKT_a the anchor's (last restart point) and KKT_p the candidate's
+ * error at the previous evaluation without restart (+inf right after a restart), restart iff
+ *   KKT_c <= 0.2 KKT_a  (sufficient decay), or
+ *   KKT_c <= 0.8 KKT_a and KKT_c > KKT_p  (necessary decay, no longer improving), or
+ *   t >= 0.36 k  (artificial: t attempts since the last restart, k attempts in total).
+ * Writes the candidate (0 current, 1 average) and its error; returns 1 to restart. */
+int orc_restart_rule(double kkt_cur, double kkt_avg, double kkt_anchor, double kkt_prev,
+                     int64_t t_since, int64_t k, int32_t *use_avg, double *kkt_cand) {
+  int avg = kkt_avg < kkt_cur;
+  double kkt_c = avg ? kkt_avg : kkt_cur;
+  *use_avg = avg;
+  *kkt_cand = kkt_c;
+  return (kkt_c <= 0.2 * kkt_anchor) || (kkt_c <= 0.8 * kkt_anchor && kkt_c > kkt_prev) ||
+         ((double)t_since >= 0.36 * (double)k);
+}
+
+/* O4: the primal weight after a restart, from the distances of the restart point to the anchor,
+ * dx = |x_c - x_a|_2 and dy = |y_c - y_a|_2: exp(0.5 ln(dy / dx) + 0.5 ln omega), the geometric
+ * mean of dy / dx and the old weight; unchanged unless both distances exceed 1e-10. */
+double orc_primal_weight(double omega, double dx, double dy) {
+  if (dx > 1e-10 && dy > 1e-10) return exp(0.5 * log(dy / dx) + 0.5 * log(omega));
+  return omega;
 }
 
 /* ------------------------------------------------------------------------------------------- */
@@ -376,7 +471,8 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
       !tv || !cs || !ls || !us || !bs || !xn || !yn || !axn || !atyn || !xa || !ya)
     return -1;
 
-  orc_scale(m, n, lp->row_ptr, lp->col, lp->val, o->ruiz_iters, o->pock_chambolle, Dr, Dc, sv);
+  const int rev = o->sum_order == 1;
+  scale_ord(m, n, lp->row_ptr, lp->col, lp->val, o->ruiz_iters, o->pock_chambolle, Dr, Dc, sv, rev);
   orc_transpose(m, n, lp->row_ptr, lp->col, sv, trp, tci, tv);
   for (int32_t j = 0; j < n; ++j) {
     cs[j] = Dc[j] * lp->c[j];
@@ -384,29 +480,22 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     us[j] = isfinite(lp->u[j]) ? lp->u[j] / Dc[j] : lp->u[j];
   }
   for (int32_t i = 0; i < m; ++i) bs[i] = Dr[i] * lp->b[i];
-  const double nb = norm2(lp->b, m), nc = norm2(lp->c, n);
+  const double nb = norm2_ord(lp->b, m, rev), nc = norm2_ord(lp->c, n, rev);
 
   /* ---- O2: initialisation ---------------------------------------------------------------- */
   for (int32_t j = 0; j < n; ++j) cur.x[j] = clip(o->x0 ? o->x0[j] / Dc[j] : 0.0, ls[j], us[j]);
   for (int32_t i = 0; i < m; ++i) cur.y[i] = proj_y(o->y0 ? o->y0[i] / Dr[i] : 0.0, lp->sense[i]);
-  double omega;
-  {
-    double ncs = norm2(cs, n), nbs = norm2(bs, m);
-    if (o->omega0 > 0.0) omega = o->omega0;
-    else if (ncs > 1e-10 && nbs > 1e-10) omega = ncs / nbs;
-    else omega = 1.0;
-  }
-  double amax = 0.0;
-  for (int32_t k = 0; k < nnz; ++k)
-    if (fabs(sv[k]) > amax) amax = fabs(sv[k]);
-  double eta = amax > 0.0 ? 1.0 / amax : 1.0;
-  orc_spmv(m, lp->row_ptr, lp->col, sv, cur.x, cur.ax);
-  orc_spmv(n, trp, tci, tv, cur.y, cur.aty);
+  double omega = orc_initial_weight(o->omega0, norm2_ord(cs, n, rev), norm2_ord(bs, m, rev));
+  double eta = orc_initial_step(sv, nnz);
+  res->omega_init = omega;
+  res->eta_init = eta;
+  spmv_ord(m, lp->row_ptr, lp->col, sv, cur.x, cur.ax, rev);
+  spmv_ord(n, trp, tci, tv, cur.y, cur.aty, rev);
   copy_iterate(&avg, &cur, m, n);
   memcpy(xa, cur.x, sizeof(double) * (size_t)n);
   memcpy(ya, cur.y, sizeof(double) * (size_t)m);
   double wsum = 0.0;
-  residuals r0 = eval_residuals(m, n, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax, cur.aty, Dr, Dc);
+  residuals r0 = eval_residuals(m, n, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax, cur.aty, Dr, Dc, rev);
   double kkt_anchor = kkt_weighted(&r0, omega);
   double kkt_prev = INFINITY;
   int64_t k = 0, last_restart = 0;
@@ -419,27 +508,28 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     /* O3: one attempt */
     double tau = eta / omega, sigma = eta * omega;
     pdhg_step(m, n, lp->row_ptr, lp->col, sv, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax,
-              cur.aty, tau, sigma, xn, yn, axn);
-    orc_spmv(n, trp, tci, tv, yn, atyn);
+              cur.aty, tau, sigma, xn, yn, axn, rev);
+    spmv_ord(n, trp, tci, tv, yn, atyn, rev);
     k += 1;
     double dx2 = 0.0, dy2 = 0.0, inter = 0.0;
-    for (int32_t j = 0; j < n; ++j) dx2 += (xn[j] - cur.x[j]) * (xn[j] - cur.x[j]);
-    for (int32_t i = 0; i < m; ++i) {
+    for (int32_t tj = 0; tj < n; ++tj) {
+      const int32_t j = ord(tj, n, rev);
+      dx2 += (xn[j] - cur.x[j]) * (xn[j] - cur.x[j]);
+    }
+    for (int32_t ti = 0; ti < m; ++ti) {
+      const int32_t i = ord(ti, m, rev);
       double dy = yn[i] - cur.y[i];
       dy2 += dy * dy;
       inter += dy * (axn[i] - cur.ax[i]);
     }
-    double denom = 2.0 * fabs(inter);
-    double eta_bar = denom > 0.0 ? (omega * dx2 + dy2 / omega) / denom : INFINITY;
-    double kk = (double)(k + 1);
-    double eta_new = fmin((1.0 - pow(kk, -0.3)) * eta_bar, (1.0 + pow(kk, -0.6)) * eta);
-    int accepted = eta <= eta_bar;
+    double eta_bar, eta_new;
+    int accepted = orc_step_rule(omega, dx2, dy2, inter, eta, k, &eta_bar, &eta_new);
     double margin = rel_margin(eta, eta_bar);
     double cond = 1.0;
     {
       double xx = 0.0, yy = 0.0;
-      for (int32_t j = 0; j < n; ++j) xx += cur.x[j] * cur.x[j];
-      for (int32_t i = 0; i < m; ++i) yy += cur.y[i] * cur.y[i];
+      for (int32_t tj = 0; tj < n; ++tj) xx += cur.x[ord(tj, n, rev)] * cur.x[ord(tj, n, rev)];
+      for (int32_t ti = 0; ti < m; ++ti) yy += cur.y[ord(ti, m, rev)] * cur.y[ord(ti, m, rev)];
       if (dx2 > 0.0) cond += sqrt(xx / dx2);
       if (dy2 > 0.0) cond += sqrt(yy / dy2);
     }
@@ -469,8 +559,8 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
     /* O4 + O5: evaluation */
     if (k % every == 0) {
       flags |= 2;
-      residuals rc_ = eval_residuals(m, n, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax, cur.aty, Dr, Dc);
-      residuals ra_ = eval_residuals(m, n, cs, bs, lp->sense, ls, us, avg.x, avg.y, avg.ax, avg.aty, Dr, Dc);
+      residuals rc_ = eval_residuals(m, n, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax, cur.aty, Dr, Dc, rev);
+      residuals ra_ = eval_residuals(m, n, cs, bs, lp->sense, ls, us, avg.x, avg.y, avg.ax, avg.aty, Dr, Dc, rev);
       double relc[3], rela[3];
       relative_errors(&rc_, nb, nc, &relc[0], &relc[1], &relc[2]);
       relative_errors(&ra_, nb, nc, &rela[0], &rela[1], &rela[2]);
@@ -492,14 +582,12 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
         break;
       }
       double kkt_c_cur = kkt_weighted(&rc_, omega), kkt_c_avg = kkt_weighted(&ra_, omega);
-      int use_avg = kkt_c_avg < kkt_c_cur;
-      double kkt_c = use_avg ? kkt_c_avg : kkt_c_cur;
+      int32_t use_avg;
+      double kkt_c;
+      int64_t t_since = k - last_restart;
+      int restart = orc_restart_rule(kkt_c_cur, kkt_c_avg, kkt_anchor, kkt_prev, t_since, k, &use_avg, &kkt_c);
       double mg = rel_margin(kkt_c_avg, kkt_c_cur);
       if (mg < margin) margin = mg;
-      int64_t t_since = k - last_restart;
-      int restart = (kkt_c <= 0.2 * kkt_anchor) ||
-                    (kkt_c <= 0.8 * kkt_anchor && kkt_c > kkt_prev) ||
-                    ((double)t_since >= 0.36 * (double)k);
       mg = rel_margin(kkt_c, 0.2 * kkt_anchor);
       if (mg < margin) margin = mg;
       mg = rel_margin(kkt_c, 0.8 * kkt_anchor);
@@ -514,11 +602,17 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
         flags |= 4 | (use_avg ? 8 : 0);
         if (use_avg) copy_iterate(&cur, &avg, m, n);
         double ddx = 0.0, ddy = 0.0;
-        for (int32_t j = 0; j < n; ++j) ddx += (cur.x[j] - xa[j]) * (cur.x[j] - xa[j]);
-        for (int32_t i = 0; i < m; ++i) ddy += (cur.y[i] - ya[i]) * (cur.y[i] - ya[i]);
+        for (int32_t tj = 0; tj < n; ++tj) {
+          const int32_t j = ord(tj, n, rev);
+          ddx += (cur.x[j] - xa[j]) * (cur.x[j] - xa[j]);
+        }
+        for (int32_t ti = 0; ti < m; ++ti) {
+          const int32_t i = ord(ti, m, rev);
+          ddy += (cur.y[i] - ya[i]) * (cur.y[i] - ya[i]);
+        }
         ddx = sqrt(ddx);
         ddy = sqrt(ddy);
-        if (ddx > 1e-10 && ddy > 1e-10) omega = exp(0.5 * log(ddy / ddx) + 0.5 * log(omega));
+        omega = orc_primal_weight(omega, ddx, ddy);
         memcpy(xa, cur.x, sizeof(double) * (size_t)n);
         memcpy(ya, cur.y, sizeof(double) * (size_t)m);
         kkt_anchor = kkt_weighted(use_avg ? &ra_ : &rc_, omega);
@@ -551,7 +645,7 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
 
   if (status != ORC_OPTIMAL) {
     /* report the current iterate and its errors */
-    residuals rc_ = eval_residuals(m, n, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax, cur.aty, Dr, Dc);
+    residuals rc_ = eval_residuals(m, n, cs, bs, lp->sense, ls, us, cur.x, cur.y, cur.ax, cur.aty, Dr, Dc, rev);
     relative_errors(&rc_, nb, nc, &out_rel[0], &out_rel[1], &out_rel[2]);
     out_obj[0] = rc_.pobj, out_obj[1] = rc_.dobj;
     which = 0;

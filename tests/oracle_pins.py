@@ -363,7 +363,93 @@ def pin_step_condition(lib=oracle.LIB):
     assert n_acc > 50
 
 
-ALL_PINS = [pin_spmv_transpose, pin_step_by_hand, pin_kkt_by_hand, pin_kkt_at_highs, pin_fixed_point,
+# ------------------------------------------------------------------------------------------------
+# Formula pins: the scalar rules of PDLP on hand-worked numbers. Each rule is the oracle function the
+# solve calls; the expected values are worked out in the comments, not recomputed from the formula.
+def pin_step_rule(lib=oracle.LIB):
+    """Adaptive step size. omega = 2, |dx|^2 = 3, |dy|^2 = 8, dy'(A dx) = 1.5:
+    eta_bar = (2 * 3 + 8 / 2) / (2 * 1.5) = 10 / 3. At k = 63, (k + 1) = 64 = 2^6, so
+    (k+1)^-0.3 = 2^-1.8 = 0.28717458874925877 and (k+1)^-0.6 = 2^-3.6 = 0.08246924442330906."""
+    acc, eb, en = oracle.step_rule(2.0, 3.0, 8.0, 1.5, 0.5, 63, lib_path=lib)
+    assert acc and abs(eb - 10.0 / 3.0) <= 1e-15, (acc, eb)
+    # eta = 0.5: growth branch, min(2.376..., 0.5 * 1.0824692444233091) = 0.5412346222116545
+    assert abs(en - 0.5412346222116545) <= 1e-14, en
+    # eta = 5 > eta_bar: rejected; shrink branch (1 - 2^-1.8) * 10/3 = 2.3760847041691374
+    acc, eb, en = oracle.step_rule(2.0, 3.0, 8.0, -1.5, 5.0, 63, lib_path=lib)  # |interaction| is used
+    assert not acc and abs(eb - 10.0 / 3.0) <= 1e-15 and abs(en - 2.3760847041691374) <= 1e-14, (acc, eb, en)
+    # acceptance is inclusive: omega = 1, |dx|^2 = |dy|^2 = 1, interaction 0.5 gives eta_bar = 2 exactly
+    acc, eb, _ = oracle.step_rule(1.0, 1.0, 1.0, 0.5, 2.0, 10, lib_path=lib)
+    assert acc and eb == 2.0
+    acc, _, _ = oracle.step_rule(1.0, 1.0, 1.0, 0.5, 2.0 * (1 + 2.0**-52), 10, lib_path=lib)
+    assert not acc
+    # no interaction: eta_bar = +inf, always accepted, eta grows by (1 + (k+1)^-0.6); k = 0: 1^-0.6 = 1
+    acc, eb, en = oracle.step_rule(1.0, 1.0, 1.0, 0.0, 0.25, 0, lib_path=lib)
+    assert acc and eb == np.inf and en == 0.5, (acc, eb, en)
+
+
+def pin_restart_rule(lib=oracle.LIB):
+    """Restart test against an anchor error of 1: sufficient decay at 0.2, necessary decay at 0.8
+    with no progress since the previous evaluation, artificial restart after 36 % of all attempts;
+    the candidate is the average only when its error is strictly smaller."""
+    inf = np.inf
+    R = lambda *a: oracle.restart_rule(*a, lib_path=lib)  # noqa: E731
+    # (i) sufficient decay, inclusive boundary; the current iterate is the better candidate
+    assert R(0.2, 0.5, 1.0, inf, 10, 1000) == (True, False, 0.2)
+    assert R(0.2000001, 0.5, 1.0, inf, 10, 1000) == (False, False, 0.2000001)
+    assert R(0.5, 0.15, 1.0, inf, 10, 1000) == (True, True, 0.15)  # the average qualifies
+    # (ii) necessary decay: <= 0.8 of the anchor and worse than the previous candidate
+    assert R(0.7, 0.9, 1.0, 0.6, 10, 1000)[0] is True
+    assert R(0.8, 0.9, 1.0, 0.6, 10, 1000)[0] is True
+    assert R(0.8000001, 0.9, 1.0, 0.6, 10, 1000)[0] is False
+    assert R(0.7, 0.9, 1.0, 0.7, 10, 1000)[0] is False  # equal to the previous: still improving
+    assert R(0.7, 0.9, 1.0, 0.75, 10, 1000)[0] is False
+    # (iii) artificial: 36 of 100 attempts since the last restart, inclusive
+    assert R(0.9, 0.95, 1.0, 0.5, 36, 100)[0] is True
+    assert R(0.9, 0.95, 1.0, 0.5, 35, 100)[0] is False
+    # ties between the two candidates go to the current iterate
+    assert R(0.5, 0.5, 1.0, inf, 10, 1000)[1] is False
+    assert R(0.5, 0.4999999, 1.0, inf, 10, 1000)[1] is True
+
+
+def pin_primal_weight(lib=oracle.LIB):
+    """omega <- exp(ln(dy/dx)/2 + ln(omega)/2) = sqrt(omega * dy / dx), unless a distance is <= 1e-10."""
+    W = lambda *a: oracle.primal_weight(*a, lib_path=lib)  # noqa: E731
+    assert abs(W(4.0, 1.0, 9.0) - 6.0) <= 1e-14  # sqrt(4 * 9)
+    assert abs(W(8.0, 2.0, 1.0) - 2.0) <= 1e-14  # sqrt(8 / 2)
+    assert abs(W(2.0, 2e-10, 8e-10) - 2.8284271247461903) <= 1e-14  # sqrt(2 * 4), both just above 1e-10
+    assert W(2.0, 1e-10, 5.0) == 2.0 and W(2.0, 5.0, 1e-10) == 2.0 and W(3.0, 0.0, 0.0) == 3.0
+
+
+def pin_kkt_weighted(lib=oracle.LIB):
+    """sqrt(omega^2 |r_p|^2 + |r_d|^2 / omega^2 + gap^2): omega = 2, 3, 8, gap 1 -> sqrt(12 + 2 + 1)."""
+    assert abs(oracle.kkt_weighted(2.0, 3.0, 8.0, 1.0, lib_path=lib) - np.sqrt(15.0)) <= 1e-14
+    assert abs(oracle.kkt_weighted(0.5, 3.0, 8.0, -2.0, lib_path=lib) - np.sqrt(0.75 + 32.0 + 4.0)) <= 1e-14
+
+
+def pin_initial_values(lib=oracle.LIB):
+    """Start values on a 2x2 LP with only the Pock-Chambolle pass, worked by hand.
+    A = [[1, 2], [3, 4]]: row sums 3, 7, column sums 4, 6, so Dr = (1/sqrt3, 1/sqrt7),
+    Dc = (1/2, 1/sqrt6) and a~_ij = a_ij / sqrt(r_i c_j): 1/sqrt12, 2/sqrt18, 3/sqrt28, 4/sqrt42; the
+    largest is 4/sqrt42, so eta0 = sqrt42 / 4. With c = b = (1, 1): |c~|^2 = 1/4 + 1/6 = 5/12,
+    |b~|^2 = 1/3 + 1/7 = 10/21, omega0 = sqrt((5/12) / (10/21)) = sqrt(7/8)."""
+    lp = _lp_from_dense([[1.0, 2.0], [3.0, 4.0]], [1.0, 1.0], [E_, E_], [1.0, 1.0], [0.0, 0.0], [10.0, 10.0])
+    r = oracle.solve(lp, tol=0.0, iter_limit=1, ruiz_iters=0, trace_len=1, lib_path=lib)
+    assert abs(r.omega_init - np.sqrt(7.0 / 8.0)) <= 1e-15, r.omega_init
+    assert abs(r.eta_init - np.sqrt(42.0) / 4.0) <= 1e-15, r.eta_init
+    assert r.trace["omega"][0] == r.omega_init  # no evaluation after one attempt
+    # a given primal weight is used as is; a zero right-hand side gives the default 1
+    assert oracle.solve(lp, tol=0.0, iter_limit=1, ruiz_iters=0, omega0=3.5, lib_path=lib).omega_init == 3.5
+    lp0 = _lp_from_dense([[1.0, 2.0], [3.0, 4.0]], [0.0, 0.0], [E_, E_], [1.0, 1.0], [0.0, 0.0], [10.0, 10.0])
+    assert oracle.solve(lp0, tol=0.0, iter_limit=1, ruiz_iters=0, lib_path=lib).omega_init == 1.0
+    assert oracle.initial_weight(0.0, 3.0, 1.5, lib_path=lib) == 2.0
+    assert oracle.initial_weight(0.0, 3.0, 1e-10, lib_path=lib) == 1.0
+    assert oracle.initial_step([0.5, -4.0, 2.0], lib_path=lib) == 0.25
+    assert oracle.initial_step([], lib_path=lib) == 1.0
+
+
+FORMULA_PINS = [pin_step_rule, pin_restart_rule, pin_primal_weight, pin_kkt_weighted, pin_initial_values]
+
+ALL_PINS = FORMULA_PINS + [pin_spmv_transpose, pin_step_by_hand, pin_kkt_by_hand, pin_kkt_at_highs, pin_fixed_point,
             pin_scaling, pin_box_only, pin_knapsack, pin_disjoint_cover, pin_bruteforce,
             pin_highs_setcover, pin_highs_general, pin_energy_small, pin_duality_and_kkt,
             pin_warm_start, pin_step_condition]
