@@ -129,8 +129,8 @@ class Result:
 def solve(lp, tol: float = 1e-4, iter_limit: int = 1_000_000, ruiz_iters: int = 10,
           pock_chambolle: bool = True, eval_every: int = 64, x0=None, y0=None, omega0: float = 0.0,
           trace_len: int = 0, sum_order: int = 0, lib_path: str = LIB) -> Result:
-    """sum_order 1 takes every sum of the method in reverse index order (a different, equally valid
-    rounding of the same arithmetic)."""
+    """sum_order 1 takes every sum of the method in reverse index order, 2 the even indices first
+    and then the odd ones (different, equally valid roundings of the same arithmetic)."""
     lib = load(lib_path)
     s, keep = _arrays(lp)
     x = np.zeros(lp.n)

@@ -70,9 +70,9 @@ typedef struct {
   double *trace_cond;   /* [trace_len] 1 + |x|/|dx| + |y|/|dy| of attempt k (scaled space): the factor
                            by which relative errors of the iterates enter the step-size ratio */
   int32_t sum_order;    /* 0: every sum in index order; 1: every sum (matrix rows, reductions, norms,
-                           scaling sums) in reverse index order. Any order is a valid evaluation of
-                           the same formulas; comparing the two measures how far rounding alone moves
-                           the iterates. */
+                           scaling sums) in reverse index order; 2: even indices first, then odd.
+                           Any order is a valid evaluation of the same formulas; comparing them
+                           measures how far rounding alone moves the iterates. */
   int32_t pad_;
 } orc_opts;
 
@@ -92,8 +92,17 @@ enum { ORC_OPTIMAL = 1, ORC_ITER_LIMIT = 2, ORC_NUMERICAL = 3 };
 /* Sparse helpers                                                                               */
 /* ------------------------------------------------------------------------------------------- */
 
-/* Position t of a sum over [0, len) in index order (rev == 0) or in reverse order (rev == 1). */
-static int32_t ord(int32_t t, int32_t len, int rev) { return rev ? len - 1 - t : t; }
+/* The index visited at step t of a sum over [0, len): in index order (mode 0), in reverse order
+ * (mode 1), or the even indices in order and then the odd ones (mode 2). Every mode is a valid
+ * evaluation of the same sum with its own rounding. */
+static int32_t ord(int32_t t, int32_t len, int mode) {
+  if (mode == 1) return len - 1 - t;
+  if (mode == 2) {
+    const int32_t half = (len + 1) / 2;
+    return t < half ? 2 * t : 2 * (t - half) + 1;
+  }
+  return t;
+}
 
 /* y = A x for A in CSR; each row sum in the order `rev` selects */
 static void spmv_ord(int32_t m, const int32_t *rp, const int32_t *ci, const double *v, const double *x,
@@ -471,7 +480,7 @@ int orc_solve(const orc_lp *lp, const orc_opts *o, double *x_out, double *y_out,
       !tv || !cs || !ls || !us || !bs || !xn || !yn || !axn || !atyn || !xa || !ya)
     return -1;
 
-  const int rev = o->sum_order == 1;
+  const int rev = (o->sum_order == 1 || o->sum_order == 2) ? o->sum_order : 0;
   scale_ord(m, n, lp->row_ptr, lp->col, lp->val, o->ruiz_iters, o->pock_chambolle, Dr, Dc, sv, rev);
   orc_transpose(m, n, lp->row_ptr, lp->col, sv, trp, tci, tv);
   for (int32_t j = 0; j < n; ++j) {

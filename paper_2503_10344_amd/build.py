@@ -20,6 +20,9 @@ FLAGS = [
     "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no product is fused into a sum unless the code asks for fma() itself: every update rounds
+    # its product and its sum separately, as the method's formulas are written
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-parameter", "-Wno-unused-command-line-argument",
 ]
 

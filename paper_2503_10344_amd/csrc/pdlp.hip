@@ -615,7 +615,7 @@ struct Solver {
                        (const int32_t *)(trans ? d_tb_inst : d_ab_inst),
                        (const int32_t *)(trans ? d_t_bchunk : d_a_bchunk), x, y);
   }
-  void spmv_T(int trans, const T *x, T *y) { spmv_chunks<T, T, T, T>(trans, x, y); }
+  void spmv_T(int trans, const T *x, T *y) { spmv_chunks<T, T, double, T>(trans, x, y); }
 
   // Autotuner: time A x and A'y for each candidate chunk size; keep the smallest size unless
   // another is at least 15 % faster. The choice is cached per sparsity signature.
@@ -706,8 +706,8 @@ struct Solver {
   void refresh_averages() {
     if constexpr (sizeof(T) == sizeof(float)) {
       hipLaunchKernelGGL(k_avg_flush<T>, dim3(ev_blocks), dim3(kBlock), 0, stream, P);
-      spmv_chunks<T, double, T, T>(0, xbar, axbar);
-      spmv_chunks<T, double, T, T>(1, ybar, atybar);
+      spmv_chunks<T, double, double, T>(0, xbar, axbar);
+      spmv_chunks<T, double, double, T>(1, ybar, atybar);
     }
   }
   void launch_chunk_body() {
@@ -851,8 +851,8 @@ struct Solver {
     if (warm && opt.warm_fallback) {
       // cold start in the average slots; compare the relative KKT errors of both points
       start_point(nullptr, nullptr, xbar, ybar);
-      spmv_chunks<T, double, T, T>(0, xbar, axbar);
-      spmv_chunks<T, double, T, T>(1, ybar, atybar);
+      spmv_chunks<T, double, double, T>(0, xbar, axbar);
+      spmv_chunks<T, double, double, T>(1, ybar, atybar);
       launch_eval(kEvalPoint);
       HIPCHK(hipGetLastError());
       read_state();
@@ -945,8 +945,21 @@ struct Solver {
   void run_loop(int64_t iter_limit) {
     const int64_t max_chunks = iter_limit / opt.eval_every + 3;
     int64_t ch = 0;
+    // PDLP_TRACE_EVALS=<period>: every <period> evaluations, print the relative errors of both
+    // candidates of the first instances (one interval in flight then; the results do not change)
+    static const char *trace_env = getenv("PDLP_TRACE_EVALS");
+    const int64_t trace_every = trace_env ? std::max<int64_t>(1, atoll(trace_env)) : 0;
     for (; ch < max_chunks; ++ch) {
       run_chunk(ch);
+      if (trace_every && ch % trace_every == 0) {
+        read_state();
+        for (int q = 0; q < std::min(K, 4); ++q) {
+          const State &s = h_st[q];
+          fprintf(stderr, "[pdlp-trace] inst %d k %lld restarts %d omega %.4e eta %.4e | cur p %.3e d %.3e g %.3e | avg p %.3e d %.3e g %.3e%s\n",
+                  q, (long long)s.k, s.restarts, s.omega, s.eta, s.ev_rel[0], s.ev_rel[1], s.ev_rel[2], s.ev_rel[3],
+                  s.ev_rel[4], s.ev_rel[5], s.done ? " done" : "");
+        }
+      }
       HIPCHK(hipMemcpyAsync(&h_flags[ch & 1], ndone, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipEventRecord(ev[ch & 1], stream));
       if (ch >= 1) {

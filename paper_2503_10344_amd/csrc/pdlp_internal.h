@@ -43,6 +43,7 @@ struct State {
   double tol;         // relative KKT tolerance (<= 0: never met)
   double rel_p, rel_d, rel_gap, pobj, dobj;  // last evaluated point (original space)
   double cand_rel[2]; // relative KKT error of current [0] / average [1] at the last evaluation
+  double ev_rel[6];   // at the last evaluation: rel_p, rel_d, rel_gap of current [0..2] and average [3..5]
   double nb, nc;      // |b|, |c| of the original data
   int64_t k;          // attempts so far
   int64_t last_restart;

@@ -133,11 +133,15 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 struct NoPre {};
 
 // The two accumulation forms of the engine, spelled out so that every path that sums a row rounds
-// identically: the first accumulator of a lane takes a fused multiply-add; the masked ones take a
-// rounded product, a select against zero and a rounded add.
+// identically: a rounded product and a rounded add (the library is built without floating-point
+// contraction, so no product is fused into a sum), and for the masked slots a select against zero
+// in between. The iteration products accumulate in FP64 in both precisions: an FP32 value times an
+// FP32 value is exact in FP64, so an FP32 row sum carries only the rounding of its FP64 additions
+// until it is stored.
 template <typename Acc>
 __device__ __forceinline__ Acc acc_fma(Acc s, Acc v, Acc x) {
-  return fma(v, x, s);
+  const Acc prod = v * x;
+  return s + prod;
 }
 template <typename Acc>
 __device__ __forceinline__ Acc acc_masked(Acc s, bool p, Acc v, Acc x) {
@@ -327,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   const State *st = P.st + w.inst;
   if (st->done | st->stop) return;
   const int cur = st->cur;
-  const T sigma = T(st->eta * st->omega);
+  const double sigma = st->eta * st->omega;
   const T *__restrict__ xn = P.x[cur ^ 1];
   const T *__restrict__ yc = P.y[cur];
   const T *__restrict__ axc = P.ax[cur];
@@ -342,16 +346,19 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   };
   int cb, ce;
   cb = P.L.a_bchunk[P.L.ab0[w.inst] + w.lb], ce = P.L.a_bchunk[P.L.ab0[w.inst] + w.lb + 1];
-  block_chunks<T, T, T>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, cb, ce,
-                        [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; },
-                        [&](int i, T s, const DualPre &q) {
-                          const T ynew = proj_dual(q.y + sigma * (q.b - T(2) * s + q.ax), q.s);
-                          yn[i] = ynew;
-                          axn[i] = s;
-                          const double dy = double(ynew) - double(q.y);
-                          acc[0] += dy * dy;
-                          acc[1] += dy * (double(s) - double(q.ax));
-                        });
+  // The update is computed in FP64 from the stored operands and rounded once to T.
+  block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, cb, ce,
+                             [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; },
+                             [&](int i, double s, const DualPre &q) {
+                               const T axi = T(s);
+                               const double ax1 = double(axi), ax0 = double(q.ax), y0 = double(q.y);
+                               const T ynew = T(proj_dual(y0 + sigma * (double(q.b) - 2.0 * ax1 + ax0), q.s));
+                               yn[i] = ynew;
+                               axn[i] = axi;
+                               const double dy = double(ynew) - y0;
+                               acc[0] += dy * dy;
+                               acc[1] += dy * (ax1 - ax0);
+                             });
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
     P.p_dual[2 * blockIdx.x] = acc[0];
@@ -503,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   const State *st = P.st + w.inst;
   if (st->done) return;
   const int cur = st->cur, commit = st->commit, stop = st->stop;
-  const T tau = T(st->eta / st->omega);
+  const double tau = st->eta / st->omega;
   const T wa = T(st->avg_w);
   const double wad = st->avg_w, wd1 = st->avg_w1;
   const int amode = st->avg_mode;
@@ -540,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
       if (kTrack) atybar[j] = q.atybar + wa * (atyj - q.atybar);
     }
     if (!stop) {
-      const T xnew = clipv(q.x - tau * (q.c - atyj), q.l, q.u);
+      const T xnew = T(clipv(double(q.x) - tau * (double(q.c) - double(atyj)), double(q.l), double(q.u)));
       xnx[j] = xnew;
       const double d = double(xnew) - double(q.x);
       acc[0] += d * d;
@@ -549,11 +556,12 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
   int cb, ce;
   cb = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb], ce = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb + 1];
   if (commit) {
-    block_chunks<T, T, T>(P.t_rp, P.t_ci, P.t_val, yc, P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
-                          [&](int j, T s, const PrimalPre &q) {
-                            aty[j] = s;
-                            primal(j, s, q);
-                          });
+    block_chunks<T, T, double>(P.t_rp, P.t_ci, P.t_val, yc, P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
+                               [&](int j, double s, const PrimalPre &q) {
+                                 const T atyj = T(s);
+                                 aty[j] = atyj;
+                                 primal(j, atyj, q);
+                               });
     const T *__restrict__ axc = P.ax[cur];
     const T *__restrict__ yprev = P.y[cur ^ 1];  // the older accepted y of a paired update
     double *__restrict__ ybar = P.ybar;
@@ -612,6 +620,7 @@ __device__ inline void eval_logic(State *st, int32_t *ndone, const double *tot, 
   const double ka = fmax(ra[0], fmax(ra[1], ra[2]));
   st->cand_rel[0] = kc;
   st->cand_rel[1] = ka;
+  for (int q = 0; q < 3; ++q) st->ev_rel[q] = rc[q], st->ev_rel[3 + q] = ra[q];
   if (mode != kEvalChunk) {
     st->rel_p = rc[0], st->rel_d = rc[1], st->rel_gap = rc[2], st->pobj = rc[3], st->dobj = rc[4];
     if (mode == kEvalInit) {
@@ -779,7 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
   const int mode = st->restart_mode;
   if (mode == kNoRestart) return;
   const int cur = st->cur, stop = st->stop;
-  const T tau = T(st->eta / st->omega);
+  const double tau = st->eta / st->omega;
   T *__restrict__ xc = P.x[cur];
   T *__restrict__ xnx = P.x[cur ^ 1];
   T *__restrict__ yc = P.y[cur];
@@ -798,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_restart(Iter<T> P) {
     }
     P.xa[j] = xj;
     if (!stop) {
-      const T xnew = clipv(xj - tau * (P.c[j] - atyj), P.l[j], P.u[j]);
+      const T xnew = T(clipv(double(xj) - tau * (double(P.c[j]) - double(atyj)), double(P.l[j]), double(P.u[j])));
       xnx[j] = xnew;
       const double d = double(xnew) - double(xj);
       acc[0] += d * d;

@@ -193,6 +193,15 @@ def _is_cuda(a):
     return getattr(a, "is_cuda", False)
 
 
+def _vec(a, length, name):
+    """Contiguous float64 copy of a vector the C side reads `length` entries of; a wrong length
+    raises here instead of letting the library read past the end of the array."""
+    v = np.ascontiguousarray(a, np.float64)
+    if v.ndim != 1 or v.size != length:
+        raise ValueError(f"{name} must have {length} entries, got shape {v.shape}")
+    return v
+
+
 def _dptr(a):
     """Device pointer of a contiguous GPU torch tensor."""
     if not (_is_cuda(a) and a.is_contiguous()):
@@ -313,8 +322,8 @@ class Problem:
                              a["sense"], a["l"], a["u"], self.opt)
 
     def solve(self, tol=1e-4, iter_limit=1_000_000, x0=None, y0=None, omega0=0.0) -> dict:
-        x0a = None if x0 is None else np.ascontiguousarray(x0, np.float64)
-        y0a = None if y0 is None else np.ascontiguousarray(y0, np.float64)
+        x0a = None if x0 is None else _vec(x0, self.n, "x0")
+        y0a = None if y0 is None else _vec(y0, self.m, "y0")
         pdlp_solve(self.h, tol, iter_limit, x0a, y0a, omega0)
         return pdlp_get(self.h).as_dict()
 
@@ -324,7 +333,7 @@ class Problem:
         return Solution(x, y, rc, r.as_dict())
 
     def spmv(self, x, trans=False) -> np.ndarray:
-        x = np.ascontiguousarray(x, np.float64)
+        x = _vec(x, self.m if trans else self.n, "x")
         y = np.zeros(self.n if trans else self.m)
         pdlp_spmv(self.h, 1 if trans else 0, x, y)
         return y
@@ -360,7 +369,7 @@ class Problem:
 
     def update_bounds(self, l, u):
         """New column bounds (after fixings) for the next solve; see pdlp_update_bounds."""
-        lo, hi = np.ascontiguousarray(l, np.float64), np.ascontiguousarray(u, np.float64)
+        lo, hi = _vec(l, self.n, "l"), _vec(u, self.n, "u")
         _check(load().pdlp_update_bounds(self.h, _ptr(lo), _ptr(hi)))
 
     def kernel_stats(self) -> dict:
@@ -468,21 +477,23 @@ class Batch:
         k = len(self.dims)
         keep = []
 
-        def ptr_array(vs):
+        def ptr_array(vs, side):
             if vs is None:
                 return None
+            if len(vs) != k:
+                raise ValueError(f"one start vector (or None) per instance: {k} expected, got {len(vs)}")
             arr = (C.c_void_p * k)()
             for i, v in enumerate(vs):
                 if v is not None:
-                    a = np.ascontiguousarray(v, np.float64)
+                    a = _vec(v, self.dims[i][side], f"start vector of instance {i}")
                     keep.append(a)
                     arr[i] = a.ctypes.data
             return arr
 
-        xa, ya = ptr_array(x0s), ptr_array(y0s)
+        xa, ya = ptr_array(x0s, 1), ptr_array(y0s, 0)
         om = None
         if omega0s is not None:
-            oa = np.ascontiguousarray(omega0s, np.float64)
+            oa = _vec(omega0s, k, "omega0s")
             keep.append(oa)
             om = oa.ctypes.data_as(C.c_void_p)
         pdlp_batch_solve(self.h, tol, iter_limit, xa, ya, om)
@@ -507,7 +518,10 @@ class Batch:
 
     def update_bounds(self, i, l, u):
         """New column bounds of instance i for the next batched solve."""
-        lo, hi = np.ascontiguousarray(l, np.float64), np.ascontiguousarray(u, np.float64)
+        if 0 <= int(i) < len(self.dims):
+            lo, hi = _vec(l, self.dims[int(i)][1], "l"), _vec(u, self.dims[int(i)][1], "u")
+        else:  # the library rejects the index
+            lo, hi = np.ascontiguousarray(l, np.float64), np.ascontiguousarray(u, np.float64)
         _check(load().pdlp_batch_update_bounds(self.h, int(i), _ptr(lo), _ptr(hi)))
 
     def schedule(self) -> dict:

@@ -195,3 +195,30 @@ def test_gnn_rejects_null_arguments(lib):
     assert lib.pdlp_gnn_train_step(None, None, None, None, None, C.c_float(1e-3), None) == -1
     assert lib.pdlp_batch_get_internal(None, *([None] * 8)) == -1
     assert lib.pdlp_gnn_set_omega_weight(None, C.c_float(1.0)) == -1
+
+
+def test_binding_checks_vector_lengths(lib):
+    """Vectors the library reads n or m entries of are checked in the binding: a short array raises
+    ValueError instead of being read past its end (no GPU needed: the check comes before any call)."""
+    from paper_2503_10344_amd import pdlp
+    prob = pdlp.Problem.__new__(pdlp.Problem)  # no device handle: only the checks run
+    prob.m, prob.n, prob.h = 3, 5, None
+    for kw in (dict(x0=np.zeros(4)), dict(y0=np.zeros(2)), dict(x0=np.zeros((5, 1)))):
+        with pytest.raises(ValueError):
+            prob.solve(**kw)
+    with pytest.raises(ValueError):
+        prob.spmv(np.zeros(3))
+    with pytest.raises(ValueError):
+        prob.spmv(np.zeros(5), trans=True)
+    with pytest.raises(ValueError):
+        prob.update_bounds(np.zeros(5), np.zeros(4))
+    bt = pdlp.Batch.__new__(pdlp.Batch)
+    bt.dims, bt.h = [(3, 5), (2, 4)], None
+    with pytest.raises(ValueError):
+        bt.solve(x0s=[np.zeros(5), np.zeros(5)])
+    with pytest.raises(ValueError):
+        bt.solve(y0s=[np.zeros(3)])
+    with pytest.raises(ValueError):
+        bt.solve(omega0s=[1.0])
+    with pytest.raises(ValueError):
+        bt.update_bounds(1, np.zeros(5), np.zeros(5))

@@ -1,16 +1,15 @@
 """Reference snapshots (pdlp_set_snapshots / pdlp_get_snapshots) against the oracle.
 
 * FP64 tracks the oracle: the restart points the GPU keeps (rel_tol = inf) are taken at the same
-  attempts as the oracle's and equal them within the tracking bound (ten times the oracle's own
-  divergence under 1-ulp input perturbations, at least 1e-9), up to the first discrete decision whose
-  margin that divergence could flip; a finite rel_tol keeps the same attempts as the oracle's
-  selection.
+  attempts as the oracle's and equal them within the tracking bound (tests/tracking.py: twice the
+  oracle's own divergence under other summation orders, at least 1e-9), up to the first discrete
+  decision whose margin that divergence could flip; a finite rel_tol keeps the same attempts as the
+  oracle's selection.
 * Taking snapshots does not change the solve (bitwise, FP32 and FP64); the ring keeps the newest k;
   a batch instance's snapshots are bitwise the single solve's; argument and order errors.
 * Full size (500k x 1M, FP32, 1e-4): every snapshot's KKT error, re-evaluated by the oracle, matches
   the one the solve measured, and the points respect bounds and dual signs.
 """
-import copy
 import ctypes
 import sys
 
@@ -18,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+import tracking
 from oracle import snap_oracle as so
 
 try:  # import at collection time: the first import on a fresh machine can take a minute
@@ -43,22 +43,6 @@ def pdlp():
     return mod
 
 
-def _divergence_bound(lp, K, tr):
-    """Ten times the largest relative change of the oracle's traced iterates under 1-ulp
-    perturbations of the matrix values and costs (two seeds), running maximum, floor 1e-9."""
-    div = np.zeros(K)
-    for seed in (1, 2):
-        rng = np.random.default_rng(seed)
-        lp2 = copy.deepcopy(lp)
-        lp2.val = lp.val * (1 + 2.0**-52 * rng.choice([-1.0, 1.0], size=lp.val.size))
-        lp2.c = lp.c * (1 + 2.0**-52 * rng.choice([-1.0, 1.0], size=lp.c.size))
-        t2 = oracle.solve(lp2, tol=0.0, iter_limit=K, trace_len=K).trace
-        for key in ("x", "y"):
-            d = np.linalg.norm(t2[key] - tr[key], axis=1) / np.maximum(np.linalg.norm(tr[key], axis=1), 1e-30)
-            div = np.maximum(div, d)
-    return np.maximum(1e-9, 10.0 * np.maximum.accumulate(div))
-
-
 @pytest.mark.parametrize("name", ["general", "energy", "knapsack"])
 def test_snapshots_track_the_oracle_fp64(pdlp, name):
     lp = {"general": lambda: g.general_sparse(7, m=400, n=800, cap=200),
@@ -67,7 +51,7 @@ def test_snapshots_track_the_oracle_fp64(pdlp, name):
     K = 1024
     ref = so.reference_snapshots(lp, k=100, rel_tol=np.inf, iter_limit=K)
     tr = ref.result.trace
-    bound = _divergence_bound(lp, K, tr)
+    bound = tracking.tracking_bound(lp, K, tr)
     risky = np.nonzero(tr["margin"] < np.maximum(1e-12, 100.0 * bound))[0]
     cut = int(risky[0]) + 1 if risky.size else K + 1  # first attempt whose decision could flip
     with pdlp.Problem(lp, precision="fp64", tile_nnz=1024, warm_fallback=False) as p:
