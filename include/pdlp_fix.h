@@ -52,6 +52,22 @@ int pdlp_variable_strategy(pdlp_problem *p, int32_t strategy, int32_t tiebreak, 
                            const double *x, const double *y, const double *red_cost, int32_t *order,
                            int32_t *count);
 
+/* Allocation-free variant of pdlp_variable_strategy, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc). Same arguments,
+ * same result bit for bit, with these differences:
+ *   - var_type, x, y, red_cost and order must be device memory on the handle's GPU, which must be
+ *     the current device (count stays host memory); otherwise PDLP_ERR_ARG;
+ *   - the workspace is a static device buffer of 64 MiB that the library holds on each GPU it runs
+ *     on until the process ends; a call needs about 20.25 max(n, m) bytes, plus 4 n + 12 m when DUAL
+ *     is the strategy or the tiebreak (so max(n, m) up to 3.3 million, or n = m up to 1.85 million
+ *     with DUAL); a larger problem is rejected with PDLP_ERR_ARG before any work is launched;
+ *   - it never calls hipMalloc or hipFree. All calls on one GPU share the buffer, so calls that
+ *     overlap in time on one GPU (several threads or streams) race and must be serialised by the
+ *     caller. Each call writes every part of the buffer it reads, so nothing carries over. */
+int pdlp_variable_strategy_noalloc(pdlp_problem *p, int32_t strategy, int32_t tiebreak, const uint8_t *var_type,
+                                   const double *x, const double *y, const double *red_cost, int32_t *order,
+                                   int32_t *count);
+
 /* Fixing values of LP-based fixing for every variable.
  *   var_type [n], x [n], l [n], u [n] (original bounds, +-HUGE_VAL allowed), uniform [n] in (0, 1)
  *   value [n]     receives the fixing value (x_j for continuous variables)

@@ -4,6 +4,10 @@
 #pragma once
 
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pdlp_fix.h"
@@ -41,6 +45,24 @@ struct Work {
     return static_cast<U *>(e.first);
   }
 };
+// Workspace carved from one caller-independent buffer (the allocation-free entry point): pieces
+// aligned to 256 bytes, in call order; asking for more than the buffer holds raises before any
+// kernel has been launched (every piece is taken at the start of a call).
+struct ScratchWork {
+  uint8_t *base;
+  int64_t cap, used = 0;
+  template <typename U>
+  U *get(int64_t count) {
+    const int64_t bytes = (std::max<int64_t>(count, 1) * (int64_t)sizeof(U) + 255) & ~(int64_t)255;
+    if (used + bytes > cap)
+      raise(PDLP_ERR_ARG, "problem too large for pdlp_variable_strategy_noalloc: its workspace exceeds the " +
+                              std::to_string(cap >> 20) + " MiB static buffer (about 20.25 max(n, m) bytes, plus 4 n + 12 m with DUAL)");
+    U *p = reinterpret_cast<U *>(base + used);
+    used += bytes;
+    return p;
+  }
+};
+
 template <typename T>
 Cache &cache_of(Solver<T> &s) {
   if (!s.fix_cache) s.fix_cache = std::make_shared<Cache>();
@@ -58,9 +80,11 @@ static bool on_device(const void *p) {
 }
 
 // A device pointer to `count` values of `src`: src itself when it is device memory, else a copy.
-template <typename U>
-const U *device_input(Work &w, const U *src, int64_t count, hipStream_t st) {
-  U *buf = w.get<U>(count);  // taken in both cases so the slot numbering does not depend on it
+// (The allocation-free path accepts device inputs only, so it never copies.)
+template <typename U, typename W>
+const U *device_input(W &w, const U *src, int64_t count, hipStream_t st) {
+  if constexpr (std::is_same<W, ScratchWork>::value) return src;
+  U *buf = w.template get<U>(count);  // taken in both cases so the slot numbering does not depend on it
   if (!src || count == 0) return buf;
   if (on_device(src)) return src;
   HIPCHK(hipMemcpyAsync(buf, src, sizeof(U) * (size_t)count, hipMemcpyHostToDevice, st));
@@ -113,9 +137,11 @@ static bool finite_host(const double *v, int64_t len) {
   return true;
 }
 
-template <typename T>
-void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *var_type, const double *x,
-                       const double *y, const double *rc, int32_t *order, int32_t *count) {
+// The order of one strategy. W supplies the device workspace: the handle's cache (grown on demand)
+// or, for the allocation-free entry point, pieces of the static scratch buffer.
+template <typename T, typename W>
+void variable_strategy_in(Solver<T> &s, W &w, int strategy, int tiebreak, const uint8_t *var_type, const double *x,
+                          const double *y, const double *rc, int32_t *order, int32_t *count) {
   const bool valid_s = strategy >= PDLP_ORDER_FRAC && strategy <= PDLP_ORDER_TYPE;
   const bool valid_t = tiebreak >= PDLP_ORDER_NONE && tiebreak <= PDLP_ORDER_TYPE;
   if (!valid_s || !valid_t) raise(PDLP_ERR_ARG, "unknown variable strategy or tiebreak");
@@ -133,24 +159,23 @@ void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *
       (need_y && !on_device(y) && !finite_host(y, m)))
     raise(PDLP_ERR_ARG, "x, y and red_cost must be finite");
   hipStream_t st = s.stream;
-  Work w(s.mem, cache_of(s));
   const int64_t big = std::max<int64_t>(std::max(n, m), 1);
   const uint8_t *d_vt = device_input(w, var_type, n, st);
   const double *d_x = device_input(w, need_x ? x : nullptr, need_x ? n : 0, st);
   const double *d_rc = device_input(w, need_rc ? rc : nullptr, need_rc ? n : 0, st);
   const double *d_y = device_input(w, need_y ? y : nullptr, need_y ? m : 0, st);
-  uint32_t *k0 = w.get<uint32_t>(big), *k1 = w.get<uint32_t>(big);
-  int32_t *v0 = w.get<int32_t>(big), *v1 = w.get<int32_t>(big);
+  uint32_t *k0 = w.template get<uint32_t>(big), *k1 = w.template get<uint32_t>(big);
+  int32_t *v0 = w.template get<int32_t>(big), *v1 = w.template get<int32_t>(big);
   const int64_t max_tiles = (big + kSortTile - 1) / kSortTile;
   const int64_t scan_len = std::max<int64_t>((int64_t)kDigits * max_tiles, big);
   RadixSort rs{st};
-  rs.counts = w.get<int32_t>((int64_t)kDigits * max_tiles);
-  rs.offs = w.get<int32_t>(scan_len);
-  rs.tsum = w.get<int32_t>((scan_len + kScanTile - 1) / kScanTile + 1);
-  uint32_t *d_group = w.get<uint32_t>(need_y ? n : 0);
-  int32_t *R0 = w.get<int32_t>(need_y ? m : 0), *R1 = w.get<int32_t>(need_y ? m : 0);
-  int32_t *rank = w.get<int32_t>(need_y ? m : 0);
-  int32_t *tail = w.get<int32_t>(2);
+  rs.counts = w.template get<int32_t>((int64_t)kDigits * max_tiles);
+  rs.offs = w.template get<int32_t>(scan_len);
+  rs.tsum = w.template get<int32_t>((scan_len + kScanTile - 1) / kScanTile + 1);
+  uint32_t *d_group = w.template get<uint32_t>(need_y ? n : 0);
+  int32_t *R0 = w.template get<int32_t>(need_y ? m : 0), *R1 = w.template get<int32_t>(need_y ? m : 0);
+  int32_t *rank = w.template get<int32_t>(need_y ? m : 0);
+  int32_t *tail = w.template get<int32_t>(2);
 
   // binary and integer variables, in index order
   int32_t k = 0;
@@ -211,6 +236,50 @@ void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *
 }
 
 template <typename T>
+void variable_strategy(Solver<T> &s, int strategy, int tiebreak, const uint8_t *var_type, const double *x,
+                       const double *y, const double *rc, int32_t *order, int32_t *count) {
+  Work w(s.mem, cache_of(s));
+  variable_strategy_in(s, w, strategy, tiebreak, var_type, x, y, rc, order, count);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free variant. Its workspace is one static device array per GPU, `scratch`; host code
+// reaches it only through the address hipGetSymbolAddress returns for the current device (the
+// array's name in host code is a host-side stand-in, not a device address). Every call on a GPU
+// reuses that GPU's array, so two calls that overlap on one GPU race. No piece of the workspace is
+// read before the same call wrote it, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------------------------
+constexpr int64_t kScratchBytes = int64_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+static uint8_t *scratch_address() {
+  static std::mutex mu;
+  static std::map<int, uint8_t *> addr;  // device -> address of its copy of `scratch`
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) raise(PDLP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  addr[dev] = static_cast<uint8_t *>(ptr);
+  return addr[dev];
+}
+
+template <typename T>
+void variable_strategy_noalloc(Solver<T> &s, int strategy, int tiebreak, const uint8_t *var_type, const double *x,
+                               const double *y, const double *rc, int32_t *order, int32_t *count) {
+  for (const void *q : {(const void *)var_type, (const void *)x, (const void *)y, (const void *)rc, (const void *)order})
+    if (q && !on_device(q)) raise(PDLP_ERR_ARG, "pdlp_variable_strategy_noalloc takes device pointers only");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != s.device) raise(PDLP_ERR_ARG, "the handle's GPU must be the current device");
+  ScratchWork w{scratch_address(), kScratchBytes};
+  variable_strategy_in(s, w, strategy, tiebreak, var_type, x, y, rc, order, count);
+}
+
+template <typename T>
 void lp_fixing(Solver<T> &s, const uint8_t *var_type, const double *x, const double *l, const double *u,
                const double *uniform, double *value) {
   if (!var_type || !x || !l || !u || !uniform || !value) raise(PDLP_ERR_ARG, "NULL argument to pdlp_lp_fixing");
@@ -251,6 +320,20 @@ int pdlp_variable_strategy(pdlp_problem *p, int32_t strategy, int32_t tiebreak, 
   }
   return guarded([&] {
     p->s.visit([&](auto &s) { pdlp::fix::variable_strategy(s, strategy, tiebreak, var_type, x, y, red_cost, order, count); });
+  });
+}
+
+int pdlp_variable_strategy_noalloc(pdlp_problem *p, int32_t strategy, int32_t tiebreak, const uint8_t *var_type,
+                                   const double *x, const double *y, const double *red_cost, int32_t *order,
+                                   int32_t *count) {
+  if (!p) {
+    pdlp::g_last_error = "NULL handle";
+    return PDLP_ERR_ARG;
+  }
+  return guarded([&] {
+    p->s.visit([&](auto &s) {
+      pdlp::fix::variable_strategy_noalloc(s, strategy, tiebreak, var_type, x, y, red_cost, order, count);
+    });
   });
 }
 

@@ -188,6 +188,7 @@ static std::map<std::string, int> g_tune_cache;
 template <typename T>
 struct Solver {
   pdlp_options opt{};
+  int device = 0;  // the GPU that was current at create
   hipStream_t stream = nullptr;
   bool own_stream = false;
   Arena mem;
@@ -287,6 +288,7 @@ struct Solver {
   // ---------------------------------------------------------------------------------------------
   void create(const std::vector<const HostProblem *> &Hs, const pdlp_options &o) {
     opt = o;
+    HIPCHK(hipGetDevice(&device));
     if (o.work_blocks > 0) work_blocks = o.work_blocks;
     K = (int32_t)Hs.size();
     mem.limit = o.device_mem_limit;

@@ -63,7 +63,7 @@ EXPORTS = ["pdlp_options_default", "pdlp_create", "pdlp_solve", "pdlp_get", "pdl
            "pdlp_get_scaling", "pdlp_get_internal", "pdlp_get_schedule", "pdlp_kernel_stats", "pdlp_device_bytes", "pdlp_destroy",
            "pdlp_error_string", "pdlp_last_error", "pdlp_batch_create", "pdlp_batch_solve",
            "pdlp_batch_get", "pdlp_batch_get_schedule", "pdlp_batch_destroy", "pdlp_update_bounds",
-           "pdlp_batch_update_bounds", "pdlp_variable_strategy",
+           "pdlp_batch_update_bounds", "pdlp_variable_strategy", "pdlp_variable_strategy_noalloc",
            "pdlp_lp_fixing", "pdlp_prop_create", "pdlp_propagate", "pdlp_prop_destroy", "pdlp_branching",
            "pdlp_set_snapshots", "pdlp_get_snapshots", "pdlp_batch_set_snapshots", "pdlp_batch_get_snapshots"]
 
@@ -154,6 +154,8 @@ def load(path: str = LIB_PATH):
     # LP-based variable strategies and fixing
     lib.pdlp_variable_strategy.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, C.POINTER(i32)]
     lib.pdlp_variable_strategy.restype = C.c_int
+    lib.pdlp_variable_strategy_noalloc.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, C.POINTER(i32)]
+    lib.pdlp_variable_strategy_noalloc.restype = C.c_int
     lib.pdlp_lp_fixing.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.pdlp_lp_fixing.restype = C.c_int
     # linear-constraint propagation and branching
@@ -400,6 +402,16 @@ class Problem:
         cnt = C.c_int32()
         _check(load().pdlp_variable_strategy(self.h, int(strategy), int(tiebreak), *args, C.byref(cnt)))
         return order[:cnt.value].clone() if _is_cuda(order) else order[:cnt.value].copy()
+
+    def variable_strategy_noalloc(self, strategy, var_type, order, x=None, y=None, rc=None, tiebreak=ORDER_NONE):
+        """The same order computed without any device allocation (include/pdlp_fix.h): every argument
+        is a contiguous torch tensor on the handle's GPU, `order` (int32, at least n entries) is the
+        caller's output buffer. Returns the number of ordered variables."""
+        _torch().cuda.current_stream().synchronize()  # inputs written on torch's stream are complete
+        args = [_dptr(var_type)] + [None if a is None else _dptr(a) for a in (x, y, rc)] + [_dptr(order)]
+        cnt = C.c_int32()
+        _check(load().pdlp_variable_strategy_noalloc(self.h, int(strategy), int(tiebreak), *args, C.byref(cnt)))
+        return cnt.value
 
     def lp_fixing(self, var_type, x, l, u, uniform):
         """Fixing value of every variable under LP-based fixing (continuous ones keep x); numpy
