@@ -6,9 +6,12 @@ pdlp_create) of the general sparse LP: m = 500,000 rows, n = 1,000,000 columns, 
 capped at 5,000 (27.35M nonzeros for seed 0), 40 % equality / 60 % <= rows, 70 % boxed / 30 % free
 columns, FP32 iterates and matrix with FP64 norms, to relative KKT error 1e-4.
 
-Printed: one JSON line (metric, value = median seconds per solve, roofline of the fused A x + dual
-update kernel measured with HIP events during the timed solves, FP64 cold-solve comparison, and the
-FP64 CPU oracle timed on a bounded sample as cpu_baseline). Progress goes to stderr.
+Printed: one JSON line: metric, value = median seconds per solve (the production configuration:
+each evaluation interval replayed from a captured hipGraph); the roofline of the dominant iteration
+kernel by measured time, from a separate solve of the same LP whose launches are bracketed by HIP
+events on the handle's stream; the FP64 cold solve; other seeds of the same generator (bounded);
+the learned warm start on held-out LPs; and the FP64 CPU oracle timed on a bounded sample as
+cpu_baseline. Progress goes to stderr.
 """
 import argparse
 import json
@@ -23,13 +26,12 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# HBM bytes per k_dual launch measured by rocprofv3 (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the
-# factors of a 256 MiB device copy), keyed by workload and by the SHA-1 of the sources the kernel and
-# its launch configuration are built from; any change to them makes the figure stale (reported null).
+# HBM bytes per launch of the dominant kernel measured by rocprofv3 (FETCH_SIZE x 2.000 + WRITE_SIZE
+# x 1.000, the factors of a 256 MiB device copy), keyed by workload, kernel and the SHA-1 of the
+# sources the kernels and their launch configuration are built from; any change to them makes the
+# figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
-MEASURED_TRAFFIC = {  # {(workload, sha1): bytes per k_dual launch}; commands and raw figures in profiles/
-    ("zipf", "00dca0defda824aa8625a8477725300a5fb560d4"): 436_974_037,
-    ("energy", "00dca0defda824aa8625a8477725300a5fb560d4"): 460_483_544,
+MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; commands and raw figures in profiles/
 }
 
 
@@ -112,7 +114,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1000, help="oracle attempts in the CPU sample")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start comparison")
-    ap.add_argument("--warm-instances", type=int, default=48)
+    ap.add_argument("--warm-instances", type=int, default=200)
+    ap.add_argument("--other-seeds", default="1,2", help="further seeds of the workload, solved once each")
+    ap.add_argument("--other-seeds-limit", type=int, default=150_000)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known size for scaling "
@@ -152,9 +156,9 @@ def main():
     lp, desc = make_workload(args.workload, args.seed)
     log(f"workload generated in {time.time() - t:.1f} s: m={lp.m} n={lp.n} nnz={lp.nnz}")
 
-    # ---------------- FP32 solves (the measured configuration) ----------------
+    # ---------------- FP32 solves (the measured configuration: hipGraphs, no timing events) ----------
     t = time.time()
-    p = pdlp.Problem(lp, precision="fp32", kernel_timing=True)
+    p = pdlp.Problem(lp, precision="fp32")
     torch.cuda.synchronize()
     create_s = time.time() - t
     sched = p.schedule()
@@ -162,7 +166,7 @@ def main():
     for w in range(args.warmup):
         info = p.solve(tol=args.tol, iter_limit=args.iter_limit)
         log(f"warmup {w}: {info['status_name']} iters={info['iterations']} {info['solve_seconds']:.3f} s")
-    times, iters, kstats = [], [], []
+    times, iters = [], []
     info = None
     for s in range(args.steps):
         torch.cuda.synchronize()
@@ -172,31 +176,41 @@ def main():
         dt = time.perf_counter() - t0
         times.append(dt)
         iters.append(info["iterations"])
-        kstats.append(p.kernel_stats())
         log(f"step {s}: {info['status_name']} iters={info['iterations']} restarts={info['restarts']} "
             f"rel_kkt={info['rel_kkt']:.2e} obj={info['primal_obj']:.10g} {dt:.3f} s")
     sol = p.get()
     sec = statistics.median(times)
     it = int(statistics.median(iters))
+    p.close()
 
+    # ---------------- kernel durations: a separate solve with HIP events around every launch ---------
+    # (graphs are off in that mode; the trajectory is the same bit for bit)
+    pk = pdlp.Problem(lp, precision="fp32", kernel_timing=True)
+    ik = pk.solve(tol=args.tol, iter_limit=args.iter_limit)
+    ks = pk.kernel_stats()
+    pk.close()
+    log(f"timing solve: {ik['iterations']} iterations (timed solves: {it}), {ik['solve_seconds']:.3f} s with events")
     tb = 4
     kern = {}
-    for name in ("dual", "primal"):
-        launches = sum(k[name]["launches"] for k in kstats)
-        total = sum(k[name]["total_ms"] for k in kstats)
-        avg_ms = total / max(launches, 1)
+    # the A side of an attempt is k_panel (column-panel sums of the long rows, when used) + k_dual
+    a_us = ks["dual"]["avg_ms"] * 1e3 + (ks["panel"]["avg_ms"] * 1e3 if ks["panel"]["launches"] else 0.0)
+    sides = {"dual": (a_us, ks["dual"]["launches"]), "primal": (ks["primal"]["avg_ms"] * 1e3, ks["primal"]["launches"])}
+    for name, (us, launches) in sides.items():
         bytes_ = algorithmic_bytes(name, lp.m, lp.n, lp.nnz, tb)
-        kern[name] = dict(launches=launches, avg_us=avg_ms * 1e3, alg_bytes=bytes_,
-                          gbs=bytes_ / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None)
-    dom = kern["dual"]
-    traffic = MEASURED_TRAFFIC.get((args.workload, kernel_source_sha1()))
+        gbs = bytes_ / (us * 1e-6) / 1e9 if us > 0 else None
+        kern[name] = dict(launches=launches, avg_us=us, alg_bytes=bytes_, gbs=gbs,
+                          frac=(gbs / PEAK_HBM_GBS) if gbs else None)
+    if ks["panel"]["launches"]:
+        kern["dual"]["of_which_k_panel_us"] = ks["panel"]["avg_ms"] * 1e3
+    dname = max(kern, key=lambda k: kern[k]["avg_us"])  # dominant by measured time per attempt
+    dom = kern[dname]
+    traffic = MEASURED_TRAFFIC.get((args.workload, dname, kernel_source_sha1()))
+    label = {"dual": "k_panel + k_dual (A x' with the dual update and step-size sums)",
+             "primal": "k_primal (A'y' with the primal update and the averages)"}[dname]
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": "k_dual (A x' + dual update + step-size reductions)",
-                "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": round(dom["avg_us"], 2)}
+                "kernel": label, "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": round(dom["avg_us"], 2)}
     log(f"kernels: {json.dumps(kern)}")
-
-    p.close()
 
     # ---------------- FP64 cold solve (comparison) ----------------
     fp64 = None
@@ -213,6 +227,24 @@ def main():
                     primal_obj=i64["primal_obj"], create_s=round(c64, 2))
         log(f"fp64 cold: {i64['status_name']} iters={i64['iterations']} {s64:.3f} s obj={i64['primal_obj']:.10g}")
         p64.close()
+
+    # ---------------- other seeds of the same generator (time to tolerance is heavy-tailed) ----------
+    others = []
+    for sd in [int(v) for v in args.other_seeds.split(",") if v.strip()]:
+        if args.workload != "zipf":
+            break
+        lpo, _ = make_workload(args.workload, sd)
+        po = pdlp.Problem(lpo, precision="fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        io = po.solve(tol=args.tol, iter_limit=args.other_seeds_limit)
+        torch.cuda.synchronize()
+        dto = time.perf_counter() - t0
+        others.append({"seed": sd, "status": io["status_name"], "iterations": io["iterations"], "seconds": round(dto, 3),
+                       "rel_kkt": io["rel_kkt"], "nnz": lpo.nnz, "iteration_cap": args.other_seeds_limit})
+        log(f"seed {sd}: {io['status_name']} iters={io['iterations']} rel_kkt={io['rel_kkt']:.2e} {dto:.3f} s")
+        po.close()
+        del lpo
 
     # ---------------- CPU baseline: the FP64 oracle on a bounded sample ----------------
     cpu, chk = None, {"rel_kkt": None}
@@ -271,6 +303,7 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "fp64_cold": fp64,
+        "other_seeds": others,
         "warm_start": warm,
         "cpu_baseline": cpu,
     }

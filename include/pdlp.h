@@ -82,7 +82,12 @@ typedef struct pdlp_options {
   int32_t single_avg_updates; /* FP32 pairs the running-average updates of consecutive accepted
                               attempts (one pass over x-bar and y-bar for two updates); 1 = update on
                               every accepted attempt instead. Both give the same bits (default 0) */
-  int32_t reserved[4];
+  int32_t panel_rows;      /* FP32: rows of A with at least this many nonzeros are summed by column
+                              panels (x held in LDS panel by panel, per-panel row sums added in panel
+                              order) when such rows carry at least half of an instance's nonzeros;
+                              0 = 64 (default 0), -1 = never. FP64 handles always use the chunk
+                              engine */
+  int32_t reserved[3];
 } pdlp_options;
 
 typedef struct pdlp_result {
@@ -146,7 +151,9 @@ int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_resul
 /*
  * y = A x (trans = 0, x [n], y [m]) or y = A' x (trans = 1, x [m], y [n]) with the ORIGINAL
  * (unscaled) matrix, computed by the library's SpMV kernels in the handle's precision on the
- * handle's stream. x and y are host pointers unless device_ptrs is set.
+ * handle's stream. trans = 2 computes A x the way the PDHG iteration forms it (FP32 handles sum
+ * the long rows of A by column panels, see pdlp_options.panel_rows; otherwise the same as 0).
+ * x and y are host pointers unless device_ptrs is set.
  */
 int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y);
 
@@ -174,6 +181,8 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
  * Kernel timing of the last pdlp_solve with pdlp_options.kernel_timing = 1.
  *   kernel 0: A x' fused with the dual update and the step-size partial sums
  *   kernel 1: A'y' fused with the primal update and the iterate averages
+ *   kernel 2: the column-panel sums of the long rows of A x' (launched before kernel 0 when the
+ *             handle uses column panels; no launches otherwise)
  * (the step-size decision itself runs in a small per-instance kernel between them and is not timed)
  * *launches receives the number of launches, *total_ms their summed HIP-event durations.
  */

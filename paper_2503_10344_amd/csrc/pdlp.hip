@@ -164,11 +164,97 @@ static void build_chunks(const int32_t *rp, int32_t r0, int32_t r1, int cap, std
   cls.push_back((int8_t)c_start);
 }
 
-// Stable order of the items [lo, hi) by descending length class; out receives old indices.
+// Stable order of the items [lo, hi) by descending length (so also by descending length class, and
+// rows of similar length sit together for the column-panel blocks); out receives old indices.
 static void class_order(const std::vector<int64_t> &len, int32_t lo, int32_t hi, std::vector<int32_t> &out) {
-  std::vector<int32_t> bucket[7];
-  for (int32_t i = lo; i < hi; ++i) bucket[length_class(len[(size_t)(i - lo)])].push_back(i);
-  for (int c = 6; c >= 0; --c) out.insert(out.end(), bucket[c].begin(), bucket[c].end());
+  std::vector<int32_t> idx;
+  idx.reserve((size_t)(hi - lo));
+  for (int32_t i = lo; i < hi; ++i) idx.push_back(i);
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int32_t a, int32_t b) { return len[(size_t)(a - lo)] > len[(size_t)(b - lo)]; });
+  out.insert(out.end(), idx.begin(), idx.end());
+}
+
+// Column-panel layout of the long rows (host side; see Panels in pdlp_internal.h).
+constexpr int kPanelDefaultMinRow = 64;  // rows at least this long are summed by column panels
+constexpr int kPanelEntries = 16384;     // target entries per (row block, panel) work group
+constexpr int kPanelMaxRows = 4096;      // rows per row block at most
+constexpr int kPanelMaxPanels = 256;     // instances with more x panels keep the chunk engine
+struct PanelHost {
+  std::vector<int32_t> wg_rb, wg_p, rb_inst, rb_lrow0, rb_R, rb_G, src;
+  std::vector<int64_t> wg_ebase, wg_obase;
+  std::vector<uint16_t> off, col;
+  void append(const PanelHost &o) {
+    auto cat = [](auto &a, const auto &b) { a.insert(a.end(), b.begin(), b.end()); };
+    cat(wg_rb, o.wg_rb), cat(wg_p, o.wg_p), cat(rb_inst, o.rb_inst), cat(rb_lrow0, o.rb_lrow0);
+    cat(rb_R, o.rb_R), cat(rb_G, o.rb_G), cat(src, o.src), cat(wg_ebase, o.wg_ebase), cat(wg_obase, o.wg_obase);
+    cat(off, o.off), cat(col, o.col);
+  }
+};
+
+// Long rows of one instance (rows [r0, r0 + R) in internal order, columns [c0, c0 + nq)) cut into
+// row blocks and panels. ci: internal column of each entry. src receives the CSR position of every
+// entry of the layout (its value is gathered on the device). Returns false when a work group would
+// need offsets beyond 16 bits (the instance then keeps the chunk engine for all rows).
+static bool build_panels(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int q, int32_t r0,
+                         int32_t R, int32_t c0, int32_t nq, PanelHost &H) {
+  const int P = (nq + kPanelW - 1) / kPanelW;
+  const int64_t target = (int64_t)kPanelEntries * P;
+  const int64_t e0 = (int64_t)H.col.size(), o0 = (int64_t)H.off.size();
+  const int rb0 = (int)H.rb_R.size();
+  PanelHost out;
+  int32_t r = 0;
+  std::vector<int32_t> cnt;
+  while (r < R) {
+    int32_t e = r;
+    int64_t acc = 0;
+    while (e < R && (e == r || (acc + (rp[r0 + e + 1] - rp[r0 + e]) <= target && e - r < kPanelMaxRows))) {
+      acc += rp[r0 + e + 1] - rp[r0 + e];
+      ++e;
+    }
+    for (;;) {  // shrink the block until every (block, panel) holds fewer than 2^16 entries
+      const int32_t nr = e - r;
+      cnt.assign((size_t)P * (nr + 1), 0);
+      for (int32_t i = 0; i < nr; ++i)
+        for (int32_t k = rp[r0 + r + i]; k < rp[r0 + r + i + 1]; ++k) cnt[(size_t)((ci[k] - c0) / kPanelW) * (nr + 1) + i + 1]++;
+      int64_t worst = 0;
+      for (int p = 0; p < P; ++p) {
+        int64_t t = 0;
+        for (int32_t i = 0; i <= nr; ++i) t += cnt[(size_t)p * (nr + 1) + i];
+        worst = std::max(worst, t);
+      }
+      if (worst < 65536) break;
+      if (nr == 1) return false;
+      e = r + nr / 2;
+    }
+    const int32_t nr = e - r;
+    const int rb = rb0 + (int)out.rb_R.size();
+    int64_t bnnz = (int64_t)rp[r0 + e] - rp[r0 + r];
+    const double seg = (double)bnnz / nr / P / 4.0;  // entries per lane and panel with G lanes a row
+    int G = 1;
+    while (G < 64 && 2.0 * G <= seg) G *= 2;
+    out.rb_inst.push_back(q), out.rb_lrow0.push_back(r), out.rb_R.push_back(nr), out.rb_G.push_back(G);
+    for (int p = 0; p < P; ++p) {
+      out.wg_rb.push_back(rb), out.wg_p.push_back(p);
+      out.wg_ebase.push_back(e0 + (int64_t)out.col.size());
+      out.wg_obase.push_back(o0 + (int64_t)out.off.size());
+      int64_t run = 0;
+      out.off.push_back(0);
+      for (int32_t i = 0; i < nr; ++i) {
+        for (int32_t k = rp[r0 + r + i]; k < rp[r0 + r + i + 1]; ++k) {
+          const int32_t lc = ci[k] - c0;
+          if (lc / kPanelW != p) continue;
+          out.col.push_back((uint16_t)(lc - p * kPanelW));
+          out.src.push_back(k);
+          ++run;
+        }
+        out.off.push_back((uint16_t)run);
+      }
+    }
+    r = e;
+  }
+  H.append(out);
+  return true;
 }
 
 static const int kChunkCandidates[] = {512, 1024, 2048, 4096};
@@ -239,10 +325,26 @@ struct Solver {
   hipGraphExec_t graph = nullptr;
   // kernel timing (opt.kernel_timing): two pools of start/stop events per attempt and kernel
   std::vector<hipEvent_t> tev[2];
-  int64_t t_launches[2] = {0, 0};
-  double t_ms[2] = {0.0, 0.0};
+  int64_t t_launches[3] = {0, 0, 0};
+  double t_ms[3] = {0.0, 0.0, 0.0};
   Iter<T> P{};
   std::shared_ptr<void> fix_cache;  // workspace of the LP-based variable strategies, kept between calls
+  // column-panel path of the long rows of A (FP32; PQ.nwg == 0: off). h_lr_*: see Layout.
+  Panels<T> PQ{};
+  double *part = nullptr;
+  int64_t part_len = 0, pan_entries = 0;
+  int32_t *pan_src = nullptr;  // CSR position of each layout entry (set-up only)
+  std::vector<int32_t> h_lr_R, h_lr_P;
+  std::vector<int64_t> h_lr_base;
+  int32_t *d_lr_R = nullptr, *d_lr_P = nullptr;
+  int64_t *d_lr_base = nullptr;
+  // iteration layout of the A side (k_dual): per instance a skipped chunk over its long rows, the
+  // chunks of its other rows, then the long-row blocks. Equal to the product layout without panels.
+  int32_t *ia_chunk_row = nullptr;
+  int8_t *ia_chunk_cls = nullptr;
+  int32_t *d_ia_ab0 = nullptr, *d_ia_ab_inst = nullptr, *d_ia_bchunk = nullptr, *d_ab_nchunk = nullptr;
+  std::vector<int32_t> h_ia_ab0;
+  int ia_blocks = 1;
   // reference snapshots (restart points within snap.rel_tol; off while snap.K == 0)
   Snap snap{};
   bool solved = false;
@@ -357,6 +459,25 @@ struct Solver {
       sig = buf;
     }
 
+    // ---- column-panel layout of the long rows (FP32 iterations only) ----
+    h_lr_R.assign((size_t)K, 0), h_lr_P.assign((size_t)K, 0), h_lr_base.assign((size_t)K, 0);
+    PanelHost PH;
+    if (sizeof(T) == sizeof(float) && o.panel_rows >= 0) {
+      const int min_row = o.panel_rows > 0 ? o.panel_rows : kPanelDefaultMinRow;
+      for (int q = 0; q < K; ++q) {
+        const int32_t r0 = h_row0[q], r1 = h_row0[q + 1], c0 = h_col0[q], nq = h_col0[q + 1] - c0;
+        int32_t R = 0;
+        while (r0 + R < r1 && h_arp[r0 + R + 1] - h_arp[r0 + R] >= min_row) ++R;
+        const int64_t long_nnz = (int64_t)h_arp[r0 + R] - h_arp[r0], inst_nnz = (int64_t)h_arp[r1] - h_arp[r0];
+        const int P = (nq + kPanelW - 1) / kPanelW;
+        // worth it when the long rows carry most of the instance's nonzeros
+        if (R == 0 || nq == 0 || 2 * long_nnz < inst_nnz || P > kPanelMaxPanels) continue;
+        if (!build_panels(h_arp, ci, q, r0, R, c0, nq, PH)) continue;
+        h_lr_R[q] = R, h_lr_P[q] = P, h_lr_base[q] = part_len;
+        part_len += (int64_t)P * R;
+      }
+    }
+
     const int64_t mm = std::max(m, 1), nn = std::max(n, 1);
     a_rp = alloc_upload(h_arp);
     a_ci = alloc_upload(ci);
@@ -378,6 +499,19 @@ struct Solver {
     h_st.resize((size_t)K);
     last.assign((size_t)K, pdlp_result{});
     ci.clear(), ci.shrink_to_fit(), val.clear(), val.shrink_to_fit();
+    d_lr_R = alloc_upload(h_lr_R), d_lr_P = alloc_upload(h_lr_P), d_lr_base = alloc_upload(h_lr_base);
+    if (!PH.wg_rb.empty()) {
+      PQ.nwg = (int32_t)PH.wg_rb.size();
+      PQ.wg_rb = alloc_upload(PH.wg_rb), PQ.wg_p = alloc_upload(PH.wg_p);
+      PQ.wg_ebase = alloc_upload(PH.wg_ebase), PQ.wg_obase = alloc_upload(PH.wg_obase);
+      PQ.rb_inst = alloc_upload(PH.rb_inst), PQ.rb_lrow0 = alloc_upload(PH.rb_lrow0);
+      PQ.rb_R = alloc_upload(PH.rb_R), PQ.rb_G = alloc_upload(PH.rb_G);
+      PQ.off = alloc_upload(PH.off), PQ.col = alloc_upload(PH.col);
+      pan_src = alloc_upload(PH.src);
+      pan_entries = (int64_t)PH.src.size();
+      part = mem.alloc<double>(std::max<int64_t>(part_len, 1));
+    }
+    PH = PanelHost{};
 
     // ---- transpose (counting sort; the per-column sort of source positions makes it deterministic)
     int32_t *row_of = mem.alloc<int32_t>(nnz);
@@ -475,6 +609,16 @@ struct Solver {
       hipLaunchKernelGGL(k_convert<T>, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, (int64_t)nnz,
                          (const double *)t_v64, t_v);
     }
+    if (PQ.nwg > 0) {  // values of the panel layout, gathered from the iteration-precision matrix
+      T *pv = mem.alloc<T>(std::max<int64_t>(pan_entries, 1));
+      hipLaunchKernelGGL(k_gather_t<T>, dim3(grid_for(pan_entries)), dim3(kBlock), 0, stream, (int)pan_entries,
+                         (const int32_t *)pan_src, (const int32_t *)nullptr, (const T *)a_v, (int32_t *)nullptr, pv);
+      HIPCHK(hipGetLastError());
+      PQ.val = pv;
+      sync();
+      mem.release(pan_src);
+      pan_src = nullptr;
+    }
 
     // iterates and staging
     for (int q = 0; q < 2; ++q) xs[q] = mem.alloc<T>(nn), ys[q] = mem.alloc<T>(mm), axs[q] = mem.alloc<T>(mm);
@@ -509,7 +653,7 @@ struct Solver {
     ev_blocks = h_ev0.back();
     d_ev_inst = alloc_upload(ev_inst);
     d_ev0 = alloc_upload(h_ev0);
-    p_dual = mem.alloc<double>((int64_t)ab_blocks * 2);
+    p_dual = mem.alloc<double>((int64_t)ia_blocks * 2);
     p_primal = mem.alloc<double>(tb_blocks);
     p_restart = mem.alloc<double>(ev_blocks);
     p_eval = mem.alloc<double>((int64_t)ev_blocks * kEvalNV);
@@ -522,17 +666,18 @@ struct Solver {
     Layout &L = P.L;
     L.K = K;
     L.row0 = d_row0, L.col0 = d_col0, L.a_chunk0 = d_a_chunk0, L.t_chunk0 = d_t_chunk0;
-    L.ab0 = d_ab0, L.ab_inst = d_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
-    L.a_bchunk = d_a_bchunk, L.t_bchunk = d_t_bchunk;
+    L.ab0 = d_ia_ab0, L.ab_inst = d_ia_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
+    L.a_bchunk = d_ia_bchunk, L.t_bchunk = d_t_bchunk;
+    L.ab_nchunk = d_ab_nchunk, L.lr_R = d_lr_R, L.lr_P = d_lr_P, L.lr_base = d_lr_base;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
-    L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ab_blocks, L.tb_blocks = tb_blocks;
+    L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ia_blocks, L.tb_blocks = tb_blocks;
     L.ev_blocks = ev_blocks;
-    P.a_rp = a_rp, P.a_ci = a_ci, P.a_chunk_row = a_chunk_row, P.a_chunk_cls = a_chunk_cls, P.a_val = a_v;
+    P.a_rp = a_rp, P.a_ci = a_ci, P.a_chunk_row = ia_chunk_row, P.a_chunk_cls = ia_chunk_cls, P.a_val = a_v;
     P.t_rp = t_rp, P.t_ci = t_ci, P.t_chunk_row = t_chunk_row, P.t_chunk_cls = t_chunk_cls, P.t_val = t_v;
     P.c = cT, P.l = lT, P.u = uT, P.b = bT, P.sense = sense, P.Dr = Dr, P.Dc = Dc;
     for (int q = 0; q < 2; ++q) P.x[q] = xs[q], P.y[q] = ys[q], P.ax[q] = axs[q];
     P.aty = aty, P.xbar = xbar, P.ybar = ybar, P.axbar = axbar, P.atybar = atybar, P.xa = xa, P.ya = ya;
-    P.p_dual = p_dual, P.p_primal = p_primal, P.p_restart = p_restart, P.p_eval = p_eval;
+    P.p_dual = p_dual, P.p_primal = p_primal, P.p_restart = p_restart, P.p_eval = p_eval, P.part = part;
     P.st = st, P.ndone = ndone;
   }
 
@@ -553,7 +698,9 @@ struct Solver {
     }
     for (void *p : {(void *)a_chunk_row, (void *)t_chunk_row, (void *)a_chunk_cls, (void *)t_chunk_cls,
                     (void *)d_a_chunk0, (void *)d_t_chunk0, (void *)d_ab0, (void *)d_ab_inst, (void *)d_tb0,
-                    (void *)d_tb_inst, (void *)d_a_bchunk, (void *)d_t_bchunk})
+                    (void *)d_tb_inst, (void *)d_a_bchunk, (void *)d_t_bchunk, (void *)ia_chunk_row,
+                    (void *)ia_chunk_cls, (void *)d_ia_ab0, (void *)d_ia_ab_inst, (void *)d_ia_bchunk,
+                    (void *)d_ab_nchunk})
       if (p) mem.release(p);
     a_chunk_row = alloc_upload(ra), t_chunk_row = alloc_upload(rt);
     a_chunk_cls = alloc_upload(ca), t_chunk_cls = alloc_upload(ct);
@@ -600,6 +747,53 @@ struct Solver {
     d_ab0 = alloc_upload(h_ab0), d_ab_inst = alloc_upload(ab_inst);
     d_tb0 = alloc_upload(h_tb0), d_tb_inst = alloc_upload(tb_inst);
     d_a_bchunk = alloc_upload(a_bchunk), d_t_bchunk = alloc_upload(t_bchunk);
+
+    // Iteration layout of the A side (k_dual). Per instance: a chunk over its long rows that no
+    // block takes (their sums come from the column panels), the chunks of its other rows shared out
+    // by weight exactly as above, then one block per kBlock long rows. Blocks are given as (first,
+    // end) chunk pairs. Without long rows this is the layout above, block for block.
+    std::vector<int32_t> ri, ia_inst, ia_bc, ia_nch, cstart((size_t)K), cend((size_t)K);
+    std::vector<int8_t> ci8;
+    for (int q = 0; q < K; ++q) {
+      const int32_t rs = h_row0[q] + h_lr_R[q];
+      if (ri.empty()) ri.push_back(h_row0[q]);
+      if (h_lr_R[q] > 0) ri.push_back(rs), ci8.push_back(6);
+      cstart[q] = (int32_t)ci8.size();
+      build_chunks(h_arp.data(), rs, h_row0[q + 1], cap, ri, ci8);
+      cend[q] = (int32_t)ci8.size();
+    }
+    {
+      const int nch = (int)ci8.size();
+      std::vector<int64_t> wpre((size_t)nch + 1, 0);
+      for (int c = 0; c < nch; ++c)
+        wpre[c + 1] = wpre[c] + (h_arp[ri[c + 1]] - h_arp[ri[c]]) + (ri[c + 1] - ri[c]);
+      h_ia_ab0.assign(1, 0);
+      for (int q = 0; q < K; ++q) {
+        const int c0 = cstart[q], c1 = cend[q];
+        const int64_t wq = wpre[c1] - wpre[c0];
+        int64_t nbq = std::min<int64_t>(work_blocks, (wq + kMinBlockWeight - 1) / kMinBlockWeight);
+        nbq = std::max<int64_t>(1, std::min<int64_t>(nbq, std::max(c1 - c0, 1)));
+        std::vector<int32_t> starts;
+        int c = c0;
+        for (int64_t lb = 0; lb < nbq; ++lb) {
+          const int64_t target = wpre[c0] + (wq * lb + nbq - 1) / nbq;
+          while (c < c1 && wpre[c] < target) ++c;
+          starts.push_back(c);
+        }
+        for (int64_t lb = 0; lb < nbq; ++lb) {
+          ia_bc.push_back(starts[lb]), ia_bc.push_back(lb + 1 < nbq ? starts[lb + 1] : c1);
+          ia_inst.push_back(q);
+        }
+        const int nlong = (h_lr_R[q] + kBlock - 1) / kBlock;
+        for (int j = 0; j < nlong; ++j) ia_bc.push_back(c1), ia_bc.push_back(c1), ia_inst.push_back(q);
+        ia_nch.push_back((int32_t)nbq);
+        h_ia_ab0.push_back(h_ia_ab0.back() + (int32_t)nbq + nlong);
+      }
+    }
+    ia_blocks = h_ia_ab0.back();
+    ia_chunk_row = alloc_upload(ri), ia_chunk_cls = alloc_upload(ci8);
+    d_ia_ab0 = alloc_upload(h_ia_ab0), d_ia_ab_inst = alloc_upload(ia_inst);
+    d_ia_bchunk = alloc_upload(ia_bc), d_ab_nchunk = alloc_upload(ia_nch);
   }
 
   template <typename V, typename X, typename Acc, typename Y>
@@ -677,8 +871,12 @@ struct Solver {
   // ---------------------------------------------------------------------------------------------
   // Iteration launches
   // ---------------------------------------------------------------------------------------------
+  void launch_panels() {
+    if (PQ.nwg > 0) hipLaunchKernelGGL(k_panel<T>, dim3(PQ.nwg), dim3(kPanelBlock), 0, stream, P, PQ);
+  }
   void launch_attempt() {
-    hipLaunchKernelGGL(k_dual<T>, dim3(ab_blocks), dim3(kBlock), 0, stream, P);
+    launch_panels();
+    hipLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P);
     launch_step();
     hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
   }
@@ -717,34 +915,40 @@ struct Solver {
     refresh_averages();
     launch_eval_restart();
   }
-  // Direct launches bracketed by events (pool `slot`): [attempt][kernel][start, stop].
+  // Direct launches bracketed by events (pool `slot`): per attempt [k_panel start, k_dual start,
+  // k_dual stop, k_primal start, k_primal stop].
   void launch_chunk_timed(int slot) {
     auto &pool = tev[slot];
     if (pool.empty()) {
-      pool.resize((size_t)opt.eval_every * 4);
+      pool.resize((size_t)opt.eval_every * 5);
       for (auto &e : pool) HIPCHK(hipEventCreate(&e));
     }
     for (int r = 0; r < opt.eval_every; ++r) {
-      hipEvent_t *e = &pool[(size_t)r * 4];
+      hipEvent_t *e = &pool[(size_t)r * 5];
       HIPCHK(hipEventRecord(e[0], stream));
-      hipLaunchKernelGGL(k_dual<T>, dim3(ab_blocks), dim3(kBlock), 0, stream, P);
+      launch_panels();
       HIPCHK(hipEventRecord(e[1], stream));
-      launch_step();
+      hipLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P);
       HIPCHK(hipEventRecord(e[2], stream));
-      hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
+      launch_step();
       HIPCHK(hipEventRecord(e[3], stream));
+      hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
+      HIPCHK(hipEventRecord(e[4], stream));
     }
     refresh_averages();
     launch_eval_restart();
     HIPCHK(hipGetLastError());
   }
-  // Add the durations recorded in pool `slot` (its chunk has completed).
+  // Add the durations recorded in pool `slot` (its chunk has completed): kernel 0 = k_dual,
+  // 1 = k_primal, 2 = k_panel (counted only when the handle uses column panels).
   void collect_times(int slot) {
     auto &pool = tev[slot];
+    static const int kFrom[3] = {1, 3, 0}, kTo[3] = {2, 4, 1};
     for (int r = 0; r < opt.eval_every && !pool.empty(); ++r)
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < 3; ++k) {
+        if (k == 2 && PQ.nwg == 0) continue;
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 4 + 2 * k], pool[(size_t)r * 4 + 2 * k + 1]));
+        HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 5 + kFrom[k]], pool[(size_t)r * 5 + kTo[k]]));
         t_ms[k] += ms;
         t_launches[k] += 1;
       }
@@ -843,8 +1047,8 @@ struct Solver {
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));
     if (snap.K > 0) HIPCHK(hipMemsetAsync(snap.taken, 0, sizeof(int32_t) * (size_t)K, stream));
-    t_launches[0] = t_launches[1] = 0;
-    t_ms[0] = t_ms[1] = 0.0;
+    t_launches[0] = t_launches[1] = t_launches[2] = 0;
+    t_ms[0] = t_ms[1] = t_ms[2] = 0.0;
     const bool warm = stage_start(x0s, y0s);
     std::vector<int> fallback((size_t)K, 0), warm_q((size_t)K, 0);
     for (int q = 0; q < K; ++q) warm_q[q] = (x0s && x0s[q]) || (y0s && y0s[q]);
@@ -1063,7 +1267,20 @@ struct Solver {
 
   // Original-space product y = A x = Dr^-1 A~ Dc^-1 x (trans = 0) or y = A'x (trans = 1), in the
   // caller's numbering.
-  void spmv(int trans, const double *x, double *y) {
+  // A x as the iteration forms it: long rows by column panels (k_panel_x, k_long_sum), the other
+  // rows by the chunks of the iteration layout.
+  void spmv_iter(const T *x, T *y) {
+    if (PQ.nwg > 0) {
+      hipLaunchKernelGGL(k_panel_x<T>, dim3(PQ.nwg), dim3(kPanelBlock), 0, stream, P.L, PQ, x, part);
+      hipLaunchKernelGGL(k_long_sum<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P.L, (const double *)part, y);
+    }
+    hipLaunchKernelGGL((k_spmv_pairs<T, T, double, T>), dim3(ia_blocks), dim3(kBlock), 0, stream, (const int32_t *)a_rp,
+                       (const int32_t *)a_ci, (const T *)a_v, (const int32_t *)ia_chunk_row, (const int8_t *)ia_chunk_cls,
+                       (const int32_t *)d_ia_ab0, (const int32_t *)d_ia_ab_inst, (const int32_t *)d_ia_bchunk, x, y);
+  }
+
+  void spmv(int trans_mode, const double *x, double *y) {
+    const int trans = trans_mode == 1;
     const int in = trans ? m : n, out = trans ? n : m;
     double *sin = trans ? stage_m : stage_n;
     double *xin = trans ? yd : xd;
@@ -1077,7 +1294,8 @@ struct Solver {
     gather64(in, sin, trans ? d_perm_r : d_perm_c, xin);
     hipLaunchKernelGGL(k_div_to<T>, dim3(grid_for(in)), dim3(kBlock), 0, stream, in, (const double *)xin,
                        (const double *)(trans ? Dr : Dc), tin);
-    spmv_T(trans, tin, tout);
+    if (trans_mode == 2) spmv_iter(tin, tout);
+    else spmv_T(trans, tin, tout);
     hipLaunchKernelGGL(k_div_from<T>, dim3(grid_for(out)), dim3(kBlock), 0, stream, out, (const T *)tout,
                        (const double *)(trans ? Dc : Dr), yint);
     gather64(out, yint, trans ? d_inv_c : d_inv_r, sout);
@@ -1319,7 +1537,7 @@ int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_resul
 }
 
 int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y) {
-  if (!p || !x || !y || (trans != 0 && trans != 1)) {
+  if (!p || !x || !y || trans < 0 || trans > 2) {
     pdlp::g_last_error = "bad argument to pdlp_spmv";
     return PDLP_ERR_ARG;
   }
@@ -1360,7 +1578,7 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
 }
 
 int pdlp_kernel_stats(pdlp_problem *p, int32_t kernel, int64_t *launches, double *total_ms) {
-  if (!p || kernel < 0 || kernel > 1) {
+  if (!p || kernel < 0 || kernel > 2) {
     pdlp::g_last_error = "bad argument to pdlp_kernel_stats";
     return PDLP_ERR_ARG;
   }

@@ -19,6 +19,11 @@ constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kWaves = kBlock / kWave;
 constexpr int kEvalNV = 18;   // per-block partial sums of the evaluation kernel
 constexpr int kEvalSpan = 2048;    // elements per evaluation block (target)
+// Column-panel path of A x for long rows (FP32): x is cut into panels of kPanelW entries that a
+// work group keeps in LDS while it sums its rows' entries in that panel; the per-panel sums of a
+// row (FP64) are added up in panel order by the kernel that runs the row's epilogue.
+constexpr int kPanelW = 16384;     // x entries per panel (64 KB of FP32 in LDS)
+constexpr int kPanelBlock = 1024;  // threads per panel work group
 
 enum RestartMode : int32_t { kNoRestart = 0, kToCurrent = 1, kToAverage = 2 };
 enum EvalMode : int32_t { kEvalInit = 0, kEvalChunk = 1, kEvalPoint = 2 };
@@ -69,9 +74,31 @@ struct Layout {
   const int32_t *a_chunk0, *t_chunk0; // [K+1] chunk ranges of A and A'
   const int32_t *ab0, *ab_inst;     // [K+1], [ab_blocks] A-side work blocks (k_dual)
   const int32_t *tb0, *tb_inst;     // [K+1], [tb_blocks] A'-side work blocks (k_primal)
-  const int32_t *a_bchunk, *t_bchunk; // [blocks+1] first chunk of each work block (nnz-balanced)
+  const int32_t *a_bchunk;           // [2 ab_blocks] first and end chunk of each A-side work block
+  const int32_t *t_bchunk;           // [tb_blocks + 1] first chunk of each A'-side work block
   const int32_t *ev_blk0, *ev_inst; // [K+1], [ev_blocks] evaluation blocks
   int32_t a_nchunks, t_nchunks, ab_blocks, tb_blocks, ev_blocks;
+  // long rows of A (column-panel path): the first lr_R[q] rows of instance q; their panel sums are
+  // part[lr_base[q] + p * lr_R[q] + r], p < lr_P[q]. Of the instance's A-side blocks the first
+  // ab_nchunk[q] run chunks, the others finish kBlock long rows each. All zero without the path.
+  const int32_t *ab_nchunk, *lr_R, *lr_P;
+  const int64_t *lr_base;
+};
+
+// Column-panel work groups: (row block, panel) pairs. A row block is a run of consecutive long rows
+// of one instance; its entries in panel p are stored row by row (each row's in CSR order) as a
+// 16-bit column offset within the panel and a value, with per-row start offsets (16-bit, relative
+// to the work group's first entry).
+template <typename T>
+struct Panels {
+  int32_t nwg;
+  const int32_t *wg_rb, *wg_p;      // [nwg] row block and panel of each work group
+  const int64_t *wg_ebase;          // [nwg] first entry of the work group
+  const int64_t *wg_obase;          // [nwg] first of its R + 1 row offsets
+  const int32_t *rb_inst, *rb_lrow0, *rb_R, *rb_G;  // row block: instance, first long row (index
+                                    // within the instance), rows, lanes per row
+  const uint16_t *off, *col;
+  const T *val;
 };
 
 // Everything an iteration kernel reads or writes. Passed by value.
@@ -101,6 +128,7 @@ struct Iter {
   double *p_primal;   // [tb_blocks]     |dx|^2 of the primal candidate
   double *p_restart;  // [ev_blocks]     |dx|^2 after a restart
   double *p_eval;     // [ev_blocks][kEvalNV]
+  double *part;       // panel sums of the long rows (see Layout)
   State *st;
   int32_t *ndone;  // number of instances with done == 1
 };

@@ -310,6 +310,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int32_t *__restrict__ rp,
                           [&](int) { return NoPre{}; }, [&](int i, Acc s, NoPre) { y[i] = Y(s); });
 }
 
+// The same product over a layout whose blocks are (first, end) chunk pairs (the A-side iteration
+// layout; its long-row blocks have no chunks).
+template <typename V, typename X, typename Acc, typename Y>
+__global__ __launch_bounds__(kBlock) void k_spmv_pairs(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                       const V *__restrict__ val, const int32_t *__restrict__ chunk_row,
+                                                       const int8_t *__restrict__ chunk_cls,
+                                                       const int32_t *__restrict__ b0, const int32_t *__restrict__ binst,
+                                                       const int32_t *__restrict__ bpair, const X *__restrict__ x,
+                                                       Y *__restrict__ y) {
+  const WBlock w = work_block(b0, binst);
+  const int gb = b0[w.inst] + w.lb;
+  block_chunks<V, X, Acc>(rp, ci, val, x, chunk_row, chunk_cls, bpair[2 * gb], bpair[2 * gb + 1],
+                          [&](int) { return NoPre{}; }, [&](int i, Acc s, NoPre) { y[i] = Y(s); });
+}
+
 // Balanced contiguous share [*lo, *hi) of `count` items for block lb of nb.
 __device__ __forceinline__ void share(int base, int count, int lb, int nb, int *lo, int *hi) {
   *lo = base + (int)(((int64_t)lb * count) / nb);
@@ -317,7 +332,91 @@ __device__ __forceinline__ void share(int base, int count, int lb, int nb, int *
 }
 
 // ----------------------------------------------------------------------------------------------
-// One PDHG attempt is three launches: k_dual, k_step, k_primal. Block partial sums are finished
+// Column-panel sums of A x for the long rows (FP32). Rows of 64 or more nonzeros gather their x
+// values at random from the whole vector; served from L2 those gathers are bound by the number of
+// requests a compute unit can keep in flight, not by bytes. Here a work group takes one row block
+// and one panel of kPanelW consecutive columns: it copies that panel of x into LDS with coalesced
+// loads, then sums each row's entries in the panel with LDS gathers (G lanes per row, four FP64
+// accumulators per lane as in the chunk engine, then a G-lane shuffle tree) and writes the row's
+// panel sum. The row's epilogue adds its panel sums in panel order (k_dual, k_long_sum). Every
+// summation order is fixed by the layout, so results are deterministic.
+// ----------------------------------------------------------------------------------------------
+template <typename T, typename X>
+__device__ __forceinline__ void panel_sums(const Layout &L, const Panels<T> &Q, const X *__restrict__ x,
+                                           double *__restrict__ part, T *xs) {
+  const int wg = blockIdx.x;
+  const int rb = Q.wg_rb[wg], p = Q.wg_p[wg], q = Q.rb_inst[rb];
+  const int c0 = L.col0[q] + p * kPanelW;
+  const int cn = min(kPanelW, L.col0[q + 1] - c0);
+  for (int i = (int)threadIdx.x; i < cn; i += kPanelBlock) xs[i] = T(x[c0 + i]);
+  __syncthreads();
+  const int R = Q.rb_R[rb], G = Q.rb_G[rb];
+  const int64_t eb = Q.wg_ebase[wg];
+  const uint16_t *__restrict__ off = Q.off + Q.wg_obase[wg];
+  const uint16_t *__restrict__ col = Q.col + eb;
+  const T *__restrict__ val = Q.val + eb;
+  const int ng = kPanelBlock / G, g = (int)threadIdx.x / G, l = (int)threadIdx.x % G;
+  const int Rq = L.lr_R[q];
+  double *__restrict__ out = part + L.lr_base[q] + (int64_t)p * Rq + Q.rb_lrow0[rb];
+  for (int r = g; r < R; r += ng) {  // the G lanes of a group run the same rows
+    const int a = off[r], b = off[r + 1];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int e = a + l;
+    // plain (cached) loads: with few lanes per row the four strided loads of a lane share cache
+    // lines, which the streaming hint would fetch from L2 one load at a time (measured 25 % slower)
+    for (; e + 3 * G < b; e += 4 * G) {
+      const int k0 = col[e], k1 = col[e + G], k2 = col[e + 2 * G], k3 = col[e + 3 * G];
+      const T v0 = val[e], v1 = val[e + G], v2 = val[e + 2 * G], v3 = val[e + 3 * G];
+      s0 = acc_fma(s0, double(v0), double(xs[k0]));
+      s1 = acc_fma(s1, double(v1), double(xs[k1]));
+      s2 = acc_fma(s2, double(v2), double(xs[k2]));
+      s3 = acc_fma(s3, double(v3), double(xs[k3]));
+    }
+    for (; e < b; e += G) s0 = acc_fma(s0, double(val[e]), double(xs[col[e]]));
+    double s = (s0 + s1) + (s2 + s3);
+    for (int d = G >> 1; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+    if (l == 0) out[r] = s;
+  }
+}
+
+// The panel sums of A x' of one PDHG attempt (launched before k_dual).
+template <typename T>
+__global__ __launch_bounds__(kPanelBlock) void k_panel(Iter<T> P, Panels<T> Q) {
+  __shared__ T xs[kPanelW];
+  const State *st = P.st + Q.rb_inst[Q.wg_rb[blockIdx.x]];
+  if (st->done | st->stop) return;
+  panel_sums<T, T>(P.L, Q, P.x[st->cur ^ 1], P.part, xs);
+}
+
+// The panel sums of A x for a given x (products outside the iteration, diagnostics).
+template <typename T>
+__global__ __launch_bounds__(kPanelBlock) void k_panel_x(Layout L, Panels<T> Q, const T *__restrict__ x,
+                                                         double *__restrict__ part) {
+  __shared__ T xs[kPanelW];
+  panel_sums<T, T>(L, Q, x, part, xs);
+}
+
+// y_i = sum of row i's panel sums, for the long rows (grid: the A-side blocks of the iteration
+// layout; the chunk blocks return).
+template <typename Y>
+__global__ __launch_bounds__(kBlock) void k_long_sum(Layout L, const double *__restrict__ part, Y *__restrict__ y) {
+  const WBlock w = work_block(L.ab0, L.ab_inst);
+  const int nch = L.ab_nchunk[w.inst];
+  if (w.lb < nch) return;
+  const int Rq = L.lr_R[w.inst], Pq = L.lr_P[w.inst], r0 = L.row0[w.inst];
+  const double *__restrict__ pq = part + L.lr_base[w.inst];
+  const int j = w.lb - nch;
+  const int rhi = min((j + 1) * kBlock, Rq);
+  for (int r = j * kBlock + (int)threadIdx.x; r < rhi; r += kBlock) {
+    double s = 0.0;
+    for (int pn = 0; pn < Pq; ++pn) s += pq[(int64_t)pn * Rq + r];
+    y[r0 + r] = Y(s);
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// One PDHG attempt is three launches: k_dual, k_step, k_primal (k_panel first when a handle sums
+// long rows by column panels). Block partial sums are finished
 // by the per-instance k_step in the next launch, so no block ever needs a device-wide fence.
 //
 // k_dual: A x' fused with the dual update.
@@ -344,21 +443,36 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
     T y, ax, b;
     uint8_t s;
   };
-  int cb, ce;
-  cb = P.L.a_bchunk[P.L.ab0[w.inst] + w.lb], ce = P.L.a_bchunk[P.L.ab0[w.inst] + w.lb + 1];
+  auto pre = [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; };
   // The update is computed in FP64 from the stored operands and rounded once to T.
-  block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, cb, ce,
-                             [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; },
-                             [&](int i, double s, const DualPre &q) {
-                               const T axi = T(s);
-                               const double ax1 = double(axi), ax0 = double(q.ax), y0 = double(q.y);
-                               const T ynew = T(proj_dual(y0 + sigma * (double(q.b) - 2.0 * ax1 + ax0), q.s));
-                               yn[i] = ynew;
-                               axn[i] = axi;
-                               const double dy = double(ynew) - y0;
-                               acc[0] += dy * dy;
-                               acc[1] += dy * (ax1 - ax0);
-                             });
+  auto epi = [&](int i, double s, const DualPre &q) {
+    const T axi = T(s);
+    const double ax1 = double(axi), ax0 = double(q.ax), y0 = double(q.y);
+    const T ynew = T(proj_dual(y0 + sigma * (double(q.b) - 2.0 * ax1 + ax0), q.s));
+    yn[i] = ynew;
+    axn[i] = axi;
+    const double dy = double(ynew) - y0;
+    acc[0] += dy * dy;
+    acc[1] += dy * (ax1 - ax0);
+  };
+  const int nch = P.L.ab_nchunk[w.inst];
+  if (w.lb < nch) {
+    const int gb = P.L.ab0[w.inst] + w.lb;
+    block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, P.L.a_bchunk[2 * gb],
+                               P.L.a_bchunk[2 * gb + 1], pre, epi);
+  } else {
+    // long rows (column-panel path): the row sum is its panel sums added in panel order
+    const int Rq = P.L.lr_R[w.inst], Pq = P.L.lr_P[w.inst], r0 = P.L.row0[w.inst];
+    const double *__restrict__ part = P.part + P.L.lr_base[w.inst];
+    const int j = w.lb - nch;
+    const int rhi = min((j + 1) * kBlock, Rq);
+    for (int r = j * kBlock + (int)threadIdx.x; r < rhi; r += kBlock) {
+      const DualPre q = pre(r0 + r);
+      double s = 0.0;
+      for (int pn = 0; pn < Pq; ++pn) s += part[(int64_t)pn * Rq + r];
+      epi(r0 + r, s, q);
+    }
+  }
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
     P.p_dual[2 * blockIdx.x] = acc[0];

@@ -36,7 +36,8 @@ class Options(C.Structure):
                 ("pock_chambolle", C.c_int32), ("use_graphs", C.c_int32), ("device_ptrs", C.c_int32),
                 ("tile_nnz", C.c_int32), ("verbose", C.c_int32), ("device_mem_limit", C.c_int64),
                 ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("kernel_timing", C.c_int32),
-                ("work_blocks", C.c_int32), ("single_avg_updates", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("work_blocks", C.c_int32), ("single_avg_updates", C.c_int32), ("panel_rows", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Result(C.Structure):
@@ -222,7 +223,8 @@ def _ptr(a):
 
 def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
             device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
-            warm_fallback=True, kernel_timing=False, work_blocks=0, single_avg_updates=False) -> Options:
+            warm_fallback=True, kernel_timing=False, work_blocks=0, single_avg_updates=False,
+            panel_rows=0) -> Options:
     o = Options()
     load().pdlp_options_default(C.byref(o))
     o.precision = FP64 if str(precision).lower() in ("fp64", "f64", "double", "1") else FP32
@@ -238,6 +240,7 @@ def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True,
     o.kernel_timing = 1 if kernel_timing else 0
     o.work_blocks = work_blocks
     o.single_avg_updates = 1 if single_avg_updates else 0
+    o.panel_rows = panel_rows
     if stream is None:
         try:
             import torch
@@ -334,10 +337,12 @@ class Problem:
         r = pdlp_get(self.h, x, y, rc)
         return Solution(x, y, rc, r.as_dict())
 
-    def spmv(self, x, trans=False) -> np.ndarray:
+    def spmv(self, x, trans=False, iteration=False) -> np.ndarray:
+        """A x (A'x with trans). iteration=True: A x the way the PDHG iteration forms it (long rows
+        by column panels in FP32 handles that use them)."""
         x = _vec(x, self.m if trans else self.n, "x")
         y = np.zeros(self.n if trans else self.m)
-        pdlp_spmv(self.h, 1 if trans else 0, x, y)
+        pdlp_spmv(self.h, 2 if iteration else (1 if trans else 0), x, y)
         return y
 
     def set_snapshots(self, k, rel_tol):
@@ -376,7 +381,7 @@ class Problem:
 
     def kernel_stats(self) -> dict:
         out = {}
-        for k, name in ((0, "dual"), (1, "primal")):
+        for k, name in ((0, "dual"), (1, "primal"), (2, "panel")):
             n, ms = C.c_int64(), C.c_double()
             _check(load().pdlp_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
             out[name] = dict(launches=n.value, total_ms=ms.value,

@@ -368,3 +368,70 @@ def test_batch_matches_single(pdlp):
             say("batch", i, s.info["iterations"], singles[i].info["iterations"])
             assert s.info["iterations"] == singles[i].info["iterations"]
             assert np.array_equal(s.x, singles[i].x) and np.array_equal(s.y, singles[i].y)
+
+
+def test_column_panel_product_parity(pdlp):
+    """FP32 handles sum the long rows of A by column panels of x held in LDS (per-panel FP64 sums
+    added in panel order). The product as the iteration forms it, against the oracle's: several
+    panels with a ragged last one (n = 40,000 = 2 x 16,384 + 7,232), rows from 1 to 5,000 nonzeros
+    (long rows in many row blocks, short ones through the chunks), the single-panel case, and a
+    matrix whose long rows carry too few nonzeros to use panels; every row within one FP32 rounding
+    of its FP64 sum (2e-6 of (|A||x|)_i)."""
+    cases = [g.general_sparse(1, m=20000, n=40000), g.general_sparse(5, m=3000, n=9000, cap=2000),
+             g.set_cover(2, m=800, n=2000)]
+    rng = np.random.default_rng(3)
+    for lp in cases:
+        x = rng.standard_normal(lp.n)
+        ref = oracle.spmv(lp.row_ptr, lp.col, lp.val, x)
+        bound = 2e-6 * _absprod(lp, x) + 1e-30
+        with pdlp.Problem(lp, precision="fp32", kernel_timing=True) as p:
+            it = p.spmv(x, iteration=True)
+            plain = p.spmv(x)
+            p.solve(tol=0.0, iter_limit=64)
+            launches = p.kernel_stats()["panel"]["launches"]
+        with pdlp.Problem(lp, precision="fp32", panel_rows=-1, kernel_timing=True) as p:
+            off = p.spmv(x, iteration=True)
+            p.solve(tol=0.0, iter_limit=64)
+            assert p.kernel_stats()["panel"]["launches"] == 0
+        L = np.diff(lp.row_ptr)
+        long_share = L[L >= 64].sum() / max(lp.nnz, 1)
+        say("panels", lp.name, "long-row share %.2f" % long_share, "panel launches", launches,
+            "max err / bound %.2e" % np.max(np.abs(it - ref) / bound))
+        assert (launches > 0) == (long_share >= 0.5)
+        assert np.all(np.abs(it - ref) <= bound)
+        assert np.all(np.abs(plain - ref) <= bound) and np.all(np.abs(off - ref) <= bound)
+    # a panel-sized x: exactly one panel, every column used
+    m, n = 400, 16384
+    rows, cols, vals = [], [], []
+    for i in range(m):
+        cs = rng.choice(n, size=int(rng.integers(64, 700)), replace=False)
+        rows += [i] * cs.size
+        cols += cs.tolist()
+        vals += rng.standard_normal(cs.size).tolist()
+    rp, ci, v = g._csr_from_triplets(m, n, rows, cols, vals)
+    lp = g.LP(m, n, rp, ci, v, np.zeros(n), np.zeros(m), np.full(m, ord("E"), np.uint8),
+              np.full(n, -np.inf), np.full(n, np.inf))
+    x = rng.standard_normal(n)
+    with pdlp.Problem(lp, precision="fp32") as p:
+        it = p.spmv(x, iteration=True)
+    ref = lp.to_scipy() @ x
+    assert np.all(np.abs(it - ref) <= 2e-6 * _absprod(lp, x) + 1e-30)
+
+
+def test_column_panels_in_a_batch_match_single_solves(pdlp):
+    """Panels are built per instance: members with and without long rows solved in one batch give
+    the bits of their single solves."""
+    lps = [g.general_sparse(21, m=4000, n=20000, cap=3000), g.set_cover(22, m=500, n=1200),
+           g.general_sparse(23, m=2500, n=40000, cap=4000)]
+    singles = []
+    for lp in lps:
+        with pdlp.Problem(lp, precision="fp32", tile_nnz=1024) as p:
+            p.solve(tol=1e-4, iter_limit=50_000)
+            singles.append(p.get())
+    with pdlp.Batch(lps, precision="fp32", tile_nnz=1024) as bt:
+        bt.solve(tol=1e-4, iter_limit=50_000)
+        for i in range(len(lps)):
+            s = bt.get(i)
+            say("panel batch", i, s.info["iterations"], singles[i].info["iterations"])
+            assert s.info["iterations"] == singles[i].info["iterations"]
+            assert np.array_equal(s.x, singles[i].x) and np.array_equal(s.y, singles[i].y)
