@@ -249,18 +249,64 @@ def test_end_to_end_energy(pdlp, prec):
     assert abs(info["primal_obj"] - orc.pobj) <= 1e-4 * max(1.0, abs(orc.pobj))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_end_to_end_general(pdlp, prec):
-    # This family has heavy-tailed attempt counts (seeds 5-10 in FP32: 3e4 to > 4e5, depending on
-    # rounding); seed 7 converges in ~3e4 attempts in both precisions.
+@pytest.fixture(scope="module")
+def general7():
+    """The 3,000 x 6,000 general sparse LP (seed 7), its HiGHS optimum and the oracle at 1e-4."""
     lp = g.general_sparse(7, m=3000, n=6000, cap=1000)
     f, xs, ys = P.highs(lp)
+    return lp, f, xs, ys, oracle.solve(lp, tol=1e-4, iter_limit=400_000)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_end_to_end_general(pdlp, prec, general7):
+    """Relative KKT 1e-4 as the oracle re-evaluates it, and the objective inside the weak-duality
+    interval around HiGHS's optimum. Neither the attempt count nor the objective at 1e-4 is compared
+    with the oracle's: any rounding difference changes a restart decision after a few thousand
+    attempts (the oracle's own summation orders part at attempt 5,696 on this LP and stop at 32,256
+    to 36,352 attempts), and 1e-4 points of this LP differ by ~1e-3 relative in objective
+    (||x*|| ~ 9e5, so small relative infeasibility moves c'x). Both are printed."""
+    lp, f, xs, ys, orc = general7
     with pdlp.Problem(lp, precision=prec) as p:
-        info = p.solve(tol=1e-4, iter_limit=400_000)
+        info = p.solve(tol=1e-4, iter_limit=2_000_000)
         sol = p.get()
-    say("general", prec, info["status_name"], info["iterations"], info["primal_obj"], f)
-    assert info["status"] == pdlp.OPTIMAL
+    say("general", prec, info["status_name"], info["iterations"], info["primal_obj"], "oracle", orc.pobj,
+        orc.iterations, "highs", f, "rel to oracle %.2e" % (abs(info["primal_obj"] - orc.pobj) / abs(orc.pobj)))
+    assert info["status"] == pdlp.OPTIMAL and orc.status == oracle.OPTIMAL
     assert _objective_interval_ok(lp, sol.x, sol.y, f, xs, ys, "general")["rel_kkt"] <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tighter_tolerance_gives_the_objective_within_1e4_of_the_optimum(pdlp, prec, general7):
+    """Objective accuracy is a matter of tolerance: solved to relative KKT 3e-5, the general LP's
+    objective lies within 1e-4 relative of HiGHS's optimum in both precisions (at 1e-4 it is
+    ~1.2e-3 away)."""
+    lp, f, xs, ys, _ = general7
+    with pdlp.Problem(lp, precision=prec) as p:
+        info = p.solve(tol=3e-5, iter_limit=2_000_000)
+        sol = p.get()
+    k = oracle.kkt(lp, sol.x, sol.y)
+    say("general tol 3e-5", prec, info["status_name"], info["iterations"], info["primal_obj"], "highs", f,
+        "rel err %.2e" % (abs(info["primal_obj"] - f) / abs(f)), "oracle rel_kkt %.2e" % k["rel_kkt"])
+    assert info["status"] == pdlp.OPTIMAL and k["rel_kkt"] <= 3e-5
+    assert abs(info["primal_obj"] - f) <= 1e-4 * max(1.0, abs(f))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_reduced_costs_match_the_oracle(pdlp, prec, general7):
+    """pdlp_get's reduced costs are c - A'y of the returned y (FP64 from the FP64 matrix in both
+    precisions): against the oracle's product on the caller's data, every entry within 1e-12 of
+    |c_j| + (|A|'|y|)_j, on LPs with rows of every sense and free, boxed and one-sided columns."""
+    lps = [general7[0], g.set_cover(0), g.energy(4, T=96, N=8, K=6, E=16), g.multi_knapsack(1, m=150, n=400)]
+    for lp in lps:
+        with pdlp.Problem(lp, precision=prec) as p:
+            p.solve(tol=1e-4, iter_limit=1_000_000)
+            sol = p.get()
+        trp, tci, tv = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col, lp.val)
+        rc = lp.c - oracle.spmv(trp, tci, tv, sol.y)
+        scale = np.abs(lp.c) + oracle.spmv(trp, tci, np.abs(tv), np.abs(sol.y))
+        err = np.max(np.abs(sol.rc - rc) / np.maximum(scale, 1e-300))
+        say("reduced costs", prec, lp.name, "max rel err %.2e" % err)
+        assert np.all(np.abs(sol.rc - rc) <= 1e-12 * scale + 1e-300)
 
 
 def test_fp64_matches_oracle_iterations(pdlp):
@@ -435,3 +481,27 @@ def test_column_panels_in_a_batch_match_single_solves(pdlp):
             say("panel batch", i, s.info["iterations"], singles[i].info["iterations"])
             assert s.info["iterations"] == singles[i].info["iterations"]
             assert np.array_equal(s.x, singles[i].x) and np.array_equal(s.y, singles[i].y)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_hard_general_seeds_reach_tolerance(pdlp, prec):
+    """Seeds 8-10 of the 3,000 x 6,000 general family need 1e5 to 5e5 attempts in every
+    implementation of the method: the FP64 oracle itself takes 77,312 / 326,400 / 116,544
+    (tests/golden/general3k_oracle.json). Both precisions must reach 1e-4 as the oracle re-evaluates
+    it within 2M attempts, with the objective in the weak-duality interval around HiGHS's optimum.
+    The count itself is printed, not compared: rounding differences move the attempt at which the
+    relative KKT error, hovering near 1e-4 for 1e4-1e5 attempts, first dips below it."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "general3k_oracle.json")))
+    for seed in (8, 9, 10):
+        lp = g.general_sparse(seed, m=3000, n=6000, cap=1000)
+        ref = gold["seeds"][str(seed)]
+        with pdlp.Problem(lp, precision=prec) as p:
+            info = p.solve(tol=1e-4, iter_limit=2_000_000)
+            sol = p.get()
+        f, xs, ys = P.highs(lp)
+        say("hard seed", seed, prec, info["status_name"], info["iterations"], "oracle", ref["iterations"],
+            "obj rel to oracle %.2e" % (abs(info["primal_obj"] - ref["pobj"]) / abs(ref["pobj"])))
+        assert info["status"] == pdlp.OPTIMAL and ref["status"] == oracle.OPTIMAL
+        assert _objective_interval_ok(lp, sol.x, sol.y, f, xs, ys, f"seed {seed}")["rel_kkt"] <= 1e-4
