@@ -206,7 +206,8 @@ def main():
     dom = kern[dname]
     traffic = MEASURED_TRAFFIC.get((args.workload, dname, kernel_source_sha1()))
     label = {"dual": "k_panel + k_dual (A x' with the dual update and step-size sums)",
-             "primal": "k_primal (A'y' with the primal update and the averages)"}[dname]
+             "primal": ("k_primal_cb (A'y' by column blocks, with the primal update and the averages)"
+                        if ks["col_blocks"]["launches"] else "k_primal (A'y' with the primal update and the averages)")}[dname]
     roofline = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": label, "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_us": round(dom["avg_us"], 2)}

@@ -87,7 +87,12 @@ typedef struct pdlp_options {
                               order) when such rows carry at least half of an instance's nonzeros;
                               0 = 64 (default 0), -1 = never. FP64 handles always use the chunk
                               engine */
-  int32_t reserved[3];
+  int32_t col_blocks;      /* FP32: A'y of an instance by column blocks (a work group owns 4096
+                              columns and reads y in 16384-row panels held in LDS) instead of the
+                              chunk engine; needs every column to have at most 64 nonzeros in each
+                              panel. 0 = when it pays (at least 2^20 nonzeros, at most 64 nonzeros
+                              in the longest column) (default 0), 1 = whenever possible, -1 = never */
+  int32_t reserved[2];
 } pdlp_options;
 
 typedef struct pdlp_result {
@@ -152,8 +157,10 @@ int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_resul
  * y = A x (trans = 0, x [n], y [m]) or y = A' x (trans = 1, x [m], y [n]) with the ORIGINAL
  * (unscaled) matrix, computed by the library's SpMV kernels in the handle's precision on the
  * handle's stream. trans = 2 computes A x the way the PDHG iteration forms it (FP32 handles sum
- * the long rows of A by column panels, see pdlp_options.panel_rows; otherwise the same as 0).
- * x and y are host pointers unless device_ptrs is set.
+ * the long rows of A by column panels, see pdlp_options.panel_rows; otherwise the same as 0), and
+ * trans = 3 computes A'x the way it does (FP32 handles may sum columns by column blocks, see
+ * pdlp_options.col_blocks; otherwise the same as 1). x and y are host pointers unless device_ptrs
+ * is set.
  */
 int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y);
 
@@ -183,6 +190,8 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
  *   kernel 1: A'y' fused with the primal update and the iterate averages
  *   kernel 2: the column-panel sums of the long rows of A x' (launched before kernel 0 when the
  *             handle uses column panels; no launches otherwise)
+ *   kernel 3: the same launches and durations as kernel 1, counted only when kernel 1 includes the
+ *             column-block form of A'y' (see pdlp_options.col_blocks; no launches otherwise)
  * (the step-size decision itself runs in a small per-instance kernel between them and is not timed)
  * *launches receives the number of launches, *total_ms their summed HIP-event durations.
  */

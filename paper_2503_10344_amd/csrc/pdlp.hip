@@ -257,6 +257,85 @@ static bool build_panels(const std::vector<int32_t> &rp, const std::vector<int32
   return true;
 }
 
+// Column-block layout of A' (host side; see ColBlocks in pdlp_internal.h).
+struct ColBlockHost {
+  std::vector<int32_t> wg_inst, wg_blk, wg_g0, gstart, ebase, src;
+  std::vector<uint32_t> desc;
+  std::vector<uint16_t> row;
+};
+constexpr int64_t kCbAutoNnz = int64_t(1) << 20;  // auto mode: instances with at least this many nonzeros
+constexpr int kCbAutoMaxCol = 64;                  // ... and no column longer than this
+
+// Columns [c0, c0 + nq) of instance q (rows [r0, r0 + mq), internal numbering; rp / ci: A in CSR)
+// in work groups of kCbCols columns and row panels of kCbRows rows, as the kernel reads them. src
+// receives the CSR position of every entry (-1: padding). Returns false (H unchanged) when a work
+// group would have more than kCbMaxGroups groups of runs or the slot count leaves the int32 range.
+static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int q, int32_t r0,
+                             int32_t mq, int32_t c0, int32_t nq, ColBlockHost &H) {
+  const int64_t z0 = rp[r0], zq = (int64_t)rp[r0 + mq] - z0;
+  // the instance's transpose: entries of each column in row order
+  std::vector<int32_t> cp((size_t)nq + 1, 0), crow((size_t)zq), csrc((size_t)zq);
+  for (int64_t k = z0; k < z0 + zq; ++k) cp[(size_t)(ci[k] - c0) + 1]++;
+  for (int32_t j = 0; j < nq; ++j) cp[j + 1] += cp[j];
+  {
+    std::vector<int32_t> fill(cp.begin(), cp.end() - 1);
+    for (int32_t i = 0; i < mq; ++i)
+      for (int32_t k = rp[r0 + i]; k < rp[r0 + i + 1]; ++k) {
+        const int32_t j = ci[k] - c0;
+        crow[fill[j]] = i, csrc[fill[j]] = k, ++fill[j];
+      }
+  }
+  const int np = (mq + kCbRows - 1) / kCbRows, nb = (nq + kCbCols - 1) / kCbCols;
+  std::vector<int32_t> cur(cp.begin(), cp.end() - 1);  // next entry of each column
+  ColBlockHost out;
+  int64_t slots = (int64_t)H.row.size() / kWave;  // entry slots (of 64) before this instance
+  const int64_t g_base = (int64_t)H.ebase.size();
+  struct Run {
+    int32_t lc, start, len;
+  };
+  std::vector<Run> runs;
+  for (int b = 0; b < nb; ++b) {
+    out.wg_inst.push_back(q), out.wg_blk.push_back(b);
+    out.wg_g0.push_back((int32_t)(H.gstart.size() + out.gstart.size()));
+    const int64_t wg_first = g_base + (int64_t)out.ebase.size();
+    const int32_t jb = b * kCbCols, jn = std::min(kCbCols, nq - jb);
+    for (int p = 0; p < np; ++p) {
+      out.gstart.push_back((int32_t)(g_base + (int64_t)out.ebase.size()));
+      const int32_t rend = (p + 1) * kCbRows;
+      runs.clear();
+      for (int32_t lc = 0; lc < jn; ++lc) {
+        const int32_t j = jb + lc;
+        int32_t len = 0;
+        while (cur[j] + len < cp[j + 1] && crow[cur[j] + len] < rend) ++len;
+        if (len > 0) runs.push_back({lc, cur[j], len});
+        cur[j] += len;
+      }
+      std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.len > c.len; });
+      for (size_t g0 = 0; g0 < runs.size(); g0 += kWave) {
+        const size_t gn = std::min<size_t>(kWave, runs.size() - g0);
+        const int32_t glen = runs[g0].len;
+        out.ebase.push_back((int32_t)slots);
+        for (size_t l = 0; l < (size_t)kWave; ++l)
+          out.desc.push_back(l < gn ? ((uint32_t)runs[g0 + l].len << 16) | (uint32_t)runs[g0 + l].lc : 0u);
+        for (int32_t t = 0; t < glen; ++t)
+          for (size_t l = 0; l < (size_t)kWave; ++l) {
+            const bool have = l < gn && t < runs[g0 + l].len;
+            out.row.push_back(have ? (uint16_t)(crow[runs[g0 + l].start + t] - p * kCbRows) : (uint16_t)0);
+            out.src.push_back(have ? csrc[runs[g0 + l].start + t] : -1);
+          }
+        slots += glen;
+        if (slots >= INT32_MAX / kWave) return false;
+      }
+    }
+    out.gstart.push_back((int32_t)(g_base + (int64_t)out.ebase.size()));
+    if (g_base + (int64_t)out.ebase.size() - wg_first > kCbMaxGroups) return false;
+  }
+  auto cat = [](auto &a, const auto &bb) { a.insert(a.end(), bb.begin(), bb.end()); };
+  cat(H.wg_inst, out.wg_inst), cat(H.wg_blk, out.wg_blk), cat(H.wg_g0, out.wg_g0), cat(H.gstart, out.gstart);
+  cat(H.ebase, out.ebase), cat(H.desc, out.desc), cat(H.row, out.row), cat(H.src, out.src);
+  return true;
+}
+
 static const int kChunkCandidates[] = {512, 1024, 2048, 4096};
 // Smallest weight (nonzeros + rows) worth a work block of its own. Timed on MI355X: 1024 beats
 // 2048 on small LPs (a 2k x 5k set cover solves in 13.7 instead of 16.2 ms, more blocks in flight)
@@ -325,8 +404,8 @@ struct Solver {
   hipGraphExec_t graph = nullptr;
   // kernel timing (opt.kernel_timing): two pools of start/stop events per attempt and kernel
   std::vector<hipEvent_t> tev[2];
-  int64_t t_launches[3] = {0, 0, 0};
-  double t_ms[3] = {0.0, 0.0, 0.0};
+  int64_t t_launches[4] = {0, 0, 0, 0};
+  double t_ms[4] = {0.0, 0.0, 0.0, 0.0};
   Iter<T> P{};
   std::shared_ptr<void> fix_cache;  // workspace of the LP-based variable strategies, kept between calls
   // column-panel path of the long rows of A (FP32; PQ.nwg == 0: off). h_lr_*: see Layout.
@@ -345,6 +424,14 @@ struct Solver {
   int32_t *d_ia_ab0 = nullptr, *d_ia_ab_inst = nullptr, *d_ia_bchunk = nullptr, *d_ab_nchunk = nullptr;
   std::vector<int32_t> h_ia_ab0;
   int ia_blocks = 1;
+  // column-block path of A'y (FP32; CQ.nwg == 0: off). h_cb_n[q]: work groups of instance q (0: the
+  // chunk engine); h_pb0: ranges of p_primal per instance.
+  ColBlocks<T> CQ{};
+  int32_t *cb_src = nullptr;  // CSR position of each layout entry (set-up only)
+  int64_t cb_entries = 0;
+  std::vector<int32_t> h_cb_n, h_pb0;
+  int32_t *d_cb_n = nullptr, *d_pb0 = nullptr;
+  bool chunk_primal = true;  // some instance runs A'y by the chunk engine (k_primal)
   // reference snapshots (restart points within snap.rel_tol; off while snap.K == 0)
   Snap snap{};
   bool solved = false;
@@ -478,6 +565,28 @@ struct Solver {
       }
     }
 
+    // ---- column-block layout of A' (FP32 iterations only) ----
+    h_cb_n.assign((size_t)K, 0);
+    ColBlockHost CH;
+    if (sizeof(T) == sizeof(float) && o.col_blocks >= 0) {
+      for (int q = 0; q < K; ++q) {
+        const int32_t r0 = h_row0[q], mq = h_row0[q + 1] - r0, c0 = h_col0[q], nq = h_col0[q + 1] - c0;
+        if (mq == 0 || nq == 0 || (mq + kCbRows - 1) / kCbRows > kCbMaxPanels) continue;
+        if (o.col_blocks == 0) {
+          const int64_t zq = (int64_t)h_arp[r0 + mq] - h_arp[r0];
+          int32_t longest = 0;
+          {
+            std::vector<int32_t> cl((size_t)nq, 0);
+            for (int64_t k = h_arp[r0]; k < h_arp[r0 + mq]; ++k) longest = std::max(longest, ++cl[ci[k] - c0]);
+          }
+          if (zq < kCbAutoNnz || longest > kCbAutoMaxCol) continue;
+        }
+        const size_t w_before = CH.wg_inst.size();
+        if (!build_col_blocks(h_arp, ci, q, r0, mq, c0, nq, CH)) continue;  // CH is unchanged then
+        h_cb_n[q] = (int32_t)(CH.wg_inst.size() - w_before);
+      }
+    }
+
     const int64_t mm = std::max(m, 1), nn = std::max(n, 1);
     a_rp = alloc_upload(h_arp);
     a_ci = alloc_upload(ci);
@@ -512,6 +621,19 @@ struct Solver {
       part = mem.alloc<double>(std::max<int64_t>(part_len, 1));
     }
     PH = PanelHost{};
+    d_cb_n = alloc_upload(h_cb_n);
+    chunk_primal = false;
+    for (int q = 0; q < K; ++q) chunk_primal |= h_cb_n[q] == 0;
+    if (!CH.wg_inst.empty()) {
+      for (int l = 0; l < kWave; ++l) CH.row.push_back(0), CH.src.push_back(-1);  // the spare slot
+      CQ.nwg = (int32_t)CH.wg_inst.size();
+      CQ.wg_inst = alloc_upload(CH.wg_inst), CQ.wg_blk = alloc_upload(CH.wg_blk), CQ.wg_g0 = alloc_upload(CH.wg_g0);
+      CQ.gstart = alloc_upload(CH.gstart), CQ.desc = alloc_upload(CH.desc), CQ.ebase = alloc_upload(CH.ebase);
+      CQ.row = alloc_upload(CH.row);
+      cb_src = alloc_upload(CH.src);
+      cb_entries = (int64_t)CH.src.size();
+    }
+    CH = ColBlockHost{};
 
     // ---- transpose (counting sort; the per-column sort of source positions makes it deterministic)
     int32_t *row_of = mem.alloc<int32_t>(nnz);
@@ -619,6 +741,16 @@ struct Solver {
       mem.release(pan_src);
       pan_src = nullptr;
     }
+    if (CQ.nwg > 0) {  // values of the column-block layout (0 for padding entries)
+      T *cv = mem.alloc<T>(std::max<int64_t>(cb_entries, 1));
+      hipLaunchKernelGGL(k_gather_or_zero<T>, dim3(grid_for(cb_entries)), dim3(kBlock), 0, stream, cb_entries,
+                         (const int32_t *)cb_src, (const T *)a_v, cv);
+      HIPCHK(hipGetLastError());
+      CQ.val = cv;
+      sync();
+      mem.release(cb_src);
+      cb_src = nullptr;
+    }
 
     // iterates and staging
     for (int q = 0; q < 2; ++q) xs[q] = mem.alloc<T>(nn), ys[q] = mem.alloc<T>(mm), axs[q] = mem.alloc<T>(mm);
@@ -654,7 +786,10 @@ struct Solver {
     d_ev_inst = alloc_upload(ev_inst);
     d_ev0 = alloc_upload(h_ev0);
     p_dual = mem.alloc<double>((int64_t)ia_blocks * 2);
-    p_primal = mem.alloc<double>(tb_blocks);
+    h_pb0.assign(1, 0);
+    for (int q = 0; q < K; ++q) h_pb0.push_back(h_pb0.back() + (h_cb_n[q] > 0 ? h_cb_n[q] : h_tb0[q + 1] - h_tb0[q]));
+    d_pb0 = alloc_upload(h_pb0);
+    p_primal = mem.alloc<double>(std::max(h_pb0.back(), 1));
     p_restart = mem.alloc<double>(ev_blocks);
     p_eval = mem.alloc<double>((int64_t)ev_blocks * kEvalNV);
     p_final = mem.alloc<double>((int64_t)ev_blocks * 5);
@@ -669,6 +804,7 @@ struct Solver {
     L.ab0 = d_ia_ab0, L.ab_inst = d_ia_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
     L.a_bchunk = d_ia_bchunk, L.t_bchunk = d_t_bchunk;
     L.ab_nchunk = d_ab_nchunk, L.lr_R = d_lr_R, L.lr_P = d_lr_P, L.lr_base = d_lr_base;
+    L.pb0 = d_pb0, L.cb_n = d_cb_n;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
     L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ia_blocks, L.tb_blocks = tb_blocks;
     L.ev_blocks = ev_blocks;
@@ -874,11 +1010,17 @@ struct Solver {
   void launch_panels() {
     if (PQ.nwg > 0) hipLaunchKernelGGL(k_panel<T>, dim3(PQ.nwg), dim3(kPanelBlock), 0, stream, P, PQ);
   }
+  void launch_primal() {
+    if (chunk_primal) hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (CQ.nwg > 0) hipLaunchKernelGGL(k_primal_cb<T>, dim3(CQ.nwg), dim3(kCbBlock), 0, stream, P, CQ);
+    }
+  }
   void launch_attempt() {
     launch_panels();
     hipLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P);
     launch_step();
-    hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
+    launch_primal();
   }
   void launch_step() {
     hipLaunchKernelGGL(k_step, dim3(K), dim3(kStepBlock), 0, stream, P.L, (const double *)p_dual,
@@ -932,7 +1074,7 @@ struct Solver {
       HIPCHK(hipEventRecord(e[2], stream));
       launch_step();
       HIPCHK(hipEventRecord(e[3], stream));
-      hipLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, P);
+      launch_primal();
       HIPCHK(hipEventRecord(e[4], stream));
     }
     refresh_averages();
@@ -940,13 +1082,15 @@ struct Solver {
     HIPCHK(hipGetLastError());
   }
   // Add the durations recorded in pool `slot` (its chunk has completed): kernel 0 = k_dual,
-  // 1 = k_primal, 2 = k_panel (counted only when the handle uses column panels).
+  // 1 = the primal kernels (k_primal and / or k_primal_cb), 2 = k_panel (counted only when the
+  // handle uses column panels), 3 = the primal bracket again when it holds k_primal_cb (counted
+  // only when the handle uses column blocks).
   void collect_times(int slot) {
     auto &pool = tev[slot];
-    static const int kFrom[3] = {1, 3, 0}, kTo[3] = {2, 4, 1};
+    static const int kFrom[4] = {1, 3, 0, 3}, kTo[4] = {2, 4, 1, 4};
     for (int r = 0; r < opt.eval_every && !pool.empty(); ++r)
-      for (int k = 0; k < 3; ++k) {
-        if (k == 2 && PQ.nwg == 0) continue;
+      for (int k = 0; k < 4; ++k) {
+        if ((k == 2 && PQ.nwg == 0) || (k == 3 && CQ.nwg == 0)) continue;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 5 + kFrom[k]], pool[(size_t)r * 5 + kTo[k]]));
         t_ms[k] += ms;
@@ -1047,8 +1191,7 @@ struct Solver {
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));
     if (snap.K > 0) HIPCHK(hipMemsetAsync(snap.taken, 0, sizeof(int32_t) * (size_t)K, stream));
-    t_launches[0] = t_launches[1] = t_launches[2] = 0;
-    t_ms[0] = t_ms[1] = t_ms[2] = 0.0;
+    for (int k = 0; k < 4; ++k) t_launches[k] = 0, t_ms[k] = 0.0;
     const bool warm = stage_start(x0s, y0s);
     std::vector<int> fallback((size_t)K, 0), warm_q((size_t)K, 0);
     for (int q = 0; q < K; ++q) warm_q[q] = (x0s && x0s[q]) || (y0s && y0s[q]);
@@ -1171,11 +1314,11 @@ struct Solver {
       if (ch >= 1) {
         HIPCHK(hipEventSynchronize(ev[(ch - 1) & 1]));
         if (opt.kernel_timing) collect_times((int)((ch - 1) & 1));
-        if (h_flags[(ch - 1) & 1] >= K) break;
+        if (h_flags[(ch - 1) & 1] >= K) break;  // chunk ch found every instance done: not timed
       }
     }
     sync();
-    if (opt.kernel_timing) collect_times((int)((ch < max_chunks ? ch : ch - 1) & 1));
+    if (opt.kernel_timing && ch == max_chunks) collect_times((int)((ch - 1) & 1));
   }
 
   void finalize() {
@@ -1279,8 +1422,17 @@ struct Solver {
                        (const int32_t *)d_ia_ab0, (const int32_t *)d_ia_ab_inst, (const int32_t *)d_ia_bchunk, x, y);
   }
 
+  // A'y as the iteration forms it: the column-block instances by k_cb_x over the chunk engine's
+  // result for all instances.
+  void spmv_iter_t(const T *yv, T *out) {
+    spmv_T(1, yv, out);
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (CQ.nwg > 0) hipLaunchKernelGGL(k_cb_x<T>, dim3(CQ.nwg), dim3(kCbBlock), 0, stream, P.L, CQ, yv, out);
+    }
+  }
+
   void spmv(int trans_mode, const double *x, double *y) {
-    const int trans = trans_mode == 1;
+    const int trans = trans_mode == 1 || trans_mode == 3;
     const int in = trans ? m : n, out = trans ? n : m;
     double *sin = trans ? stage_m : stage_n;
     double *xin = trans ? yd : xd;
@@ -1295,6 +1447,7 @@ struct Solver {
     hipLaunchKernelGGL(k_div_to<T>, dim3(grid_for(in)), dim3(kBlock), 0, stream, in, (const double *)xin,
                        (const double *)(trans ? Dr : Dc), tin);
     if (trans_mode == 2) spmv_iter(tin, tout);
+    else if (trans_mode == 3) spmv_iter_t(tin, tout);
     else spmv_T(trans, tin, tout);
     hipLaunchKernelGGL(k_div_from<T>, dim3(grid_for(out)), dim3(kBlock), 0, stream, out, (const T *)tout,
                        (const double *)(trans ? Dc : Dr), yint);
@@ -1537,7 +1690,7 @@ int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_resul
 }
 
 int pdlp_spmv(pdlp_problem *p, int32_t trans, const double *x, double *y) {
-  if (!p || !x || !y || trans < 0 || trans > 2) {
+  if (!p || !x || !y || trans < 0 || trans > 3) {
     pdlp::g_last_error = "bad argument to pdlp_spmv";
     return PDLP_ERR_ARG;
   }
@@ -1578,7 +1731,7 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
 }
 
 int pdlp_kernel_stats(pdlp_problem *p, int32_t kernel, int64_t *launches, double *total_ms) {
-  if (!p || kernel < 0 || kernel > 2) {
+  if (!p || kernel < 0 || kernel > 3) {
     pdlp::g_last_error = "bad argument to pdlp_kernel_stats";
     return PDLP_ERR_ARG;
   }

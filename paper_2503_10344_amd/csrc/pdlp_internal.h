@@ -24,6 +24,13 @@ constexpr int kEvalSpan = 2048;    // elements per evaluation block (target)
 // row (FP64) are added up in panel order by the kernel that runs the row's epilogue.
 constexpr int kPanelW = 16384;     // x entries per panel (64 KB of FP32 in LDS)
 constexpr int kPanelBlock = 1024;  // threads per panel work group
+// Column-block path of A'y (FP32): a work group owns kCbCols consecutive columns and reads y in row
+// panels of kCbRows entries held in LDS; see ColBlocks.
+constexpr int kCbCols = 4096;      // columns per work group
+constexpr int kCbRows = 16384;     // y entries per panel (64 KB of FP32)
+constexpr int kCbBlock = 1024;     // threads per work group
+constexpr int kCbMaxPanels = 512;  // instances with more y panels keep the chunk engine
+constexpr int kCbMaxGroups = 4096; // work groups with more run groups than this keep the chunk engine
 
 enum RestartMode : int32_t { kNoRestart = 0, kToCurrent = 1, kToAverage = 2 };
 enum EvalMode : int32_t { kEvalInit = 0, kEvalChunk = 1, kEvalPoint = 2 };
@@ -83,6 +90,9 @@ struct Layout {
   // ab_nchunk[q] run chunks, the others finish kBlock long rows each. All zero without the path.
   const int32_t *ab_nchunk, *lr_R, *lr_P;
   const int64_t *lr_base;
+  // A' side: instance q's |dx|^2 partials are p_primal[pb0[q] .. pb0[q+1]); cb_n[q] > 0 when its A'y
+  // runs by column blocks (that many work groups of k_primal_cb; k_primal skips the instance).
+  const int32_t *pb0, *cb_n;
 };
 
 // Column-panel work groups: (row block, panel) pairs. A row block is a run of consecutive long rows
@@ -98,6 +108,26 @@ struct Panels {
   const int32_t *rb_inst, *rb_lrow0, *rb_R, *rb_G;  // row block: instance, first long row (index
                                     // within the instance), rows, lanes per row
   const uint16_t *off, *col;
+  const T *val;
+};
+
+// Column blocks of A' (rows of A' = columns of A). Work group w owns the columns
+// [col0[q] + kCbCols * wg_blk[w], ...) of instance q = wg_inst[w] and reads y in row panels of
+// kCbRows rows. In panel p a column's entries form a run (in row order); the work group's runs in
+// panel p are sorted by length (longest first) and dealt to groups of 64 lanes, the groups
+// [gstart[wg_g0[w] + p], gstart[wg_g0[w] + p + 1]). Group g: desc[64 g + l] = (length << 16) |
+// (column within the block) of lane l's run, 0 for a lane without one; entry t of lane l's run is
+// at index 64 (ebase[g] + t) + l of row (row within the panel) and val, for t below the group's
+// longest run (lane 0's). Slots past a run's end hold row 0 and value 0, and the entry arrays end
+// with one spare slot of 64 entries, so a group's second slot can always be read.
+template <typename T>
+struct ColBlocks {
+  int32_t nwg;
+  const int32_t *wg_inst, *wg_blk, *wg_g0;
+  const int32_t *gstart;
+  const uint32_t *desc;
+  const int32_t *ebase;
+  const uint16_t *row;
   const T *val;
 };
 

@@ -600,8 +600,8 @@ __global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__r
   }
   const bool rs = st->restart_mode != kNoRestart;
   double dy2 = 0.0, inter = 0.0, dx2 = 0.0;
-  step_sums(p_dual, L.ab0[inst], L.ab0[inst + 1], rs ? p_restart : p_primal, rs ? L.ev_blk0[inst] : L.tb0[inst],
-            rs ? L.ev_blk0[inst + 1] : L.tb0[inst + 1], dy2, inter, dx2);
+  step_sums(p_dual, L.ab0[inst], L.ab0[inst + 1], rs ? p_restart : p_primal, rs ? L.ev_blk0[inst] : L.pb0[inst],
+            rs ? L.ev_blk0[inst + 1] : L.pb0[inst + 1], dy2, inter, dx2);
   if (threadIdx.x == 0) {
     st->restart_mode = kNoRestart;
     step_size_rule(st, ndone, dx2, dy2, inter);
@@ -619,38 +619,40 @@ __global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__r
 // candidate of the next attempt overwrites that buffer.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
-  const WBlock w = work_block(P.L.tb0, P.L.tb_inst);
-  const State *st = P.st + w.inst;
-  if (st->done) return;
-  const int cur = st->cur, commit = st->commit, stop = st->stop;
-  const double tau = st->eta / st->omega;
-  const T wa = T(st->avg_w);
-  const double wad = st->avg_w, wd1 = st->avg_w1;
-  const int amode = st->avg_mode;
-  const bool avg_now = commit && amode != kAvgDefer;  // x_bar / y_bar change in this launch
-  const T *__restrict__ xc = P.x[cur];
-  T *__restrict__ xnx = P.x[cur ^ 1];
-  const T *__restrict__ yc = P.y[cur];
-  const T *__restrict__ c = P.c;
-  const T *__restrict__ lo = P.l;
-  const T *__restrict__ hi = P.u;
-  T *__restrict__ aty = P.aty;
-  double *__restrict__ xbar = P.xbar;
-  T *__restrict__ atybar = P.atybar;
-  double acc[1] = {0.0};
-  struct PrimalPre {
+struct PrimalSide {
+  struct Pre {
     T x, c, l, u;
     double xbar;
     T atybar;
   };
   // FP64 keeps A'y-bar and A x-bar current with the averages' weighted updates; FP32 recomputes
   // both before each evaluation (the only readers), so it skips them here.
-  constexpr bool kTrack = sizeof(T) == sizeof(double);
-  auto fetch = [&](int j) {
-    return PrimalPre{xc[j], c[j], lo[j], hi[j], avg_now ? xbar[j] : 0.0, kTrack ? atybar[j] : T(0)};
-  };
-  auto primal = [&](int j, T atyj, const PrimalPre &q) {
+  static constexpr bool kTrack = sizeof(T) == sizeof(double);
+  int cur, commit, stop, amode;
+  bool avg_now;  // x_bar / y_bar change in this launch
+  double tau, wad, wd1;
+  T wa;
+  const T *__restrict__ xc;
+  T *__restrict__ xnx;
+  const T *__restrict__ c;
+  const T *__restrict__ lo;
+  const T *__restrict__ hi;
+  double *__restrict__ xbar;
+  T *__restrict__ atybar;
+
+  __device__ __forceinline__ PrimalSide(const Iter<T> &P, const State *st) {
+    cur = st->cur, commit = st->commit, stop = st->stop, amode = st->avg_mode;
+    avg_now = commit && amode != kAvgDefer;
+    tau = st->eta / st->omega;
+    wa = T(st->avg_w);
+    wad = st->avg_w, wd1 = st->avg_w1;
+    xc = P.x[cur], xnx = P.x[cur ^ 1], c = P.c, lo = P.l, hi = P.u, xbar = P.xbar, atybar = P.atybar;
+  }
+  __device__ __forceinline__ Pre fetch(int j) const {
+    return Pre{xc[j], c[j], lo[j], hi[j], avg_now ? xbar[j] : 0.0, kTrack ? atybar[j] : T(0)};
+  }
+  // column j's share of the launch: averages (committed attempts) and the next primal candidate
+  __device__ __forceinline__ void column(int j, T atyj, const Pre &q, double &dx2) const {
     if (commit) {
       if (amode == kAvgOne) {
         xbar[j] = q.xbar + wad * (double(q.x) - q.xbar);
@@ -664,41 +666,224 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
       const T xnew = T(clipv(double(q.x) - tau * (double(q.c) - double(atyj)), double(q.l), double(q.u)));
       xnx[j] = xnew;
       const double d = double(xnew) - double(q.x);
-      acc[0] += d * d;
+      dx2 += d * d;
     }
-  };
-  int cb, ce;
-  cb = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb], ce = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb + 1];
-  if (commit) {
-    block_chunks<T, T, double>(P.t_rp, P.t_ci, P.t_val, yc, P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
-                               [&](int j, double s, const PrimalPre &q) {
-                                 const T atyj = T(s);
-                                 aty[j] = atyj;
-                                 primal(j, atyj, q);
-                               });
+  }
+  // the dual averages of a committed attempt over rows [rb, re), thread t taking rb + t, + stride ...
+  __device__ __forceinline__ void rows(const Iter<T> &P, int rb, int re, int t, int stride) const {
+    if (!(avg_now || kTrack)) return;
+    const T *__restrict__ yc = P.y[cur];
     const T *__restrict__ axc = P.ax[cur];
     const T *__restrict__ yprev = P.y[cur ^ 1];  // the older accepted y of a paired update
     double *__restrict__ ybar = P.ybar;
     T *__restrict__ axbar = P.axbar;
+    for (int i = rb + t; i < re; i += stride) {
+      if (amode == kAvgOne) {
+        ybar[i] += wad * (double(yc[i]) - ybar[i]);
+      } else if (amode == kAvgPair) {
+        const double u = ybar[i] + wd1 * (double(yprev[i]) - ybar[i]);
+        ybar[i] = u + wad * (double(yc[i]) - u);
+      }
+      if (kTrack) axbar[i] += wa * (axc[i] - axbar[i]);
+    }
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
+  const WBlock w = work_block(P.L.tb0, P.L.tb_inst);
+  const State *st = P.st + w.inst;
+  if (st->done || P.L.cb_n[w.inst] > 0) return;
+  const PrimalSide<T> S(P, st);
+  T *__restrict__ aty = P.aty;
+  double acc[1] = {0.0};
+  auto fetch = [&](int j) { return S.fetch(j); };
+  int cb, ce;
+  cb = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb], ce = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb + 1];
+  if (S.commit) {
+    block_chunks<T, T, double>(P.t_rp, P.t_ci, P.t_val, P.y[S.cur], P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
+                               [&](int j, double s, const typename PrimalSide<T>::Pre &q) {
+                                 const T atyj = T(s);
+                                 aty[j] = atyj;
+                                 S.column(j, atyj, q, acc[0]);
+                               });
     int rb, re;
     share(P.L.row0[w.inst], P.L.row0[w.inst + 1] - P.L.row0[w.inst], w.lb, w.nb, &rb, &re);
-    if (avg_now || kTrack) {
-      for (int i = rb + (int)threadIdx.x; i < re; i += kBlock) {
-        if (amode == kAvgOne) {
-          ybar[i] += wad * (double(yc[i]) - ybar[i]);
-        } else if (amode == kAvgPair) {
-          const double t = ybar[i] + wd1 * (double(yprev[i]) - ybar[i]);
-          ybar[i] = t + wad * (double(yc[i]) - t);
-        }
-        if (kTrack) axbar[i] += wa * (axc[i] - axbar[i]);
-      }
-    }
-  } else if (!stop && ce > cb) {
+    S.rows(P, rb, re, (int)threadIdx.x, kBlock);
+  } else if (!S.stop && ce > cb) {
     const int j0 = P.t_chunk_row[cb], j1 = P.t_chunk_row[ce];
-    for (int j = j0 + (int)threadIdx.x; j < j1; j += kBlock) primal(j, aty[j], fetch(j));
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += kBlock) S.column(j, aty[j], S.fetch(j), acc[0]);
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) P.p_primal[blockIdx.x] = acc[0];
+  if (threadIdx.x == 0) P.p_primal[P.L.pb0[w.inst] + ((int)blockIdx.x - P.L.tb0[w.inst])] = acc[0];
+}
+
+// ----------------------------------------------------------------------------------------------
+// Column-block path of A'y (FP32 instances whose columns are short and spread over all rows, so
+// that every entry gathers y from a random row). Served from L2 such gathers are bound by the
+// requests a compute unit can keep in flight, not by bytes. Here a work group owns kCbCols
+// consecutive columns and walks y in row panels of kCbRows entries held in LDS. Its waves take the
+// 64-lane groups of runs of the current panel (layout in ColBlocks): a lane sums its run in row
+// order in FP64 (the product of two FP32 values is exact in FP64, so each step rounds once) and
+// adds the run's sum to the column's FP64 accumulator in LDS. A column has one run per panel and
+// panels are separated by barriers, so each column receives its panel sums in panel order and the
+// result depends on the layout alone. While a panel is summed, the next panel's y values and the
+// wave's first groups of it are loaded into registers. The layout is streamed with non-temporal
+// loads, like the chunk engine's, so that it does not evict the A-side panel data from the
+// last-level cache between attempts.
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, int wg, const T *__restrict__ y,
+                                        float *ys, double *acc, int32_t *gsl, int32_t *ebl) {
+  static_assert(sizeof(T) == sizeof(float), "the column-block path holds FP32 y panels in LDS");
+  constexpr int kW = kCbBlock / kWave;     // waves per work group
+  constexpr int kYr = kCbRows / kCbBlock;  // y values per thread and panel
+  constexpr int kGb = 4;                   // groups per wave and panel held in registers
+  // a panel has at most kCbCols runs, so kGb groups per wave cover all of them
+  static_assert(kGb * kW * kWave >= kCbCols, "every group of a panel must have a register slot");
+  const int q = Q.wg_inst[wg];
+  const int r0 = L.row0[q], mq = L.row0[q + 1] - r0;
+  const int np = (mq + kCbRows - 1) / kCbRows;
+  const uint32_t *__restrict__ desc = Q.desc;
+  const uint16_t *__restrict__ rows = Q.row;
+  const T *__restrict__ val = Q.val;
+  const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  for (int i = tid; i < kCbCols; i += kCbBlock) acc[i] = 0.0;
+  // the work group's group ranges and entry bases, in LDS
+  {
+    const int32_t *__restrict__ g = Q.gstart + Q.wg_g0[wg];
+    for (int i = tid; i <= np; i += kCbBlock) gsl[i] = g[i];
+    __syncthreads();
+    const int gf = gsl[0], gn = gsl[np] - gf;
+    for (int i = tid; i < gn; i += kCbBlock) ebl[i] = Q.ebase[gf + i];
+    __syncthreads();
+  }
+  const int gfirst = gsl[0];
+  // registers of the next panel: y values, and descriptors and first two slots of the wave's
+  // groups
+  float yr[kYr];
+  uint32_t dr[kGb], rr0[kGb], rr1[kGb];
+  float vr0[kGb], vr1[kGb];
+  auto load = [&](int p) {
+    const int rp0 = r0 + p * kCbRows, rn = min(kCbRows, mq - p * kCbRows);
+#pragma unroll
+    for (int u = 0; u < kYr; ++u) {
+      const int i = tid + u * kCbBlock;
+      yr[u] = i < rn ? float(y[rp0 + i]) : 0.0f;
+    }
+    const int g0 = gsl[p] + wave, g1 = gsl[p + 1];
+#pragma unroll
+    for (int u = 0; u < kGb; ++u) {
+      const int g = g0 + u * kW;
+      if (g < g1) {
+        const int64_t e = (int64_t)ebl[g - gfirst] * kWave + lane;
+        dr[u] = __builtin_nontemporal_load(desc + (int64_t)g * kWave + lane);
+        rr0[u] = __builtin_nontemporal_load(rows + e), vr0[u] = float(__builtin_nontemporal_load(val + e));
+        rr1[u] = __builtin_nontemporal_load(rows + e + kWave);
+        vr1[u] = float(__builtin_nontemporal_load(val + e + kWave));
+      }
+    }
+  };
+  // one group: lane l sums its run (first two slots given) and adds the sum to its column
+  auto run = [&](int g, uint32_t d, uint32_t ra, float va, uint32_t rb, float vb) {
+    const int len = (int)(d >> 16), lc = (int)(d & 0xFFFFu);
+    const int glen = __builtin_amdgcn_readfirstlane(len);  // the group's first run is its longest
+    double s = 0.0;
+    if (len > 0) s = fma(double(va), double(ys[ra]), s);
+    if (len > 1) s = fma(double(vb), double(ys[rb]), s);
+    if (glen > 2) {
+      const int64_t e = (int64_t)ebl[g - gfirst] * kWave + lane;
+      for (int t = 2; t < glen; ++t) {
+        const uint32_t r = __builtin_nontemporal_load(rows + e + (int64_t)t * kWave);
+        const float v = float(__builtin_nontemporal_load(val + e + (int64_t)t * kWave));
+        if (t < len) s = fma(double(v), double(ys[r]), s);
+      }
+    }
+    if (len > 0) acc[lc] += s;
+  };
+  if (np > 0) load(0);
+  for (int p = 0; p < np; ++p) {
+    const int rn = min(kCbRows, mq - p * kCbRows);
+    const int g0 = gsl[p] + wave, g1 = gsl[p + 1];
+    __syncthreads();  // the previous panel has been summed (and the accumulators cleared)
+#pragma unroll
+    for (int u = 0; u < kYr; ++u) {
+      const int i = tid + u * kCbBlock;
+      if (i < rn) ys[i] = yr[u];
+    }
+    uint32_t dc[kGb], rc0[kGb], rc1[kGb];
+    float vc0[kGb], vc1[kGb];
+#pragma unroll
+    for (int u = 0; u < kGb; ++u) dc[u] = dr[u], rc0[u] = rr0[u], vc0[u] = vr0[u], rc1[u] = rr1[u], vc1[u] = vr1[u];
+    __syncthreads();
+    if (p + 1 < np) load(p + 1);
+#pragma unroll
+    for (int u = 0; u < kGb; ++u)
+      if (g0 + u * kW < g1) run(g0 + u * kW, dc[u], rc0[u], vc0[u], rc1[u], vc1[u]);
+  }
+  __syncthreads();
+}
+
+// Sum over the block (kCbBlock threads) in a fixed order; valid in thread 0.
+__device__ __forceinline__ double cb_block_sum(double v, double *red) {
+  constexpr int kW = kCbBlock / kWave;
+  v = wave_sum(v);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < kW; ++w) t += red[w];
+    v = t;
+  }
+  return v;
+}
+
+// k_primal for the instances on the column-block path (grid: their work groups).
+template <typename T>
+__global__ __launch_bounds__(kCbBlock) void k_primal_cb(Iter<T> P, ColBlocks<T> Q) {
+  __shared__ float ys[kCbRows];
+  __shared__ double acc[kCbCols];
+  __shared__ int32_t gsl[kCbMaxPanels + 1];
+  __shared__ int32_t ebl[kCbMaxGroups];
+  __shared__ double red[kCbBlock / kWave];
+  const int wg = blockIdx.x, q = Q.wg_inst[wg], blk = Q.wg_blk[wg];
+  const State *st = P.st + q;
+  if (st->done) return;
+  const PrimalSide<T> S(P, st);
+  const int c0 = P.L.col0[q] + blk * kCbCols, cn = min(kCbCols, P.L.col0[q + 1] - c0);
+  const int tid = (int)threadIdx.x;
+  double dx2 = 0.0;
+  if (S.commit) {
+    cb_sums<T>(P.L, Q, wg, P.y[S.cur], ys, acc, gsl, ebl);
+    for (int i = tid; i < cn; i += kCbBlock) {
+      const int j = c0 + i;
+      const typename PrimalSide<T>::Pre pre = S.fetch(j);
+      const T atyj = T(acc[i]);
+      P.aty[j] = atyj;
+      S.column(j, atyj, pre, dx2);
+    }
+    int rb, re;
+    share(P.L.row0[q], P.L.row0[q + 1] - P.L.row0[q], blk, P.L.cb_n[q], &rb, &re);
+    S.rows(P, rb, re, tid, kCbBlock);
+  } else if (!S.stop) {
+    for (int i = tid; i < cn; i += kCbBlock) S.column(c0 + i, P.aty[c0 + i], S.fetch(c0 + i), dx2);
+  }
+  dx2 = cb_block_sum(dx2, red);
+  if (tid == 0) P.p_primal[P.L.pb0[q] + blk] = dx2;
+}
+
+// A'y for a given y over the column-block instances (plain store; products outside the iteration).
+template <typename T>
+__global__ __launch_bounds__(kCbBlock) void k_cb_x(Layout L, ColBlocks<T> Q, const T *__restrict__ y,
+                                                   T *__restrict__ out) {
+  __shared__ float ys[kCbRows];
+  __shared__ double acc[kCbCols];
+  __shared__ int32_t gsl[kCbMaxPanels + 1];
+  __shared__ int32_t ebl[kCbMaxGroups];
+  const int wg = blockIdx.x, q = Q.wg_inst[wg], blk = Q.wg_blk[wg];
+  const int c0 = L.col0[q] + blk * kCbCols, cn = min(kCbCols, L.col0[q + 1] - c0);
+  cb_sums<T>(L, Q, wg, y, ys, acc, gsl, ebl);
+  for (int i = (int)threadIdx.x; i < cn; i += kCbBlock) out[c0 + i] = T(acc[i]);
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -1217,6 +1402,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_t(int nnz, const int32_t *__r
     const int e = perm[p];
     if (t_ci) t_ci[p] = row_of[e];
     t_val[p] = val[e];
+  }
+}
+
+// out[p] = val[src[p]], or 0 where src[p] < 0
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_gather_or_zero(int64_t count, const int32_t *__restrict__ src,
+                                                           const V *__restrict__ val, V *__restrict__ out) {
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < count; p += (int64_t)gridDim.x * kBlock) {
+    const int32_t e = src[p];
+    out[p] = e >= 0 ? val[e] : V(0);
   }
 }
 

@@ -37,7 +37,7 @@ class Options(C.Structure):
                 ("tile_nnz", C.c_int32), ("verbose", C.c_int32), ("device_mem_limit", C.c_int64),
                 ("stream", C.c_void_p), ("warm_fallback", C.c_int32), ("kernel_timing", C.c_int32),
                 ("work_blocks", C.c_int32), ("single_avg_updates", C.c_int32), ("panel_rows", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("col_blocks", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Result(C.Structure):
@@ -224,7 +224,7 @@ def _ptr(a):
 def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
             device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
             warm_fallback=True, kernel_timing=False, work_blocks=0, single_avg_updates=False,
-            panel_rows=0) -> Options:
+            panel_rows=0, col_blocks=0) -> Options:
     o = Options()
     load().pdlp_options_default(C.byref(o))
     o.precision = FP64 if str(precision).lower() in ("fp64", "f64", "double", "1") else FP32
@@ -241,6 +241,7 @@ def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True,
     o.work_blocks = work_blocks
     o.single_avg_updates = 1 if single_avg_updates else 0
     o.panel_rows = panel_rows
+    o.col_blocks = col_blocks
     if stream is None:
         try:
             import torch
@@ -338,11 +339,11 @@ class Problem:
         return Solution(x, y, rc, r.as_dict())
 
     def spmv(self, x, trans=False, iteration=False) -> np.ndarray:
-        """A x (A'x with trans). iteration=True: A x the way the PDHG iteration forms it (long rows
-        by column panels in FP32 handles that use them)."""
+        """A x (A'x with trans). iteration=True: the product the way the PDHG iteration forms it (in
+        FP32 handles that use them: long rows of A by column panels, A'x by column blocks)."""
         x = _vec(x, self.m if trans else self.n, "x")
         y = np.zeros(self.n if trans else self.m)
-        pdlp_spmv(self.h, 2 if iteration else (1 if trans else 0), x, y)
+        pdlp_spmv(self.h, (3 if trans else 2) if iteration else (1 if trans else 0), x, y)
         return y
 
     def set_snapshots(self, k, rel_tol):
@@ -381,7 +382,7 @@ class Problem:
 
     def kernel_stats(self) -> dict:
         out = {}
-        for k, name in ((0, "dual"), (1, "primal"), (2, "panel")):
+        for k, name in ((0, "dual"), (1, "primal"), (2, "panel"), (3, "col_blocks")):
             n, ms = C.c_int64(), C.c_double()
             _check(load().pdlp_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
             out[name] = dict(launches=n.value, total_ms=ms.value,

@@ -1,7 +1,7 @@
-"""Writes the FP64 oracle's solves of the 500,000 x 1,000,000 general sparse LP (generator seed 0) to
-relative KKT 1e-4 and 3e-5: objective, attempts and relative errors, one entry per tolerance in
-tests/golden/zipf500k_seed0_oracle.json. Entries already in the file are kept (each solve takes
-20 minutes to hours of CPU time).
+"""Writes the FP64 oracle's solve of the 500,000 x 1,000,000 general sparse LP (generator seed 0) to
+relative KKT 1e-4: objective, attempts and relative errors, one entry per tolerance in TOLS, in
+tests/golden/zipf500k_seed0_oracle.json. Entries already in the file are kept (a solve takes about
+20 minutes on 6 cores at 1e-4; tighter tolerances take hours).
 
 Calls only oracle/ and the seeded generator. Run from the repository root:
     OMP_NUM_THREADS=<threads> python tests/golden/make_zipf500k_oracle.py
@@ -18,7 +18,7 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from paper_2503_10344_amd import generators as g  # noqa: E402
 
-TOLS = (1e-4, 3e-5)
+TOLS = (1e-4,)
 LIMIT = 1_000_000
 PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "zipf500k_seed0_oracle.json")
 

@@ -74,13 +74,19 @@ def _sample(lengths, rng, k=4096):
 
 
 def _sampled_products(p, lp, At, prec, rng):
+    """Sampled entries of A x and A'y, plain and as the iteration forms them (FP32 handles may
+    sum long rows of A by column panels and A'y by column blocks), against the oracle."""
     tol = FP32_PRODUCT if prec == "fp32" else FP64_PRODUCT
     x = rng.standard_normal(lp.n)
     y = rng.standard_normal(lp.m)
     ax = p.spmv(x)
     aty = p.spmv(y, trans=True)
+    ax_it = p.spmv(x, iteration=True)
+    aty_it = p.spmv(y, trans=True, iteration=True)
     for name, (rp, ci, v), vec, out in (("A x", (lp.row_ptr, lp.col, lp.val), x, ax),
-                                        ("A'y", At, y, aty)):
+                                        ("A'y", At, y, aty),
+                                        ("A x (iteration)", (lp.row_ptr, lp.col, lp.val), x, ax_it),
+                                        ("A'y (iteration)", At, y, aty_it)):
         rows = _sample(np.diff(rp), rng)
         srp, sci, sv = _sub_csr(rp, ci, v, rows)
         ref = oracle.spmv(srp, sci, sv, vec)

@@ -505,3 +505,65 @@ def test_hard_general_seeds_reach_tolerance(pdlp, prec):
             "obj rel to oracle %.2e" % (abs(info["primal_obj"] - ref["pobj"]) / abs(ref["pobj"])))
         assert info["status"] == pdlp.OPTIMAL and ref["status"] == oracle.OPTIMAL
         assert _objective_interval_ok(lp, sol.x, sol.y, f, xs, ys, f"seed {seed}")["rel_kkt"] <= 1e-4
+
+
+def test_column_block_product_parity(pdlp):
+    """FP32 handles may form A'y by column blocks: a work group owns 4,096 columns and reads y in
+    16,384-row panels held in LDS, each column's run of entries in a panel summed in row order in
+    FP64 and the panel sums added in panel order. The product as the iteration forms it, against the
+    oracle's, with the path forced on: three row panels with a ragged last one and three column
+    blocks with a ragged last one, columns of ~200 entries (runs longer than the two slots a group
+    keeps in registers), short columns over 49 blocks (some columns empty), and the single-panel,
+    single-block case; every entry within one FP32 rounding of its FP64 sum (2e-6 of (|A|'|y|)_j)."""
+    cases = [g.general_sparse(31, m=40000, n=9000, cap=2000), g.general_sparse(32, m=40000, n=200000, cap=500),
+             g.set_cover(2, m=800, n=2000)]
+    rng = np.random.default_rng(4)
+    for lp in cases:
+        y = rng.standard_normal(lp.m)
+        trp, tci, tv = oracle.transpose(lp.m, lp.n, lp.row_ptr, lp.col, lp.val)
+        ref = oracle.spmv(trp, tci, tv, y)
+        bound = 2e-6 * oracle.spmv(trp, tci, np.abs(tv), np.abs(y)) + 1e-30
+        with pdlp.Problem(lp, precision="fp32", col_blocks=1, kernel_timing=True) as p:
+            it = p.spmv(y, trans=True, iteration=True)
+            plain = p.spmv(y, trans=True)
+            p.solve(tol=0.0, iter_limit=64)
+            launches = p.kernel_stats()["col_blocks"]["launches"]
+        with pdlp.Problem(lp, precision="fp32", col_blocks=-1, kernel_timing=True) as p:
+            off = p.spmv(y, trans=True, iteration=True)
+            p.solve(tol=0.0, iter_limit=64)
+            assert p.kernel_stats()["col_blocks"]["launches"] == 0
+        empty = int(np.sum(np.diff(trp) == 0))
+        say("col blocks", lp.name, "empty columns", empty, "launches", launches,
+            "max err / bound %.2e" % np.max(np.abs(it - ref) / bound))
+        assert launches > 0
+        assert np.all(np.abs(it - ref) <= bound)
+        assert np.all(np.abs(plain - ref) <= bound) and np.all(np.abs(off - ref) <= bound)
+
+
+def test_column_block_solves_reach_tolerance(pdlp):
+    """Solves with A'y by column blocks (forced on) reach relative KKT 1e-4 as the oracle
+    re-evaluates it, with the objective inside the weak-duality interval; a batch of members with and
+    without column blocks gives each member the bits of its single solve (the layout, and with it
+    every summation order, depends on the instance alone)."""
+    lp = g.general_sparse(7, m=3000, n=6000, cap=1000)
+    f, xs, ys = P.highs(lp)
+    with pdlp.Problem(lp, precision="fp32", col_blocks=1) as p:
+        info = p.solve(tol=1e-4, iter_limit=2_000_000)
+        sol = p.get()
+    say("col blocks general", info["status_name"], info["iterations"], info["primal_obj"], "highs", f)
+    assert info["status"] == pdlp.OPTIMAL
+    assert _objective_interval_ok(lp, sol.x, sol.y, f, xs, ys, "col blocks")["rel_kkt"] <= 1e-4
+    lps = [g.general_sparse(33, m=20000, n=30000, cap=800), g.set_cover(34, m=500, n=1200),
+           g.general_sparse(35, m=2500, n=9000, cap=400)]
+    singles = []
+    for q in lps:
+        with pdlp.Problem(q, precision="fp32", tile_nnz=1024, col_blocks=1) as p:
+            p.solve(tol=1e-4, iter_limit=50_000)
+            singles.append(p.get())
+    with pdlp.Batch(lps, precision="fp32", tile_nnz=1024, col_blocks=1) as bt:
+        bt.solve(tol=1e-4, iter_limit=50_000)
+        for i in range(len(lps)):
+            s = bt.get(i)
+            say("col block batch", i, s.info["iterations"], singles[i].info["iterations"])
+            assert s.info["iterations"] == singles[i].info["iterations"]
+            assert np.array_equal(s.x, singles[i].x) and np.array_equal(s.y, singles[i].y)
