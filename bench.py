@@ -32,6 +32,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; commands and raw figures in profiles/
+    # k_primal_cb on the 500k x 1M general sparse LP: FETCH_SIZE 113,296 KiB x 2 + WRITE_SIZE 13,682 KiB
+    ("zipf", "primal", "4584711858dca0f00c21a788acf68c2de036deac"): 246_040_576,
 }
 
 
