@@ -791,13 +791,23 @@ __device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, 
     double s = 0.0;
     if (len > 0) s = fma(double(va), double(ys[ra]), s);
     if (len > 1) s = fma(double(vb), double(ys[rb]), s);
-    if (glen > 2) {
-      const int64_t e = (int64_t)ebl[g - gfirst] * kWave + lane;
-      for (int t = 2; t < glen; ++t) {
-        const uint32_t r = __builtin_nontemporal_load(rows + e + (int64_t)t * kWave);
-        const float v = float(__builtin_nontemporal_load(val + e + (int64_t)t * kWave));
-        if (t < len) s = fma(double(v), double(ys[r]), s);
+    // the remaining slots eight at a time: the loads of a batch are issued together, then summed
+    // in order (runs in the densest panel are tens of entries long)
+    constexpr int kB = 8;
+    const int64_t e = (int64_t)ebl[g - gfirst] * kWave + lane;
+    for (int t0 = 2; t0 < glen; t0 += kB) {
+      uint32_t rq[kB];
+      float vq[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        if (t0 + u < glen) {
+          rq[u] = __builtin_nontemporal_load(rows + e + (int64_t)(t0 + u) * kWave);
+          vq[u] = float(__builtin_nontemporal_load(val + e + (int64_t)(t0 + u) * kWave));
+        }
       }
+#pragma unroll
+      for (int u = 0; u < kB; ++u)
+        if (t0 + u < len) s = fma(double(vq[u]), double(ys[rq[u]]), s);
     }
     if (len > 0) acc[lc] += s;
   };
