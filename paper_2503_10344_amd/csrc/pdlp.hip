@@ -259,19 +259,44 @@ static bool build_panels(const std::vector<int32_t> &rp, const std::vector<int32
 
 // Column-block layout of A' (host side; see ColBlocks in pdlp_internal.h).
 struct ColBlockHost {
-  std::vector<int32_t> wg_inst, wg_blk, wg_g0, gstart, ebase, src;
-  std::vector<uint32_t> desc;
+  std::vector<int32_t> wg_inst, wg_blk, wg_g0, gstart, ebase, src, wg_t, tebase, trow, tsrc;
+  std::vector<uint32_t> desc, tdesc;
   std::vector<uint16_t> row;
 };
 constexpr int64_t kCbAutoNnz = int64_t(1) << 20;  // auto mode: instances with at least this many nonzeros
 constexpr int kCbAutoMaxCol = 64;                  // ... and no column longer than this
+constexpr double kCbDenseShare = 0.9;              // dense panels: the shortest prefix holding this share
+
+// Runs of one work group (column lc, first entry, length), sorted by length (longest first), dealt
+// to 64-lane groups: descriptors, the group's first slot (of 64 entries), and per slot and lane the
+// entry's index into crow / csrc (-1 past a run's end).
+struct CbRun {
+  int32_t lc, start, len;
+};
+template <typename Emit>
+static void cb_groups(std::vector<CbRun> &runs, std::vector<uint32_t> &desc, std::vector<int32_t> &ebase,
+                      int64_t &slots, Emit &&emit) {
+  std::stable_sort(runs.begin(), runs.end(), [](const CbRun &a, const CbRun &c) { return a.len > c.len; });
+  for (size_t g0 = 0; g0 < runs.size(); g0 += kWave) {
+    const size_t gn = std::min<size_t>(kWave, runs.size() - g0);
+    const int32_t glen = runs[g0].len;
+    ebase.push_back((int32_t)slots);
+    for (size_t l = 0; l < (size_t)kWave; ++l)
+      desc.push_back(l < gn ? ((uint32_t)runs[g0 + l].len << 16) | (uint32_t)runs[g0 + l].lc : 0u);
+    for (int32_t t = 0; t < glen; ++t)
+      for (size_t l = 0; l < (size_t)kWave; ++l)
+        emit(l < gn && t < runs[g0 + l].len ? runs[g0 + l].start + t : -1);
+    slots += glen;
+  }
+}
 
 // Columns [c0, c0 + nq) of instance q (rows [r0, r0 + mq), internal numbering; rp / ci: A in CSR)
-// in work groups of kCbCols columns and row panels of kCbRows rows, as the kernel reads them. src
-// receives the CSR position of every entry (-1: padding). Returns false (H unchanged) when a work
-// group would have more than kCbMaxGroups groups of runs or the slot count leaves the int32 range.
+// in work groups of kCbCols columns, dense row panels of kCbRows rows and the tail, as the kernel
+// reads them. src / tsrc receive the CSR position of every entry (-1: padding). Returns false (H
+// unchanged) when a work group would have more than kCbMaxGroups groups of runs in its panels or a
+// slot count leaves the int32 range.
 static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int q, int32_t r0,
-                             int32_t mq, int32_t c0, int32_t nq, ColBlockHost &H) {
+                             int32_t mq, int32_t c0, int32_t nq, ColBlockHost &H, int32_t *ndense) {
   const int64_t z0 = rp[r0], zq = (int64_t)rp[r0 + mq] - z0;
   // the instance's transpose: entries of each column in row order
   std::vector<int32_t> cp((size_t)nq + 1, 0), crow((size_t)zq), csrc((size_t)zq);
@@ -286,20 +311,27 @@ static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<i
       }
   }
   const int np = (mq + kCbRows - 1) / kCbRows, nb = (nq + kCbCols - 1) / kCbCols;
+  // dense panels: the shortest prefix of panels holding kCbDenseShare of the entries
+  int nd = 0;
+  {
+    std::vector<int64_t> per((size_t)np, 0);
+    for (int32_t i = 0; i < mq; ++i) per[(size_t)(i / kCbRows)] += rp[r0 + i + 1] - rp[r0 + i];
+    int64_t acc = 0;
+    while (nd < np && (double)acc < kCbDenseShare * (double)zq) acc += per[(size_t)nd++];
+  }
   std::vector<int32_t> cur(cp.begin(), cp.end() - 1);  // next entry of each column
   ColBlockHost out;
-  int64_t slots = (int64_t)H.row.size() / kWave;  // entry slots (of 64) before this instance
-  const int64_t g_base = (int64_t)H.ebase.size();
-  struct Run {
-    int32_t lc, start, len;
-  };
-  std::vector<Run> runs;
+  int64_t slots = (int64_t)H.row.size() / kWave;     // panel entry slots (of 64) before this instance
+  int64_t tslots = (int64_t)H.trow.size() / kWave;   // tail entry slots before this instance
+  const int64_t g_base = (int64_t)H.ebase.size(), t_base = (int64_t)H.tebase.size();
+  std::vector<CbRun> runs;
   for (int b = 0; b < nb; ++b) {
     out.wg_inst.push_back(q), out.wg_blk.push_back(b);
     out.wg_g0.push_back((int32_t)(H.gstart.size() + out.gstart.size()));
+    out.wg_t.push_back((int32_t)(t_base + (int64_t)out.tebase.size()));
     const int64_t wg_first = g_base + (int64_t)out.ebase.size();
     const int32_t jb = b * kCbCols, jn = std::min(kCbCols, nq - jb);
-    for (int p = 0; p < np; ++p) {
+    for (int p = 0; p < nd; ++p) {
       out.gstart.push_back((int32_t)(g_base + (int64_t)out.ebase.size()));
       const int32_t rend = (p + 1) * kCbRows;
       runs.clear();
@@ -310,29 +342,32 @@ static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<i
         if (len > 0) runs.push_back({lc, cur[j], len});
         cur[j] += len;
       }
-      std::stable_sort(runs.begin(), runs.end(), [](const Run &a, const Run &c) { return a.len > c.len; });
-      for (size_t g0 = 0; g0 < runs.size(); g0 += kWave) {
-        const size_t gn = std::min<size_t>(kWave, runs.size() - g0);
-        const int32_t glen = runs[g0].len;
-        out.ebase.push_back((int32_t)slots);
-        for (size_t l = 0; l < (size_t)kWave; ++l)
-          out.desc.push_back(l < gn ? ((uint32_t)runs[g0 + l].len << 16) | (uint32_t)runs[g0 + l].lc : 0u);
-        for (int32_t t = 0; t < glen; ++t)
-          for (size_t l = 0; l < (size_t)kWave; ++l) {
-            const bool have = l < gn && t < runs[g0 + l].len;
-            out.row.push_back(have ? (uint16_t)(crow[runs[g0 + l].start + t] - p * kCbRows) : (uint16_t)0);
-            out.src.push_back(have ? csrc[runs[g0 + l].start + t] : -1);
-          }
-        slots += glen;
-        if (slots >= INT32_MAX / kWave) return false;
-      }
+      cb_groups(runs, out.desc, out.ebase, slots, [&](int32_t k) {
+        out.row.push_back(k >= 0 ? (uint16_t)(crow[k] - p * kCbRows) : (uint16_t)0);
+        out.src.push_back(k >= 0 ? csrc[k] : -1);
+      });
     }
     out.gstart.push_back((int32_t)(g_base + (int64_t)out.ebase.size()));
-    if (g_base + (int64_t)out.ebase.size() - wg_first > kCbMaxGroups) return false;
+    runs.clear();
+    for (int32_t lc = 0; lc < jn; ++lc) {
+      const int32_t j = jb + lc;
+      if (cur[j] < cp[j + 1]) runs.push_back({lc, cur[j], cp[j + 1] - cur[j]});
+      cur[j] = cp[j + 1];
+    }
+    cb_groups(runs, out.tdesc, out.tebase, tslots, [&](int32_t k) {
+      out.trow.push_back(k >= 0 ? crow[k] : 0);
+      out.tsrc.push_back(k >= 0 ? csrc[k] : -1);
+    });
+    if (g_base + (int64_t)out.ebase.size() - wg_first > kCbMaxGroups || slots >= INT32_MAX / kWave ||
+        tslots >= INT32_MAX / kWave)
+      return false;
   }
   auto cat = [](auto &a, const auto &bb) { a.insert(a.end(), bb.begin(), bb.end()); };
+  *ndense = nd;
   cat(H.wg_inst, out.wg_inst), cat(H.wg_blk, out.wg_blk), cat(H.wg_g0, out.wg_g0), cat(H.gstart, out.gstart);
   cat(H.ebase, out.ebase), cat(H.desc, out.desc), cat(H.row, out.row), cat(H.src, out.src);
+  cat(H.wg_t, out.wg_t), cat(H.tebase, out.tebase), cat(H.tdesc, out.tdesc), cat(H.trow, out.trow);
+  cat(H.tsrc, out.tsrc);
   return true;
 }
 
@@ -429,7 +464,9 @@ struct Solver {
   ColBlocks<T> CQ{};
   int32_t *cb_src = nullptr;  // CSR position of each layout entry (set-up only)
   int64_t cb_entries = 0;
-  std::vector<int32_t> h_cb_n, h_pb0;
+  std::vector<int32_t> h_cb_n, h_cb_nd, h_pb0;
+  int32_t *cb_tsrc = nullptr;  // CSR position of each tail entry (set-up only)
+  int64_t cb_tentries = 0;
   int32_t *d_cb_n = nullptr, *d_pb0 = nullptr;
   bool chunk_primal = true;  // some instance runs A'y by the chunk engine (k_primal)
   // reference snapshots (restart points within snap.rel_tol; off while snap.K == 0)
@@ -566,7 +603,7 @@ struct Solver {
     }
 
     // ---- column-block layout of A' (FP32 iterations only) ----
-    h_cb_n.assign((size_t)K, 0);
+    h_cb_n.assign((size_t)K, 0), h_cb_nd.assign((size_t)K, 0);
     ColBlockHost CH;
     if (sizeof(T) == sizeof(float) && o.col_blocks >= 0) {
       for (int q = 0; q < K; ++q) {
@@ -582,7 +619,7 @@ struct Solver {
           if (zq < kCbAutoNnz || longest > kCbAutoMaxCol) continue;
         }
         const size_t w_before = CH.wg_inst.size();
-        if (!build_col_blocks(h_arp, ci, q, r0, mq, c0, nq, CH)) continue;  // CH is unchanged then
+        if (!build_col_blocks(h_arp, ci, q, r0, mq, c0, nq, CH, &h_cb_nd[q])) continue;  // CH unchanged then
         h_cb_n[q] = (int32_t)(CH.wg_inst.size() - w_before);
       }
     }
@@ -626,12 +663,20 @@ struct Solver {
     for (int q = 0; q < K; ++q) chunk_primal |= h_cb_n[q] == 0;
     if (!CH.wg_inst.empty()) {
       for (int l = 0; l < kWave; ++l) CH.row.push_back(0), CH.src.push_back(-1);  // the spare slot
+      CH.wg_t.push_back((int32_t)CH.tebase.size());                                 // end of the last tail
+      CH.tebase.push_back((int32_t)(CH.trow.size() / kWave));
+      if (CH.trow.empty()) CH.trow.push_back(0), CH.tsrc.push_back(-1);
       CQ.nwg = (int32_t)CH.wg_inst.size();
+      CQ.ndense = alloc_upload(h_cb_nd);
       CQ.wg_inst = alloc_upload(CH.wg_inst), CQ.wg_blk = alloc_upload(CH.wg_blk), CQ.wg_g0 = alloc_upload(CH.wg_g0);
       CQ.gstart = alloc_upload(CH.gstart), CQ.desc = alloc_upload(CH.desc), CQ.ebase = alloc_upload(CH.ebase);
       CQ.row = alloc_upload(CH.row);
+      CQ.wg_t = alloc_upload(CH.wg_t), CQ.tdesc = alloc_upload(CH.tdesc), CQ.tebase = alloc_upload(CH.tebase);
+      CQ.trow = alloc_upload(CH.trow);
       cb_src = alloc_upload(CH.src);
       cb_entries = (int64_t)CH.src.size();
+      cb_tsrc = alloc_upload(CH.tsrc);
+      cb_tentries = (int64_t)CH.tsrc.size();
     }
     CH = ColBlockHost{};
 
@@ -747,9 +792,14 @@ struct Solver {
                          (const int32_t *)cb_src, (const T *)a_v, cv);
       HIPCHK(hipGetLastError());
       CQ.val = cv;
+      T *tv = mem.alloc<T>(std::max<int64_t>(cb_tentries, 1));
+      hipLaunchKernelGGL(k_gather_or_zero<T>, dim3(grid_for(cb_tentries)), dim3(kBlock), 0, stream, cb_tentries,
+                         (const int32_t *)cb_tsrc, (const T *)a_v, tv);
+      HIPCHK(hipGetLastError());
+      CQ.tval = tv;
       sync();
-      mem.release(cb_src);
-      cb_src = nullptr;
+      mem.release(cb_src), mem.release(cb_tsrc);
+      cb_src = nullptr, cb_tsrc = nullptr;
     }
 
     // iterates and staging

@@ -112,23 +112,34 @@ struct Panels {
 };
 
 // Column blocks of A' (rows of A' = columns of A). Work group w owns the columns
-// [col0[q] + kCbCols * wg_blk[w], ...) of instance q = wg_inst[w] and reads y in row panels of
-// kCbRows rows. In panel p a column's entries form a run (in row order); the work group's runs in
-// panel p are sorted by length (longest first) and dealt to groups of 64 lanes, the groups
+// [col0[q] + kCbCols * wg_blk[w], ...) of instance q = wg_inst[w]. The first ndense[q] row panels
+// of kCbRows rows (the dense ones: rows are stored longest first) are read through LDS; the
+// entries in later rows (the tail) gather y directly.
+// Panels: in panel p a column's entries form a run (in row order); the work group's runs in panel
+// p are sorted by length (longest first) and dealt to groups of 64 lanes, the groups
 // [gstart[wg_g0[w] + p], gstart[wg_g0[w] + p + 1]). Group g: desc[64 g + l] = (length << 16) |
 // (column within the block) of lane l's run, 0 for a lane without one; entry t of lane l's run is
 // at index 64 (ebase[g] + t) + l of row (row within the panel) and val, for t below the group's
 // longest run (lane 0's). Slots past a run's end hold row 0 and value 0, and the entry arrays end
 // with one spare slot of 64 entries, so a group's second slot can always be read.
+// Tail: a column's tail entries form one run; the work group's tail runs, sorted by length, are
+// dealt to the groups [wg_t[w], wg_t[w + 1]), laid out as above in tdesc, tebase (one entry past
+// the last group too), trow (row within the instance) and tval.
 template <typename T>
 struct ColBlocks {
   int32_t nwg;
+  const int32_t *ndense;
   const int32_t *wg_inst, *wg_blk, *wg_g0;
   const int32_t *gstart;
   const uint32_t *desc;
   const int32_t *ebase;
   const uint16_t *row;
   const T *val;
+  const int32_t *wg_t;
+  const uint32_t *tdesc;
+  const int32_t *tebase;
+  const int32_t *trow;
+  const T *tval;
 };
 
 // Everything an iteration kernel reads or writes. Passed by value.

@@ -728,9 +728,12 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
 // adds the run's sum to the column's FP64 accumulator in LDS. A column has one run per panel and
 // panels are separated by barriers, so each column receives its panel sums in panel order and the
 // result depends on the layout alone. While a panel is summed, the next panel's y values and the
-// wave's first groups of it are loaded into registers. The layout is streamed with non-temporal
-// loads, like the chunk engine's, so that it does not evict the A-side panel data from the
-// last-level cache between attempts.
+// wave's first groups of it are loaded into registers. Rows are stored longest first, so the first
+// panels hold most entries; later panels would cost a panel step (one memory latency) for a few
+// entries each, so the entries past the dense panels (the tail) form one run per column that
+// gathers y directly and is added last. The layout is streamed with non-temporal loads, like the
+// chunk engine's, so that it does not evict the A-side panel data from the last-level cache
+// between attempts.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, int wg, const T *__restrict__ y,
@@ -743,7 +746,7 @@ __device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, 
   static_assert(kGb * kW * kWave >= kCbCols, "every group of a panel must have a register slot");
   const int q = Q.wg_inst[wg];
   const int r0 = L.row0[q], mq = L.row0[q + 1] - r0;
-  const int np = (mq + kCbRows - 1) / kCbRows;
+  const int np = Q.ndense[q];
   const uint32_t *__restrict__ desc = Q.desc;
   const uint16_t *__restrict__ rows = Q.row;
   const T *__restrict__ val = Q.val;
@@ -830,6 +833,37 @@ __device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, 
 #pragma unroll
     for (int u = 0; u < kGb; ++u)
       if (g0 + u * kW < g1) run(g0 + u * kW, dc[u], rc0[u], vc0[u], rc1[u], vc1[u]);
+  }
+  __syncthreads();  // the last panel's sums are in the accumulators
+  // the tail: one run per column, y gathered from memory, eight slots (loads, then gathers) at a time
+  {
+    constexpr int kB = 8;
+    const int t1 = Q.wg_t[wg + 1];
+    for (int g = Q.wg_t[wg] + wave; g < t1; g += kW) {
+      const uint32_t d = __builtin_nontemporal_load(Q.tdesc + (int64_t)g * kWave + lane);
+      const int64_t e = (int64_t)Q.tebase[g] * kWave + lane;
+      const int len = (int)(d >> 16), lc = (int)(d & 0xFFFFu);
+      const int glen = __builtin_amdgcn_readfirstlane(len);  // the group's first run is its longest
+      double s = 0.0;
+      for (int t0 = 0; t0 < glen; t0 += kB) {
+        int32_t rq[kB];
+        float vq[kB], yq[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          if (t0 + u < glen) {
+            rq[u] = __builtin_nontemporal_load(Q.trow + e + (int64_t)(t0 + u) * kWave);
+            vq[u] = float(__builtin_nontemporal_load(Q.tval + e + (int64_t)(t0 + u) * kWave));
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u)
+          if (t0 + u < len) yq[u] = float(y[r0 + rq[u]]);
+#pragma unroll
+        for (int u = 0; u < kB; ++u)
+          if (t0 + u < len) s = fma(double(vq[u]), double(yq[u]), s);
+      }
+      if (len > 0) acc[lc] += s;
+    }
   }
   __syncthreads();
 }
