@@ -8,8 +8,8 @@ columns, FP32 iterates and matrix with FP64 norms, to relative KKT error 1e-4.
 
 Printed: one JSON line: metric, value = median seconds per solve (the production configuration:
 each evaluation interval replayed from a captured hipGraph); the roofline of the dominant iteration
-kernel by measured time, from a separate solve of the same LP whose launches are bracketed by HIP
-events on the handle's stream; the FP64 cold solve; other seeds of the same generator (bounded);
+kernel by measured time, from a separate solve of the same LP whose kernel dispatches record HIP
+start and stop events on the handle's stream; the FP64 cold solve; other seeds of the same generator (bounded);
 the learned warm start on held-out LPs; and the FP64 CPU oracle timed on a bounded sample as
 cpu_baseline. Progress goes to stderr.
 """

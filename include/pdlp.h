@@ -73,9 +73,9 @@ typedef struct pdlp_options {
   void *stream;            /* hipStream_t to order work on; NULL = library-owned stream */
   int32_t warm_fallback;   /* 1 = replace a warm start whose relative KKT error is not below the
                               cold start's by the cold start (default 1) */
-  int32_t kernel_timing;   /* 1 = bracket every launch of the two iteration kernels with HIP events
-                              on the handle's stream (graphs are not used then); read the totals with
-                              pdlp_kernel_stats (default 0) */
+  int32_t kernel_timing;   /* 1 = time every launch of the iteration kernels with HIP events that
+                              their own dispatches record (start and stop; graphs are not used then);
+                              read the totals with pdlp_kernel_stats (default 0) */
   int32_t work_blocks;     /* most blocks per SpMV kernel for one instance (each block owns a
                               contiguous run of chunks; an instance gets one block per 1024 nonzeros
                               + rows up to this count); 0 = 16384 (default 0) */

@@ -4,6 +4,7 @@
 // A handle holds K >= 1 LPs as one block-diagonal problem (pdlp_create: K = 1; pdlp_batch_create:
 // K = k). Set-up runs once over the concatenation (scaling and transposition of a block-diagonal
 // matrix act on each block independently); the per-instance scalars are segmented reductions.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1107,25 +1108,30 @@ struct Solver {
     refresh_averages();
     launch_eval_restart();
   }
-  // Direct launches bracketed by events (pool `slot`): per attempt [k_panel start, k_dual start,
-  // k_dual stop, k_primal start, k_primal stop].
+  // Direct launches whose dispatch packets record events (pool `slot`): per attempt the start and
+  // stop of k_panel, of k_dual and of the primal kernels (k_primal and / or k_primal_cb: the first
+  // one's start, the last one's stop). The timestamps are taken by the kernels' own dispatches, so
+  // the durations are the kernels', without separate marker packets.
   void launch_chunk_timed(int slot) {
     auto &pool = tev[slot];
     if (pool.empty()) {
-      pool.resize((size_t)opt.eval_every * 5);
+      pool.resize((size_t)opt.eval_every * 6);
       for (auto &e : pool) HIPCHK(hipEventCreate(&e));
     }
     for (int r = 0; r < opt.eval_every; ++r) {
-      hipEvent_t *e = &pool[(size_t)r * 5];
-      HIPCHK(hipEventRecord(e[0], stream));
-      launch_panels();
-      HIPCHK(hipEventRecord(e[1], stream));
-      hipLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P);
-      HIPCHK(hipEventRecord(e[2], stream));
+      hipEvent_t *e = &pool[(size_t)r * 6];
+      if (PQ.nwg > 0) hipExtLaunchKernelGGL(k_panel<T>, dim3(PQ.nwg), dim3(kPanelBlock), 0, stream, e[0], e[1], 0, P, PQ);
+      hipExtLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, e[2], e[3], 0, P);
       launch_step();
-      HIPCHK(hipEventRecord(e[3], stream));
-      launch_primal();
-      HIPCHK(hipEventRecord(e[4], stream));
+      const bool cb = sizeof(T) == sizeof(float) && CQ.nwg > 0;
+      if (chunk_primal)
+        hipExtLaunchKernelGGL(k_primal<T>, dim3(tb_blocks), dim3(kBlock), 0, stream, e[4], cb ? nullptr : e[5], 0, P);
+      if constexpr (sizeof(T) == sizeof(float)) {
+        if (cb)
+          hipExtLaunchKernelGGL(k_primal_cb<T>, dim3(CQ.nwg), dim3(kCbBlock), 0, stream,
+                                chunk_primal ? nullptr : e[4], e[5], 0, P, CQ);
+      }
+      HIPCHK(hipGetLastError());
     }
     refresh_averages();
     launch_eval_restart();
@@ -1133,16 +1139,16 @@ struct Solver {
   }
   // Add the durations recorded in pool `slot` (its chunk has completed): kernel 0 = k_dual,
   // 1 = the primal kernels (k_primal and / or k_primal_cb), 2 = k_panel (counted only when the
-  // handle uses column panels), 3 = the primal bracket again when it holds k_primal_cb (counted
+  // handle uses column panels), 3 = the primal kernels again when they include k_primal_cb (counted
   // only when the handle uses column blocks).
   void collect_times(int slot) {
     auto &pool = tev[slot];
-    static const int kFrom[4] = {1, 3, 0, 3}, kTo[4] = {2, 4, 1, 4};
+    static const int kFrom[4] = {2, 4, 0, 4}, kTo[4] = {3, 5, 1, 5};
     for (int r = 0; r < opt.eval_every && !pool.empty(); ++r)
       for (int k = 0; k < 4; ++k) {
         if ((k == 2 && PQ.nwg == 0) || (k == 3 && CQ.nwg == 0)) continue;
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 5 + kFrom[k]], pool[(size_t)r * 5 + kTo[k]]));
+        HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 6 + kFrom[k]], pool[(size_t)r * 6 + kTo[k]]));
         t_ms[k] += ms;
         t_launches[k] += 1;
       }
