@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--other-seeds", default="1,2", help="further seeds of the workload, solved once each")
     ap.add_argument("--other-seeds-limit", type=int, default=150_000)
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--col-blocks", type=int, default=0,
+                    help="pdlp_options.col_blocks for the solves (0 auto, 1 forced where possible, -1 off)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known size for scaling "
                          "hardware byte counters)")
@@ -160,7 +162,7 @@ def main():
 
     # ---------------- FP32 solves (the measured configuration: hipGraphs, no timing events) ----------
     t = time.time()
-    p = pdlp.Problem(lp, precision="fp32")
+    p = pdlp.Problem(lp, precision="fp32", col_blocks=args.col_blocks)
     torch.cuda.synchronize()
     create_s = time.time() - t
     sched = p.schedule()
@@ -187,7 +189,7 @@ def main():
 
     # ---------------- kernel durations: a separate solve with HIP events around every launch ---------
     # (graphs are off in that mode; the trajectory is the same bit for bit)
-    pk = pdlp.Problem(lp, precision="fp32", kernel_timing=True)
+    pk = pdlp.Problem(lp, precision="fp32", kernel_timing=True, col_blocks=args.col_blocks)
     ik = pk.solve(tol=args.tol, iter_limit=args.iter_limit)
     ks = pk.kernel_stats()
     pk.close()
@@ -351,7 +353,7 @@ def bench_batch(args):
     log(f"{len(lps)} instances generated in {time.time() - t:.1f} s: sum m={sum(lp.m for lp in lps)} "
         f"sum n={sum(lp.n for lp in lps)} nnz={nnz}")
     t = time.time()
-    b = pdlp.Batch(lps, precision="fp32")
+    b = pdlp.Batch(lps, precision="fp32", col_blocks=args.col_blocks)
     torch.cuda.synchronize()
     create_s = time.time() - t
     for w in range(args.warmup):
@@ -367,13 +369,28 @@ def bench_batch(args):
     b.close()
     seq, seq_it = 0.0, []
     for lp in lps:
-        with pdlp.Problem(lp, precision="fp32") as p:
+        with pdlp.Problem(lp, precision="fp32", col_blocks=args.col_blocks) as p:
             p.solve(tol=args.tol, iter_limit=args.iter_limit)
             i = p.solve(tol=args.tol, iter_limit=args.iter_limit)
             seq += i["solve_seconds"]
             seq_it.append(i["iterations"])
     sec = statistics.median(times)
     it = [i["iterations"] for i in infos]
+    # aggregate algorithmic traffic over the makespan: every instance's attempts times its bytes per
+    # attempt (both sides of an attempt), all kernels of the batch together
+    alg = sum(i["iterations"] * (algorithmic_bytes("dual", lp.m, lp.n, lp.nnz, 4) +
+                                 algorithmic_bytes("primal", lp.m, lp.n, lp.nnz, 4)) for i, lp in zip(infos, lps))
+    gbs = alg / sec / 1e9
+    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "all iteration kernels of the batch: sum over instances of attempts x algorithmic bytes "
+                          "per attempt (A x' + dual update, A'y' + primal update + averages), over the makespan",
+                "alg_bytes_total": int(alg)}
+    log(f"batch roofline: {json.dumps(roofline)}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = batch_cpu_baseline(lps, it)
+        log(f"cpu baseline: {json.dumps(cpu)}")
     out = {"metric": "makespan to 1e-4 rel. KKT of a batch of LPs (FP32 PDLP)", "value": round(sec, 4), "unit": "s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 2),
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -381,8 +398,45 @@ def bench_batch(args):
                                   f"n = 2.5 m, nnz={nnz}, batch seed {args.seed}", "tol": args.tol},
            "optimal": sum(i["status_name"] == "optimal" for i in infos), "iterations_max": max(it),
            "iterations_median": statistics.median(it), "sequential_s": round(seq, 3),
-           "speedup_vs_sequential": round(seq / sec, 2), "create_s": round(create_s, 2)}
+           "speedup_vs_sequential": round(seq / sec, 2), "create_s": round(create_s, 2),
+           "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def batch_cpu_baseline(lps, iterations, every=8, n1=8, n2=136):
+    """The FP64 oracle on a sample of the batch (every `every`-th instance): setup and per-attempt
+    time from runs of n1 and n2 attempts, per-attempt time per (nnz + m + n) fitted by least squares
+    over the sample, extrapolated to every instance's GPU attempt count and summed (the instances
+    one after the other on the host's cores)."""
+    import numpy as np
+    import oracle
+    xs, per, setup = [], [], []
+    t_all = time.time()
+    for k in range(0, len(lps), every):
+        lp = lps[k]
+        t = time.time()
+        oracle.solve(lp, tol=0.0, iter_limit=n1)
+        t1 = time.time() - t
+        t = time.time()
+        oracle.solve(lp, tol=0.0, iter_limit=n2)
+        t2 = time.time() - t
+        pa = (t2 - t1) / (n2 - n1)
+        xs.append(lp.nnz + lp.m + lp.n)
+        per.append(pa)
+        setup.append(max(t1 - n1 * pa, 0.0))
+    xs, per, setup = np.array(xs, float), np.array(per), np.array(setup)
+    A = np.stack([np.ones_like(xs), xs], axis=1)
+    cp = np.linalg.lstsq(A, per, rcond=None)[0]
+    cs = np.linalg.lstsq(A, setup, rcond=None)[0]
+    est = 0.0
+    for lp, k in zip(lps, iterations):
+        w = lp.nnz + lp.m + lp.n
+        est += max(cs[0] + cs[1] * w, 0.0) + max(cp[0] + cp[1] * w, 0.0) * k
+    return {"value": round(float(est), 2), "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"FP64 oracle (C, OpenMP row loops) on {len(xs)} of the {len(lps)} instances (one in {every}), "
+                       f"{n1} and {n2} attempts each ({time.time() - t_all:.1f} s in all); setup and per-attempt time "
+                       f"fitted linearly in nnz + m + n and summed over all instances with the GPU's attempt counts, "
+                       f"solved one after the other; host CPU: {cpu_model()}")}
 
 
 def bench_fixing(args):

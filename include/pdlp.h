@@ -88,10 +88,13 @@ typedef struct pdlp_options {
                               0 = 64 (default 0), -1 = never. FP64 handles always use the chunk
                               engine */
   int32_t col_blocks;      /* FP32: A'y of an instance by column blocks (a work group owns 4096
-                              columns and reads y in 16384-row panels held in LDS) instead of the
-                              chunk engine; needs every column to have at most 64 nonzeros in each
-                              panel. 0 = when it pays (at least 2^20 nonzeros, at most 64 nonzeros
-                              in the longest column) (default 0), 1 = whenever possible, -1 = never */
+                              columns and reads y in 16384-row panels held in LDS, the rows past the
+                              dense panels gathered) instead of the chunk engine. 0 = for every
+                              instance whose longest column has at most 64 nonzeros when the handle
+                              holds at least 2^20 nonzeros in all (default 0); 1 = for every instance
+                              the layout allows; -1 = never. A single-LP handle reproduces a batch
+                              member's trajectory bit for bit when it takes the same choice for the
+                              instance (with 1 or -1 as the batch's rule decided) */
   int32_t reserved[2];
 } pdlp_options;
 

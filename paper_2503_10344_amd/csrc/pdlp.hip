@@ -264,8 +264,13 @@ struct ColBlockHost {
   std::vector<uint32_t> desc, tdesc;
   std::vector<uint16_t> row;
 };
-constexpr int64_t kCbAutoNnz = int64_t(1) << 20;  // auto mode: instances with at least this many nonzeros
-constexpr int kCbAutoMaxCol = 64;                  // ... and no column longer than this
+// Auto mode: an instance takes column blocks when no column is longer than kCbAutoMaxCol and the
+// handle holds at least kCbAutoNnz nonzeros in all. A work group owns 4,096 columns, so an instance
+// alone fills the GPU only when it is large; in a batch the instances' work groups fill it together
+// (256 LPs of 1k-50k rows: makespan 1.38 -> 0.92 s, while the same LPs one by one take 4.2 s without
+// and 5.1 s with column blocks).
+constexpr int64_t kCbAutoNnz = int64_t(1) << 20;
+constexpr int kCbAutoMaxCol = 64;
 constexpr double kCbDenseShare = 0.9;              // dense panels: the shortest prefix holding this share
 
 // Runs of one work group (column lc, first entry, length), sorted by length (longest first), dealt
@@ -611,13 +616,13 @@ struct Solver {
         const int32_t r0 = h_row0[q], mq = h_row0[q + 1] - r0, c0 = h_col0[q], nq = h_col0[q + 1] - c0;
         if (mq == 0 || nq == 0 || (mq + kCbRows - 1) / kCbRows > kCbMaxPanels) continue;
         if (o.col_blocks == 0) {
-          const int64_t zq = (int64_t)h_arp[r0 + mq] - h_arp[r0];
+          if ((int64_t)nnz < kCbAutoNnz) continue;
           int32_t longest = 0;
           {
             std::vector<int32_t> cl((size_t)nq, 0);
             for (int64_t k = h_arp[r0]; k < h_arp[r0 + mq]; ++k) longest = std::max(longest, ++cl[ci[k] - c0]);
           }
-          if (zq < kCbAutoNnz || longest > kCbAutoMaxCol) continue;
+          if (longest > kCbAutoMaxCol) continue;
         }
         const size_t w_before = CH.wg_inst.size();
         if (!build_col_blocks(h_arp, ci, q, r0, mq, c0, nq, CH, &h_cb_nd[q])) continue;  // CH unchanged then

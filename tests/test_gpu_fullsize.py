@@ -178,7 +178,9 @@ def test_batch_full_size_members_reach_tolerance_and_match_single_solves(pdlp):
     """256 LPs (about 1e8 nonzeros) in one handle: every member's returned point passes the oracle's
     re-evaluation, and sampled members are bitwise the single-problem solve with the same chunk size
     (the chunk size fixes the grouping of the FP64 partial sums, hence the rounding of a
-    trajectory)."""
+    trajectory) and the same column-block choice (the batch holds more than 2^20 nonzeros and every
+    member's columns have at most 64 entries, so the batch gives every member column blocks; alone
+    a member is below 2^20 nonzeros and takes them only with col_blocks = 1)."""
     say("generating the 256-LP batch (seed 0)")
     lps = g.batch(0)
     with pdlp.Batch(lps, precision="fp32") as bt:
@@ -193,7 +195,7 @@ def test_batch_full_size_members_reach_tolerance_and_match_single_solves(pdlp):
     say("batch: all", len(lps), "optimal; worst oracle rel_kkt %.3e" % worst)
     assert worst <= 1e-4
     for i in (0, 1, 127, 255):
-        with pdlp.Problem(lps[i], precision="fp32", tile_nnz=sched["tile_nnz"]) as p:
+        with pdlp.Problem(lps[i], precision="fp32", tile_nnz=sched["tile_nnz"], col_blocks=1) as p:
             p.solve(tol=1e-4, iter_limit=500_000)
             s = p.get()
         say("batch member", i, "iterations", sols[i].info["iterations"], "single", s.info["iterations"])
