@@ -425,27 +425,29 @@ __global__ __launch_bounds__(kBlock) void k_long_sum(Layout L, const double *__r
 // Grid: the A-side work blocks of all instances; each owns a contiguous run of chunks.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
-  const WBlock w = work_block(P.L.ab0, P.L.ab_inst);
-  const State *st = P.st + w.inst;
-  if (st->done | st->stop) return;
-  const int cur = st->cur;
-  const double sigma = st->eta * st->omega;
-  const T *__restrict__ xn = P.x[cur ^ 1];
-  const T *__restrict__ yc = P.y[cur];
-  const T *__restrict__ axc = P.ax[cur];
-  T *__restrict__ yn = P.y[cur ^ 1];
-  T *__restrict__ axn = P.ax[cur ^ 1];
-  const T *__restrict__ b = P.b;
-  const uint8_t *__restrict__ sense = P.sense;
-  double acc[2] = {0.0, 0.0};
-  struct DualPre {
+struct DualSide {
+  struct Pre {
     T y, ax, b;
     uint8_t s;
   };
-  auto pre = [&](int i) { return DualPre{yc[i], axc[i], b[i], sense[i]}; };
+  int cur;
+  double sigma;
+  const T *__restrict__ yc;
+  const T *__restrict__ axc;
+  T *__restrict__ yn;
+  T *__restrict__ axn;
+  const T *__restrict__ b;
+  const uint8_t *__restrict__ sense;
+
+  __device__ __forceinline__ DualSide(const Iter<T> &P, const State *st) {
+    cur = st->cur;
+    sigma = st->eta * st->omega;
+    yc = P.y[cur], axc = P.ax[cur], yn = P.y[cur ^ 1], axn = P.ax[cur ^ 1], b = P.b, sense = P.sense;
+  }
+  __device__ __forceinline__ Pre fetch(int i) const { return Pre{yc[i], axc[i], b[i], sense[i]}; }
+  // row i given its sum s = (A x')_i: the dual candidate, and the row's share of |dy|^2 and dy'(ax' - ax).
   // The update is computed in FP64 from the stored operands and rounded once to T.
-  auto epi = [&](int i, double s, const DualPre &q) {
+  __device__ __forceinline__ void row(int i, double s, const Pre &q, double (&acc)[2]) const {
     const T axi = T(s);
     const double ax1 = double(axi), ax0 = double(q.ax), y0 = double(q.y);
     const T ynew = T(proj_dual(y0 + sigma * (double(q.b) - 2.0 * ax1 + ax0), q.s));
@@ -454,7 +456,19 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
     const double dy = double(ynew) - y0;
     acc[0] += dy * dy;
     acc[1] += dy * (ax1 - ax0);
-  };
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
+  const WBlock w = work_block(P.L.ab0, P.L.ab_inst);
+  const State *st = P.st + w.inst;
+  if (st->done | st->stop) return;
+  const DualSide<T> D(P, st);
+  const T *__restrict__ xn = P.x[D.cur ^ 1];
+  double acc[2] = {0.0, 0.0};
+  auto pre = [&](int i) { return D.fetch(i); };
+  auto epi = [&](int i, double s, const typename DualSide<T>::Pre &q) { D.row(i, s, q, acc); };
   const int nch = P.L.ab_nchunk[w.inst];
   if (w.lb < nch) {
     const int gb = P.L.ab0[w.inst] + w.lb;
@@ -467,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
     const int j = w.lb - nch;
     const int rhi = min((j + 1) * kBlock, Rq);
     for (int r = j * kBlock + (int)threadIdx.x; r < rhi; r += kBlock) {
-      const DualPre q = pre(r0 + r);
+      const typename DualSide<T>::Pre q = pre(r0 + r);
       double s = 0.0;
       for (int pn = 0; pn < Pq; ++pn) s += part[(int64_t)pn * Rq + r];
       epi(r0 + r, s, q);
