@@ -92,9 +92,12 @@ typedef struct pdlp_options {
                               dense panels gathered) instead of the chunk engine. 0 = for every
                               instance whose longest column has at most 64 nonzeros when the handle
                               holds at least 2^20 nonzeros in all (default 0); 1 = for every instance
-                              the layout allows; -1 = never. A single-LP handle reproduces a batch
-                              member's trajectory bit for bit when it takes the same choice for the
-                              instance (with 1 or -1 as the batch's rule decided) */
+                              the layout allows; -1 = never. An instance on column blocks that has
+                              no column-panel rows and at most 131072 columns also forms A x' by row
+                              blocks (a work group owns 4096 rows and reads x in 16384-column panels
+                              held in LDS). A single-LP handle reproduces a batch member's trajectory
+                              bit for bit when it takes the same choice for the instance (with 1 or
+                              -1 as the batch's rule decided) */
   int32_t reserved[2];
 } pdlp_options;
 
@@ -189,12 +192,15 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
 
 /*
  * Kernel timing of the last pdlp_solve with pdlp_options.kernel_timing = 1.
- *   kernel 0: A x' fused with the dual update and the step-size partial sums
+ *   kernel 0: A x' fused with the dual update and the step-size partial sums (from the start of the
+ *             first to the end of the last of its launches: k_dual and / or the row-block form)
  *   kernel 1: A'y' fused with the primal update and the iterate averages
  *   kernel 2: the column-panel sums of the long rows of A x' (launched before kernel 0 when the
  *             handle uses column panels; no launches otherwise)
  *   kernel 3: the same launches and durations as kernel 1, counted only when kernel 1 includes the
  *             column-block form of A'y' (see pdlp_options.col_blocks; no launches otherwise)
+ *   kernel 4: the same launches and durations as kernel 0, counted only when kernel 0 includes the
+ *             row-block form of A x' (see pdlp_options.col_blocks; no launches otherwise)
  * (the step-size decision itself runs in a small per-instance kernel between them and is not timed)
  * *launches receives the number of launches, *total_ms their summed HIP-event durations.
  */

@@ -272,6 +272,7 @@ struct ColBlockHost {
 constexpr int64_t kCbAutoNnz = int64_t(1) << 20;
 constexpr int kCbAutoMaxCol = 64;
 constexpr double kCbDenseShare = 0.9;              // dense panels: the shortest prefix holding this share
+constexpr int kRbMaxPanels = 8;  // row blocks of A x: instances with at most this many x panels
 
 // Runs of one work group (column lc, first entry, length), sorted by length (longest first), dealt
 // to 64-lane groups: descriptors, the group's first slot (of 64 entries), and per slot and lane the
@@ -296,36 +297,27 @@ static void cb_groups(std::vector<CbRun> &runs, std::vector<uint32_t> &desc, std
   }
 }
 
-// Columns [c0, c0 + nq) of instance q (rows [r0, r0 + mq), internal numbering; rp / ci: A in CSR)
-// in work groups of kCbCols columns, dense row panels of kCbRows rows and the tail, as the kernel
-// reads them. src / tsrc receive the CSR position of every entry (-1: padding). Returns false (H
-// unchanged) when a work group would have more than kCbMaxGroups groups of runs in its panels or a
-// slot count leaves the int32 range.
-static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int q, int32_t r0,
-                             int32_t mq, int32_t c0, int32_t nq, ColBlockHost &H, int32_t *ndense) {
-  const int64_t z0 = rp[r0], zq = (int64_t)rp[r0 + mq] - z0;
-  // the instance's transpose: entries of each column in row order
-  std::vector<int32_t> cp((size_t)nq + 1, 0), crow((size_t)zq), csrc((size_t)zq);
-  for (int64_t k = z0; k < z0 + zq; ++k) cp[(size_t)(ci[k] - c0) + 1]++;
-  for (int32_t j = 0; j < nq; ++j) cp[j + 1] += cp[j];
-  {
-    std::vector<int32_t> fill(cp.begin(), cp.end() - 1);
-    for (int32_t i = 0; i < mq; ++i)
-      for (int32_t k = rp[r0 + i]; k < rp[r0 + i + 1]; ++k) {
-        const int32_t j = ci[k] - c0;
-        crow[fill[j]] = i, csrc[fill[j]] = k, ++fill[j];
-      }
-  }
-  const int np = (mq + kCbRows - 1) / kCbRows, nb = (nq + kCbCols - 1) / kCbCols;
+// Line blocks of instance q: its nl lines (columns of A for A'y, rows of A for A x), line l's
+// entries given in position order (lp: [nl + 1] offsets; lpos: position within the instance, i.e.
+// row for a column, column for a row; lsrc: CSR position), over npos positions. Work groups of
+// kCbCols lines, dense position panels of kCbRows and the tail, as the kernel reads them (layout in
+// ColBlocks; "column" there is the line, "row" the position). src / tsrc receive the CSR position
+// of every entry (-1: padding). Returns false (H unchanged) when a work group would have more than
+// kCbMaxGroups groups of runs in its panels or a slot count leaves the int32 range.
+static bool build_line_blocks(const std::vector<int32_t> &lp, const std::vector<int32_t> &lpos,
+                              const std::vector<int32_t> &lsrc, int q, int32_t nl, int32_t npos, ColBlockHost &H,
+                              int32_t *ndense) {
+  const int64_t zq = lp[(size_t)nl];
+  const int np = (npos + kCbRows - 1) / kCbRows, nb = (nl + kCbCols - 1) / kCbCols;
   // dense panels: the shortest prefix of panels holding kCbDenseShare of the entries
   int nd = 0;
   {
-    std::vector<int64_t> per((size_t)np, 0);
-    for (int32_t i = 0; i < mq; ++i) per[(size_t)(i / kCbRows)] += rp[r0 + i + 1] - rp[r0 + i];
+    std::vector<int64_t> per((size_t)std::max(np, 1), 0);
+    for (int64_t k = 0; k < zq; ++k) per[(size_t)(lpos[k] / kCbRows)] += 1;
     int64_t acc = 0;
     while (nd < np && (double)acc < kCbDenseShare * (double)zq) acc += per[(size_t)nd++];
   }
-  std::vector<int32_t> cur(cp.begin(), cp.end() - 1);  // next entry of each column
+  std::vector<int32_t> cur(lp.begin(), lp.end() - 1);  // next entry of each line
   ColBlockHost out;
   int64_t slots = (int64_t)H.row.size() / kWave;     // panel entry slots (of 64) before this instance
   int64_t tslots = (int64_t)H.trow.size() / kWave;   // tail entry slots before this instance
@@ -336,33 +328,33 @@ static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<i
     out.wg_g0.push_back((int32_t)(H.gstart.size() + out.gstart.size()));
     out.wg_t.push_back((int32_t)(t_base + (int64_t)out.tebase.size()));
     const int64_t wg_first = g_base + (int64_t)out.ebase.size();
-    const int32_t jb = b * kCbCols, jn = std::min(kCbCols, nq - jb);
+    const int32_t jb = b * kCbCols, jn = std::min(kCbCols, nl - jb);
     for (int p = 0; p < nd; ++p) {
       out.gstart.push_back((int32_t)(g_base + (int64_t)out.ebase.size()));
-      const int32_t rend = (p + 1) * kCbRows;
+      const int32_t pend = (p + 1) * kCbRows;
       runs.clear();
       for (int32_t lc = 0; lc < jn; ++lc) {
         const int32_t j = jb + lc;
         int32_t len = 0;
-        while (cur[j] + len < cp[j + 1] && crow[cur[j] + len] < rend) ++len;
+        while (cur[j] + len < lp[j + 1] && lpos[cur[j] + len] < pend) ++len;
         if (len > 0) runs.push_back({lc, cur[j], len});
         cur[j] += len;
       }
       cb_groups(runs, out.desc, out.ebase, slots, [&](int32_t k) {
-        out.row.push_back(k >= 0 ? (uint16_t)(crow[k] - p * kCbRows) : (uint16_t)0);
-        out.src.push_back(k >= 0 ? csrc[k] : -1);
+        out.row.push_back(k >= 0 ? (uint16_t)(lpos[k] - p * kCbRows) : (uint16_t)0);
+        out.src.push_back(k >= 0 ? lsrc[k] : -1);
       });
     }
     out.gstart.push_back((int32_t)(g_base + (int64_t)out.ebase.size()));
     runs.clear();
     for (int32_t lc = 0; lc < jn; ++lc) {
       const int32_t j = jb + lc;
-      if (cur[j] < cp[j + 1]) runs.push_back({lc, cur[j], cp[j + 1] - cur[j]});
-      cur[j] = cp[j + 1];
+      if (cur[j] < lp[j + 1]) runs.push_back({lc, cur[j], lp[j + 1] - cur[j]});
+      cur[j] = lp[j + 1];
     }
     cb_groups(runs, out.tdesc, out.tebase, tslots, [&](int32_t k) {
-      out.trow.push_back(k >= 0 ? crow[k] : 0);
-      out.tsrc.push_back(k >= 0 ? csrc[k] : -1);
+      out.trow.push_back(k >= 0 ? lpos[k] : 0);
+      out.tsrc.push_back(k >= 0 ? lsrc[k] : -1);
     });
     if (g_base + (int64_t)out.ebase.size() - wg_first > kCbMaxGroups || slots >= INT32_MAX / kWave ||
         tslots >= INT32_MAX / kWave)
@@ -375,6 +367,40 @@ static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<i
   cat(H.wg_t, out.wg_t), cat(H.tebase, out.tebase), cat(H.tdesc, out.tdesc), cat(H.trow, out.trow);
   cat(H.tsrc, out.tsrc);
   return true;
+}
+
+// Columns of instance q (rows [r0, r0 + mq), columns [c0, c0 + nq); rp / ci: A in CSR, internal
+// numbering): each column's entries in row order.
+static bool build_col_blocks(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int q, int32_t r0,
+                             int32_t mq, int32_t c0, int32_t nq, ColBlockHost &H, int32_t *ndense) {
+  const int64_t z0 = rp[r0], zq = (int64_t)rp[r0 + mq] - z0;
+  std::vector<int32_t> cp((size_t)nq + 1, 0), crow((size_t)zq), csrc((size_t)zq);
+  for (int64_t k = z0; k < z0 + zq; ++k) cp[(size_t)(ci[k] - c0) + 1]++;
+  for (int32_t j = 0; j < nq; ++j) cp[j + 1] += cp[j];
+  std::vector<int32_t> fill(cp.begin(), cp.end() - 1);
+  for (int32_t i = 0; i < mq; ++i)
+    for (int32_t k = rp[r0 + i]; k < rp[r0 + i + 1]; ++k) {
+      const int32_t j = ci[k] - c0;
+      crow[fill[j]] = i, csrc[fill[j]] = k, ++fill[j];
+    }
+  return build_line_blocks(cp, crow, csrc, q, nq, mq, H, ndense);
+}
+
+// Rows of instance q: each row's entries in column order.
+static bool build_row_blocks(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int q, int32_t r0,
+                             int32_t mq, int32_t c0, int32_t nq, ColBlockHost &H, int32_t *ndense) {
+  const int64_t z0 = rp[r0], zq = (int64_t)rp[r0 + mq] - z0;
+  std::vector<int32_t> lp((size_t)mq + 1, 0), pos((size_t)zq), src((size_t)zq);
+  std::vector<std::pair<int32_t, int32_t>> row;
+  for (int32_t i = 0; i < mq; ++i) {
+    row.clear();
+    for (int32_t k = rp[r0 + i]; k < rp[r0 + i + 1]; ++k) row.push_back({ci[k] - c0, k});
+    std::sort(row.begin(), row.end());
+    const int64_t b = rp[r0 + i] - z0;
+    for (size_t t = 0; t < row.size(); ++t) pos[(size_t)b + t] = row[t].first, src[(size_t)b + t] = row[t].second;
+    lp[(size_t)i + 1] = (int32_t)(b + (int64_t)row.size());
+  }
+  return build_line_blocks(lp, pos, src, q, mq, nq, H, ndense);
 }
 
 static const int kChunkCandidates[] = {512, 1024, 2048, 4096};
@@ -445,8 +471,8 @@ struct Solver {
   hipGraphExec_t graph = nullptr;
   // kernel timing (opt.kernel_timing): two pools of start/stop events per attempt and kernel
   std::vector<hipEvent_t> tev[2];
-  int64_t t_launches[4] = {0, 0, 0, 0};
-  double t_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t t_launches[5] = {0, 0, 0, 0, 0};
+  double t_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   Iter<T> P{};
   std::shared_ptr<void> fix_cache;  // workspace of the LP-based variable strategies, kept between calls
   // column-panel path of the long rows of A (FP32; PQ.nwg == 0: off). h_lr_*: see Layout.
@@ -465,16 +491,18 @@ struct Solver {
   int32_t *d_ia_ab0 = nullptr, *d_ia_ab_inst = nullptr, *d_ia_bchunk = nullptr, *d_ab_nchunk = nullptr;
   std::vector<int32_t> h_ia_ab0;
   int ia_blocks = 1;
-  // column-block path of A'y (FP32; CQ.nwg == 0: off). h_cb_n[q]: work groups of instance q (0: the
-  // chunk engine); h_pb0: ranges of p_primal per instance.
-  ColBlocks<T> CQ{};
-  int32_t *cb_src = nullptr;  // CSR position of each layout entry (set-up only)
-  int64_t cb_entries = 0;
-  std::vector<int32_t> h_cb_n, h_cb_nd, h_pb0;
-  int32_t *cb_tsrc = nullptr;  // CSR position of each tail entry (set-up only)
-  int64_t cb_tentries = 0;
-  int32_t *d_cb_n = nullptr, *d_pb0 = nullptr;
+  // column blocks of A'y and row blocks of A x (FP32; nwg == 0: off). h_cb_n[q] / h_rb_n[q]: work
+  // groups of instance q (0: the chunk engine); h_pb0 / h_db0: ranges of p_primal / p_dual pairs.
+  struct LineBlocksSrc {  // CSR positions of a layout's entries (set-up only)
+    int32_t *src = nullptr, *tsrc = nullptr;
+    int64_t ne = 0, nte = 0;
+  };
+  ColBlocks<T> CQ{}, RQ{};
+  LineBlocksSrc cb_src, rb_src;
+  std::vector<int32_t> h_cb_n, h_cb_nd, h_rb_n, h_rb_nd, h_pb0, h_db0;
+  int32_t *d_cb_n = nullptr, *d_rb_n = nullptr, *d_pb0 = nullptr, *d_db0 = nullptr;
   bool chunk_primal = true;  // some instance runs A'y by the chunk engine (k_primal)
+  bool chunk_dual = true;    // some instance runs A x by k_dual
   // reference snapshots (restart points within snap.rel_tol; off while snap.K == 0)
   Snap snap{};
   bool solved = false;
@@ -629,6 +657,16 @@ struct Solver {
         h_cb_n[q] = (int32_t)(CH.wg_inst.size() - w_before);
       }
     }
+    // ---- row blocks of A x: instances with column blocks, no long-row panels and few x panels ----
+    h_rb_n.assign((size_t)K, 0), h_rb_nd.assign((size_t)K, 0);
+    ColBlockHost RH;
+    for (int q = 0; q < K; ++q) {
+      const int32_t r0 = h_row0[q], mq = h_row0[q + 1] - r0, c0 = h_col0[q], nq = h_col0[q + 1] - c0;
+      if (!h_cb_n[q] || h_lr_R[q] > 0 || (nq + kCbRows - 1) / kCbRows > kRbMaxPanels) continue;
+      const size_t w_before = RH.wg_inst.size();
+      if (!build_row_blocks(h_arp, ci, q, r0, mq, c0, nq, RH, &h_rb_nd[q])) continue;  // RH unchanged then
+      h_rb_n[q] = (int32_t)(RH.wg_inst.size() - w_before);
+    }
 
     const int64_t mm = std::max(m, 1), nn = std::max(n, 1);
     a_rp = alloc_upload(h_arp);
@@ -664,27 +702,12 @@ struct Solver {
       part = mem.alloc<double>(std::max<int64_t>(part_len, 1));
     }
     PH = PanelHost{};
-    d_cb_n = alloc_upload(h_cb_n);
-    chunk_primal = false;
-    for (int q = 0; q < K; ++q) chunk_primal |= h_cb_n[q] == 0;
-    if (!CH.wg_inst.empty()) {
-      for (int l = 0; l < kWave; ++l) CH.row.push_back(0), CH.src.push_back(-1);  // the spare slot
-      CH.wg_t.push_back((int32_t)CH.tebase.size());                                 // end of the last tail
-      CH.tebase.push_back((int32_t)(CH.trow.size() / kWave));
-      if (CH.trow.empty()) CH.trow.push_back(0), CH.tsrc.push_back(-1);
-      CQ.nwg = (int32_t)CH.wg_inst.size();
-      CQ.ndense = alloc_upload(h_cb_nd);
-      CQ.wg_inst = alloc_upload(CH.wg_inst), CQ.wg_blk = alloc_upload(CH.wg_blk), CQ.wg_g0 = alloc_upload(CH.wg_g0);
-      CQ.gstart = alloc_upload(CH.gstart), CQ.desc = alloc_upload(CH.desc), CQ.ebase = alloc_upload(CH.ebase);
-      CQ.row = alloc_upload(CH.row);
-      CQ.wg_t = alloc_upload(CH.wg_t), CQ.tdesc = alloc_upload(CH.tdesc), CQ.tebase = alloc_upload(CH.tebase);
-      CQ.trow = alloc_upload(CH.trow);
-      cb_src = alloc_upload(CH.src);
-      cb_entries = (int64_t)CH.src.size();
-      cb_tsrc = alloc_upload(CH.tsrc);
-      cb_tentries = (int64_t)CH.tsrc.size();
-    }
-    CH = ColBlockHost{};
+    d_cb_n = alloc_upload(h_cb_n), d_rb_n = alloc_upload(h_rb_n);
+    chunk_primal = false, chunk_dual = false;
+    for (int q = 0; q < K; ++q) chunk_primal |= h_cb_n[q] == 0, chunk_dual |= h_rb_n[q] == 0;
+    upload_line_blocks(CH, h_cb_nd, CQ, cb_src);
+    upload_line_blocks(RH, h_rb_nd, RQ, rb_src);
+    CH = ColBlockHost{}, RH = ColBlockHost{};
 
     // ---- transpose (counting sort; the per-column sort of source positions makes it deterministic)
     int32_t *row_of = mem.alloc<int32_t>(nnz);
@@ -792,21 +815,8 @@ struct Solver {
       mem.release(pan_src);
       pan_src = nullptr;
     }
-    if (CQ.nwg > 0) {  // values of the column-block layout (0 for padding entries)
-      T *cv = mem.alloc<T>(std::max<int64_t>(cb_entries, 1));
-      hipLaunchKernelGGL(k_gather_or_zero<T>, dim3(grid_for(cb_entries)), dim3(kBlock), 0, stream, cb_entries,
-                         (const int32_t *)cb_src, (const T *)a_v, cv);
-      HIPCHK(hipGetLastError());
-      CQ.val = cv;
-      T *tv = mem.alloc<T>(std::max<int64_t>(cb_tentries, 1));
-      hipLaunchKernelGGL(k_gather_or_zero<T>, dim3(grid_for(cb_tentries)), dim3(kBlock), 0, stream, cb_tentries,
-                         (const int32_t *)cb_tsrc, (const T *)a_v, tv);
-      HIPCHK(hipGetLastError());
-      CQ.tval = tv;
-      sync();
-      mem.release(cb_src), mem.release(cb_tsrc);
-      cb_src = nullptr, cb_tsrc = nullptr;
-    }
+    gather_line_values(CQ, cb_src);
+    gather_line_values(RQ, rb_src);
 
     // iterates and staging
     for (int q = 0; q < 2; ++q) xs[q] = mem.alloc<T>(nn), ys[q] = mem.alloc<T>(mm), axs[q] = mem.alloc<T>(mm);
@@ -841,7 +851,11 @@ struct Solver {
     ev_blocks = h_ev0.back();
     d_ev_inst = alloc_upload(ev_inst);
     d_ev0 = alloc_upload(h_ev0);
-    p_dual = mem.alloc<double>((int64_t)ia_blocks * 2);
+    h_db0.assign(1, 0);
+    for (int q = 0; q < K; ++q)
+      h_db0.push_back(h_db0.back() + (h_rb_n[q] > 0 ? h_rb_n[q] : h_ia_ab0[q + 1] - h_ia_ab0[q]));
+    d_db0 = alloc_upload(h_db0);
+    p_dual = mem.alloc<double>((int64_t)std::max(h_db0.back(), 1) * 2);
     h_pb0.assign(1, 0);
     for (int q = 0; q < K; ++q) h_pb0.push_back(h_pb0.back() + (h_cb_n[q] > 0 ? h_cb_n[q] : h_tb0[q + 1] - h_tb0[q]));
     d_pb0 = alloc_upload(h_pb0);
@@ -853,6 +867,39 @@ struct Solver {
     sync();
   }
 
+  // Upload a line-block layout (column blocks or row blocks); the entries' CSR positions stay on
+  // the device until gather_line_values fills the values.
+  void upload_line_blocks(ColBlockHost &H, const std::vector<int32_t> &ndense, ColBlocks<T> &Q, LineBlocksSrc &S) {
+    if (H.wg_inst.empty()) return;
+    for (int l = 0; l < kWave; ++l) H.row.push_back(0), H.src.push_back(-1);  // the spare slot
+    H.wg_t.push_back((int32_t)H.tebase.size());                                 // end of the last tail
+    H.tebase.push_back((int32_t)(H.trow.size() / kWave));
+    if (H.trow.empty()) H.trow.push_back(0), H.tsrc.push_back(-1);
+    Q.nwg = (int32_t)H.wg_inst.size();
+    Q.ndense = alloc_upload(ndense);
+    Q.wg_inst = alloc_upload(H.wg_inst), Q.wg_blk = alloc_upload(H.wg_blk), Q.wg_g0 = alloc_upload(H.wg_g0);
+    Q.gstart = alloc_upload(H.gstart), Q.desc = alloc_upload(H.desc), Q.ebase = alloc_upload(H.ebase);
+    Q.row = alloc_upload(H.row);
+    Q.wg_t = alloc_upload(H.wg_t), Q.tdesc = alloc_upload(H.tdesc), Q.tebase = alloc_upload(H.tebase);
+    Q.trow = alloc_upload(H.trow);
+    S.src = alloc_upload(H.src), S.ne = (int64_t)H.src.size();
+    S.tsrc = alloc_upload(H.tsrc), S.nte = (int64_t)H.tsrc.size();
+  }
+  // The layout's values from the iteration-precision matrix (0 for padding entries).
+  void gather_line_values(ColBlocks<T> &Q, LineBlocksSrc &S) {
+    if (Q.nwg == 0) return;
+    T *v = mem.alloc<T>(std::max<int64_t>(S.ne, 1)), *tv = mem.alloc<T>(std::max<int64_t>(S.nte, 1));
+    hipLaunchKernelGGL(k_gather_or_zero<T>, dim3(grid_for(S.ne)), dim3(kBlock), 0, stream, S.ne,
+                       (const int32_t *)S.src, (const T *)a_v, v);
+    hipLaunchKernelGGL(k_gather_or_zero<T>, dim3(grid_for(S.nte)), dim3(kBlock), 0, stream, S.nte,
+                       (const int32_t *)S.tsrc, (const T *)a_v, tv);
+    HIPCHK(hipGetLastError());
+    Q.val = v, Q.tval = tv;
+    sync();
+    mem.release(S.src), mem.release(S.tsrc);
+    S = LineBlocksSrc{};
+  }
+
   void set_params() {
     Layout &L = P.L;
     L.K = K;
@@ -860,7 +907,7 @@ struct Solver {
     L.ab0 = d_ia_ab0, L.ab_inst = d_ia_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
     L.a_bchunk = d_ia_bchunk, L.t_bchunk = d_t_bchunk;
     L.ab_nchunk = d_ab_nchunk, L.lr_R = d_lr_R, L.lr_P = d_lr_P, L.lr_base = d_lr_base;
-    L.pb0 = d_pb0, L.cb_n = d_cb_n;
+    L.pb0 = d_pb0, L.cb_n = d_cb_n, L.db0 = d_db0, L.rb_n = d_rb_n;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
     L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ia_blocks, L.tb_blocks = tb_blocks;
     L.ev_blocks = ev_blocks;
@@ -1072,9 +1119,15 @@ struct Solver {
       if (CQ.nwg > 0) hipLaunchKernelGGL(k_primal_cb<T>, dim3(CQ.nwg), dim3(kCbBlock), 0, stream, P, CQ);
     }
   }
+  void launch_dual() {
+    if (chunk_dual) hipLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P);
+    if constexpr (sizeof(T) == sizeof(float)) {
+      if (RQ.nwg > 0) hipLaunchKernelGGL(k_dual_rb<T>, dim3(RQ.nwg), dim3(kCbBlock), 0, stream, P, RQ);
+    }
+  }
   void launch_attempt() {
     launch_panels();
-    hipLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, P);
+    launch_dual();
     launch_step();
     launch_primal();
   }
@@ -1126,7 +1179,14 @@ struct Solver {
     for (int r = 0; r < opt.eval_every; ++r) {
       hipEvent_t *e = &pool[(size_t)r * 6];
       if (PQ.nwg > 0) hipExtLaunchKernelGGL(k_panel<T>, dim3(PQ.nwg), dim3(kPanelBlock), 0, stream, e[0], e[1], 0, P, PQ);
-      hipExtLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, e[2], e[3], 0, P);
+      const bool rb = sizeof(T) == sizeof(float) && RQ.nwg > 0;
+      if (chunk_dual)
+        hipExtLaunchKernelGGL(k_dual<T>, dim3(ia_blocks), dim3(kBlock), 0, stream, e[2], rb ? nullptr : e[3], 0, P);
+      if constexpr (sizeof(T) == sizeof(float)) {
+        if (rb)
+          hipExtLaunchKernelGGL(k_dual_rb<T>, dim3(RQ.nwg), dim3(kCbBlock), 0, stream, chunk_dual ? nullptr : e[2],
+                                e[3], 0, P, RQ);
+      }
       launch_step();
       const bool cb = sizeof(T) == sizeof(float) && CQ.nwg > 0;
       if (chunk_primal)
@@ -1142,16 +1202,17 @@ struct Solver {
     launch_eval_restart();
     HIPCHK(hipGetLastError());
   }
-  // Add the durations recorded in pool `slot` (its chunk has completed): kernel 0 = k_dual,
-  // 1 = the primal kernels (k_primal and / or k_primal_cb), 2 = k_panel (counted only when the
-  // handle uses column panels), 3 = the primal kernels again when they include k_primal_cb (counted
-  // only when the handle uses column blocks).
+  // Add the durations recorded in pool `slot` (its chunk has completed): kernel 0 = the dual
+  // kernels (k_dual and / or k_dual_rb), 1 = the primal kernels (k_primal and / or k_primal_cb),
+  // 2 = k_panel (counted only when the handle uses column panels), 3 = the primal kernels again when
+  // they include k_primal_cb (counted only when the handle uses column blocks), 4 = the dual kernels
+  // again when they include k_dual_rb (counted only when the handle uses row blocks).
   void collect_times(int slot) {
     auto &pool = tev[slot];
-    static const int kFrom[4] = {2, 4, 0, 4}, kTo[4] = {3, 5, 1, 5};
+    static const int kFrom[5] = {2, 4, 0, 4, 2}, kTo[5] = {3, 5, 1, 5, 3};
     for (int r = 0; r < opt.eval_every && !pool.empty(); ++r)
-      for (int k = 0; k < 4; ++k) {
-        if ((k == 2 && PQ.nwg == 0) || (k == 3 && CQ.nwg == 0)) continue;
+      for (int k = 0; k < 5; ++k) {
+        if ((k == 2 && PQ.nwg == 0) || (k == 3 && CQ.nwg == 0) || (k == 4 && RQ.nwg == 0)) continue;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, pool[(size_t)r * 6 + kFrom[k]], pool[(size_t)r * 6 + kTo[k]]));
         t_ms[k] += ms;
@@ -1252,7 +1313,7 @@ struct Solver {
     upload_state();
     HIPCHK(hipMemsetAsync(ndone, 0, sizeof(int32_t), stream));
     if (snap.K > 0) HIPCHK(hipMemsetAsync(snap.taken, 0, sizeof(int32_t) * (size_t)K, stream));
-    for (int k = 0; k < 4; ++k) t_launches[k] = 0, t_ms[k] = 0.0;
+    for (int k = 0; k < 5; ++k) t_launches[k] = 0, t_ms[k] = 0.0;
     const bool warm = stage_start(x0s, y0s);
     std::vector<int> fallback((size_t)K, 0), warm_q((size_t)K, 0);
     for (int q = 0; q < K; ++q) warm_q[q] = (x0s && x0s[q]) || (y0s && y0s[q]);
@@ -1481,6 +1542,9 @@ struct Solver {
     hipLaunchKernelGGL((k_spmv_pairs<T, T, double, T>), dim3(ia_blocks), dim3(kBlock), 0, stream, (const int32_t *)a_rp,
                        (const int32_t *)a_ci, (const T *)a_v, (const int32_t *)ia_chunk_row, (const int8_t *)ia_chunk_cls,
                        (const int32_t *)d_ia_ab0, (const int32_t *)d_ia_ab_inst, (const int32_t *)d_ia_bchunk, x, y);
+    if constexpr (sizeof(T) == sizeof(float)) {  // the row-block instances, over the chunk engine's result
+      if (RQ.nwg > 0) hipLaunchKernelGGL(k_rb_x<T>, dim3(RQ.nwg), dim3(kCbBlock), 0, stream, P.L, RQ, x, y);
+    }
   }
 
   // A'y as the iteration forms it: the column-block instances by k_cb_x over the chunk engine's
@@ -1792,7 +1856,7 @@ int pdlp_get_schedule(pdlp_problem *p, int32_t *tile_nnz, int32_t *tiles_a, int3
 }
 
 int pdlp_kernel_stats(pdlp_problem *p, int32_t kernel, int64_t *launches, double *total_ms) {
-  if (!p || kernel < 0 || kernel > 3) {
+  if (!p || kernel < 0 || kernel > 4) {
     pdlp::g_last_error = "bad argument to pdlp_kernel_stats";
     return PDLP_ERR_ARG;
   }

@@ -93,6 +93,9 @@ struct Layout {
   // A' side: instance q's |dx|^2 partials are p_primal[pb0[q] .. pb0[q+1]); cb_n[q] > 0 when its A'y
   // runs by column blocks (that many work groups of k_primal_cb; k_primal skips the instance).
   const int32_t *pb0, *cb_n;
+  // A side: instance q's (|dy|^2, dy'(A dx)) partial pairs are p_dual[2 (db0[q] .. db0[q+1])); rb_n[q]
+  // > 0 when its A x runs by row blocks (that many work groups of k_dual_rb; k_dual skips it).
+  const int32_t *db0, *rb_n;
 };
 
 // Column-panel work groups: (row block, panel) pairs. A row block is a run of consecutive long rows

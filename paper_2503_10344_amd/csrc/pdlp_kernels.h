@@ -463,7 +463,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   const WBlock w = work_block(P.L.ab0, P.L.ab_inst);
   const State *st = P.st + w.inst;
-  if (st->done | st->stop) return;
+  if (st->done | st->stop | P.L.rb_n[w.inst]) return;
   const DualSide<T> D(P, st);
   const T *__restrict__ xn = P.x[D.cur ^ 1];
   double acc[2] = {0.0, 0.0};
@@ -489,8 +489,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   }
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
-    P.p_dual[2 * blockIdx.x] = acc[0];
-    P.p_dual[2 * blockIdx.x + 1] = acc[1];
+    const int slot = P.L.db0[w.inst] + ((int)blockIdx.x - P.L.ab0[w.inst]);
+    P.p_dual[2 * slot] = acc[0];
+    P.p_dual[2 * slot + 1] = acc[1];
   }
 }
 
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(kStepBlock) void k_step(Layout L, const double *__r
   }
   const bool rs = st->restart_mode != kNoRestart;
   double dy2 = 0.0, inter = 0.0, dx2 = 0.0;
-  step_sums(p_dual, L.ab0[inst], L.ab0[inst + 1], rs ? p_restart : p_primal, rs ? L.ev_blk0[inst] : L.pb0[inst],
+  step_sums(p_dual, L.db0[inst], L.db0[inst + 1], rs ? p_restart : p_primal, rs ? L.ev_blk0[inst] : L.pb0[inst],
             rs ? L.ev_blk0[inst + 1] : L.pb0[inst + 1], dy2, inter, dx2);
   if (threadIdx.x == 0) {
     st->restart_mode = kNoRestart;
@@ -749,9 +750,10 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
 // chunk engine's, so that it does not evict the A-side panel data from the last-level cache
 // between attempts.
 // ----------------------------------------------------------------------------------------------
+// v0: [K + 1] offsets of the gathered vector per instance (rows for A'y, columns for A x).
 template <typename T>
-__device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, int wg, const T *__restrict__ y,
-                                        float *ys, double *acc, int32_t *gsl, int32_t *ebl) {
+__device__ __forceinline__ void cb_sums(const int32_t *__restrict__ v0, const ColBlocks<T> &Q, int wg,
+                                        const T *__restrict__ y, float *ys, double *acc, int32_t *gsl, int32_t *ebl) {
   static_assert(sizeof(T) == sizeof(float), "the column-block path holds FP32 y panels in LDS");
   constexpr int kW = kCbBlock / kWave;     // waves per work group
   constexpr int kYr = kCbRows / kCbBlock;  // y values per thread and panel
@@ -759,7 +761,7 @@ __device__ __forceinline__ void cb_sums(const Layout &L, const ColBlocks<T> &Q, 
   // a panel has at most kCbCols runs, so kGb groups per wave cover all of them
   static_assert(kGb * kW * kWave >= kCbCols, "every group of a panel must have a register slot");
   const int q = Q.wg_inst[wg];
-  const int r0 = L.row0[q], mq = L.row0[q + 1] - r0;
+  const int r0 = v0[q], mq = v0[q + 1] - r0;
   const int np = Q.ndense[q];
   const uint32_t *__restrict__ desc = Q.desc;
   const uint16_t *__restrict__ rows = Q.row;
@@ -912,7 +914,7 @@ __global__ __launch_bounds__(kCbBlock) void k_primal_cb(Iter<T> P, ColBlocks<T> 
   const int tid = (int)threadIdx.x;
   double dx2 = 0.0;
   if (S.commit) {
-    cb_sums<T>(P.L, Q, wg, P.y[S.cur], ys, acc, gsl, ebl);
+    cb_sums<T>(P.L.row0, Q, wg, P.y[S.cur], ys, acc, gsl, ebl);
     for (int i = tid; i < cn; i += kCbBlock) {
       const int j = c0 + i;
       const typename PrimalSide<T>::Pre pre = S.fetch(j);
@@ -940,8 +942,57 @@ __global__ __launch_bounds__(kCbBlock) void k_cb_x(Layout L, ColBlocks<T> Q, con
   __shared__ int32_t ebl[kCbMaxGroups];
   const int wg = blockIdx.x, q = Q.wg_inst[wg], blk = Q.wg_blk[wg];
   const int c0 = L.col0[q] + blk * kCbCols, cn = min(kCbCols, L.col0[q + 1] - c0);
-  cb_sums<T>(L, Q, wg, y, ys, acc, gsl, ebl);
+  cb_sums<T>(L.row0, Q, wg, y, ys, acc, gsl, ebl);
   for (int i = (int)threadIdx.x; i < cn; i += kCbBlock) out[c0 + i] = T(acc[i]);
+}
+
+// Row blocks of A (FP32; the mirror of column blocks): a work group owns kCbCols consecutive rows
+// of an instance and walks x in panels of kCbRows columns held in LDS; each row's entries in a panel
+// form a run (in column order) summed by one lane, the runs past the dense panels gathered (layout
+// and summation as in cb_sums, with rows as the lines and columns as the positions). Then the dual
+// update of each of the work group's rows and its (|dy|^2, dy'(A dx)) partial pair, as k_dual.
+template <typename T>
+__global__ __launch_bounds__(kCbBlock) void k_dual_rb(Iter<T> P, ColBlocks<T> R) {
+  __shared__ float xs[kCbRows];
+  __shared__ double acc[kCbCols];
+  __shared__ int32_t gsl[kCbMaxPanels + 1];
+  __shared__ int32_t ebl[kCbMaxGroups];
+  __shared__ double red[2 * (kCbBlock / kWave)];
+  const int wg = blockIdx.x, q = R.wg_inst[wg], blk = R.wg_blk[wg];
+  const State *st = P.st + q;
+  if (st->done | st->stop) return;
+  const DualSide<T> D(P, st);
+  cb_sums<T>(P.L.col0, R, wg, P.x[D.cur ^ 1], xs, acc, gsl, ebl);
+  const int i0 = P.L.row0[q] + blk * kCbCols, rn = min(kCbCols, P.L.row0[q + 1] - i0);
+  const int tid = (int)threadIdx.x;
+  double a2[2] = {0.0, 0.0};
+  for (int i = tid; i < rn; i += kCbBlock) D.row(i0 + i, acc[i], D.fetch(i0 + i), a2);
+  constexpr int kW = kCbBlock / kWave;
+#pragma unroll
+  for (int v = 0; v < 2; ++v) a2[v] = wave_sum(a2[v]);
+  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = a2[0], red[kW + tid / kWave] = a2[1];
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = red[0], s1 = red[kW];
+    for (int w = 1; w < kW; ++w) s0 += red[w], s1 += red[kW + w];
+    const int slot = P.L.db0[q] + blk;
+    P.p_dual[2 * slot] = s0;
+    P.p_dual[2 * slot + 1] = s1;
+  }
+}
+
+// A x for a given x over the row-block instances (plain store; products outside the iteration).
+template <typename T>
+__global__ __launch_bounds__(kCbBlock) void k_rb_x(Layout L, ColBlocks<T> R, const T *__restrict__ x,
+                                                   T *__restrict__ out) {
+  __shared__ float xs[kCbRows];
+  __shared__ double acc[kCbCols];
+  __shared__ int32_t gsl[kCbMaxPanels + 1];
+  __shared__ int32_t ebl[kCbMaxGroups];
+  const int wg = blockIdx.x, q = R.wg_inst[wg], blk = R.wg_blk[wg];
+  const int i0 = L.row0[q] + blk * kCbCols, rn = min(kCbCols, L.row0[q + 1] - i0);
+  cb_sums<T>(L.col0, R, wg, x, xs, acc, gsl, ebl);
+  for (int i = (int)threadIdx.x; i < rn; i += kCbBlock) out[i0 + i] = T(acc[i]);
 }
 
 // ----------------------------------------------------------------------------------------------

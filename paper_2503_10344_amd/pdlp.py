@@ -382,7 +382,7 @@ class Problem:
 
     def kernel_stats(self) -> dict:
         out = {}
-        for k, name in ((0, "dual"), (1, "primal"), (2, "panel"), (3, "col_blocks")):
+        for k, name in ((0, "dual"), (1, "primal"), (2, "panel"), (3, "col_blocks"), (4, "row_blocks")):
             n, ms = C.c_int64(), C.c_double()
             _check(load().pdlp_kernel_stats(self.h, k, C.byref(n), C.byref(ms)))
             out[name] = dict(launches=n.value, total_ms=ms.value,

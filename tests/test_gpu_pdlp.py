@@ -540,6 +540,65 @@ def test_column_block_product_parity(pdlp):
         assert np.all(np.abs(plain - ref) <= bound) and np.all(np.abs(off - ref) <= bound)
 
 
+def test_row_block_product_parity(pdlp):
+    """An instance on column blocks with no column-panel rows and at most 8 column panels also forms
+    A x by row blocks: a work group owns 4,096 rows and reads x in 16,384-column panels held in LDS,
+    each row's run in a panel summed in column order in FP64, the panel sums added in panel order and
+    the entries past the dense panels gathered. The product as the iteration forms it, against the
+    oracle's: three row blocks and three column panels with ragged ends and rows up to 300 entries
+    (runs past the eight-slot batches), exactly eight panels, the single-block single-panel case, and
+    nine panels (the row-block path off, the chunk engine's product); every entry within one FP32
+    rounding of its FP64 sum (2e-6 of (|A||x|)_i)."""
+    cases = [(g.general_sparse(41, m=9000, n=40000, cap=300), True),
+             (g.set_cover(42, m=5000, n=8 * 16384, k=4), True),
+             (g.set_cover(2, m=800, n=2000), True),
+             (g.set_cover(43, m=3000, n=8 * 16384 + 1, k=4), False)]
+    rng = np.random.default_rng(5)
+    for lp, on in cases:
+        x = rng.standard_normal(lp.n)
+        ref = oracle.spmv(lp.row_ptr, lp.col, lp.val, x)
+        bound = 2e-6 * oracle.spmv(lp.row_ptr, lp.col, np.abs(lp.val), np.abs(x)) + 1e-30
+        with pdlp.Problem(lp, precision="fp32", col_blocks=1, panel_rows=-1, kernel_timing=True) as p:
+            it = p.spmv(x, iteration=True)
+            plain = p.spmv(x)
+            p.solve(tol=0.0, iter_limit=64)
+            st = p.kernel_stats()
+        say("row blocks", lp.name, "launches", st["row_blocks"]["launches"], "dual launches",
+            st["dual"]["launches"], "max err / bound %.2e" % np.max(np.abs(it - ref) / bound))
+        assert (st["row_blocks"]["launches"] > 0) == on
+        assert st["row_blocks"]["launches"] in (0, st["dual"]["launches"])
+        assert np.all(np.abs(it - ref) <= bound) and np.all(np.abs(plain - ref) <= bound)
+
+
+def test_row_block_solves_reach_tolerance(pdlp):
+    """Solves with A x by row blocks reach relative KKT 1e-4 as the oracle re-evaluates it, with
+    the objective inside the weak-duality interval on the set covers (HiGHS takes minutes on the
+    knapsack relaxation, so it has the KKT check alone); in a batch the row-block members keep the
+    bits of their single solves."""
+    lps = [g.batch_member(0, 6, m_lo=2000, m_hi=6000), g.set_cover(44, m=6000, n=15000, k=6),
+           g.multi_knapsack(45, m=5000, n=12500)]
+    singles = []
+    for i, q in enumerate(lps):
+        with pdlp.Problem(q, precision="fp32", col_blocks=1, kernel_timing=True) as p:
+            info = p.solve(tol=1e-4, iter_limit=200_000)
+            sol = p.get()
+            rb = p.kernel_stats()["row_blocks"]["launches"]
+        say("row blocks", q.name, info["status_name"], info["iterations"], "row-block launches", rb)
+        assert rb > 0 and info["status"] == pdlp.OPTIMAL
+        if i < 2:
+            f, xs, ys = P.highs(q)
+            assert _objective_interval_ok(q, sol.x, sol.y, f, xs, ys, "row blocks")["rel_kkt"] <= 1e-4
+        else:
+            assert oracle.kkt(q, sol.x, sol.y)["rel_kkt"] <= 1e-4
+        singles.append(sol)
+    with pdlp.Batch(lps, precision="fp32", col_blocks=1) as bt:
+        bt.solve(tol=1e-4, iter_limit=200_000)
+        for i in range(len(lps)):
+            s = bt.get(i)
+            assert s.info["iterations"] == singles[i].info["iterations"]
+            assert np.array_equal(s.x, singles[i].x) and np.array_equal(s.y, singles[i].y)
+
+
 def test_column_block_solves_reach_tolerance(pdlp):
     """Solves with A'y by column blocks (forced on) reach relative KKT 1e-4 as the oracle
     re-evaluates it, with the objective inside the weak-duality interval; a batch of members with and
