@@ -485,10 +485,10 @@ struct Solver {
   int32_t *d_lr_R = nullptr, *d_lr_P = nullptr;
   int64_t *d_lr_base = nullptr;
   // iteration layout of the A side (k_dual): per instance a skipped chunk over its long rows, the
-  // chunks of its other rows, then the long-row blocks. Equal to the product layout without panels.
+  // chunks of its other rows and the long-row blocks. Equal to the product layout without panels.
   int32_t *ia_chunk_row = nullptr;
   int8_t *ia_chunk_cls = nullptr;
-  int32_t *d_ia_ab0 = nullptr, *d_ia_ab_inst = nullptr, *d_ia_bchunk = nullptr, *d_ab_nchunk = nullptr;
+  int32_t *d_ia_ab0 = nullptr, *d_ia_ab_inst = nullptr, *d_ia_bchunk = nullptr;
   std::vector<int32_t> h_ia_ab0;
   int ia_blocks = 1;
   // column blocks of A'y and row blocks of A x (FP32; nwg == 0: off). h_cb_n[q] / h_rb_n[q]: work
@@ -906,7 +906,7 @@ struct Solver {
     L.row0 = d_row0, L.col0 = d_col0, L.a_chunk0 = d_a_chunk0, L.t_chunk0 = d_t_chunk0;
     L.ab0 = d_ia_ab0, L.ab_inst = d_ia_ab_inst, L.tb0 = d_tb0, L.tb_inst = d_tb_inst;
     L.a_bchunk = d_ia_bchunk, L.t_bchunk = d_t_bchunk;
-    L.ab_nchunk = d_ab_nchunk, L.lr_R = d_lr_R, L.lr_P = d_lr_P, L.lr_base = d_lr_base;
+    L.lr_R = d_lr_R, L.lr_P = d_lr_P, L.lr_base = d_lr_base;
     L.pb0 = d_pb0, L.cb_n = d_cb_n, L.db0 = d_db0, L.rb_n = d_rb_n;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
     L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ia_blocks, L.tb_blocks = tb_blocks;
@@ -938,8 +938,7 @@ struct Solver {
     for (void *p : {(void *)a_chunk_row, (void *)t_chunk_row, (void *)a_chunk_cls, (void *)t_chunk_cls,
                     (void *)d_a_chunk0, (void *)d_t_chunk0, (void *)d_ab0, (void *)d_ab_inst, (void *)d_tb0,
                     (void *)d_tb_inst, (void *)d_a_bchunk, (void *)d_t_bchunk, (void *)ia_chunk_row,
-                    (void *)ia_chunk_cls, (void *)d_ia_ab0, (void *)d_ia_ab_inst, (void *)d_ia_bchunk,
-                    (void *)d_ab_nchunk})
+                    (void *)ia_chunk_cls, (void *)d_ia_ab0, (void *)d_ia_ab_inst, (void *)d_ia_bchunk})
       if (p) mem.release(p);
     a_chunk_row = alloc_upload(ra), t_chunk_row = alloc_upload(rt);
     a_chunk_cls = alloc_upload(ca), t_chunk_cls = alloc_upload(ct);
@@ -989,9 +988,10 @@ struct Solver {
 
     // Iteration layout of the A side (k_dual). Per instance: a chunk over its long rows that no
     // block takes (their sums come from the column panels), the chunks of its other rows shared out
-    // by weight exactly as above, then one block per kBlock long rows. Blocks are given as (first,
-    // end) chunk pairs. Without long rows this is the layout above, block for block.
-    std::vector<int32_t> ri, ia_inst, ia_bc, ia_nch, cstart((size_t)K), cend((size_t)K);
+    // by weight exactly as above, and one block per kBlock long rows. Blocks are given as (first,
+    // end) chunk pairs, long-row block j as (-1 - j, -1 - j). Without long rows this is the layout
+    // above, block for block.
+    std::vector<int32_t> ri, ia_inst, ia_bc, cstart((size_t)K), cend((size_t)K);
     std::vector<int8_t> ci8;
     for (int q = 0; q < K; ++q) {
       const int32_t rs = h_row0[q] + h_lr_R[q];
@@ -1019,20 +1019,26 @@ struct Solver {
           while (c < c1 && wpre[c] < target) ++c;
           starts.push_back(c);
         }
-        for (int64_t lb = 0; lb < nbq; ++lb) {
-          ia_bc.push_back(starts[lb]), ia_bc.push_back(lb + 1 < nbq ? starts[lb + 1] : c1);
+        // long-row blocks spread evenly among the chunk blocks: consecutive blocks of an instance
+        // run on the same XCD (xcd_remap), so a run of long-row blocks at the end would load one XCD
+        const int nlong = (h_lr_R[q] + kBlock - 1) / kBlock;
+        const int64_t nb = nbq + nlong;
+        int64_t lb = 0, j = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+          if (j < ((b + 1) * nlong) / nb) {
+            ia_bc.push_back((int32_t)(-1 - j)), ia_bc.push_back((int32_t)(-1 - j)), ++j;
+          } else {
+            ia_bc.push_back(starts[lb]), ia_bc.push_back(lb + 1 < nbq ? starts[lb + 1] : c1), ++lb;
+          }
           ia_inst.push_back(q);
         }
-        const int nlong = (h_lr_R[q] + kBlock - 1) / kBlock;
-        for (int j = 0; j < nlong; ++j) ia_bc.push_back(c1), ia_bc.push_back(c1), ia_inst.push_back(q);
-        ia_nch.push_back((int32_t)nbq);
-        h_ia_ab0.push_back(h_ia_ab0.back() + (int32_t)nbq + nlong);
+        h_ia_ab0.push_back(h_ia_ab0.back() + (int32_t)nb);
       }
     }
     ia_blocks = h_ia_ab0.back();
     ia_chunk_row = alloc_upload(ri), ia_chunk_cls = alloc_upload(ci8);
     d_ia_ab0 = alloc_upload(h_ia_ab0), d_ia_ab_inst = alloc_upload(ia_inst);
-    d_ia_bchunk = alloc_upload(ia_bc), d_ab_nchunk = alloc_upload(ia_nch);
+    d_ia_bchunk = alloc_upload(ia_bc);
   }
 
   template <typename V, typename X, typename Acc, typename Y>

@@ -81,14 +81,15 @@ struct Layout {
   const int32_t *a_chunk0, *t_chunk0; // [K+1] chunk ranges of A and A'
   const int32_t *ab0, *ab_inst;     // [K+1], [ab_blocks] A-side work blocks (k_dual)
   const int32_t *tb0, *tb_inst;     // [K+1], [tb_blocks] A'-side work blocks (k_primal)
-  const int32_t *a_bchunk;           // [2 ab_blocks] first and end chunk of each A-side work block
+  const int32_t *a_bchunk;           // [2 ab_blocks] first and end chunk of each A-side work block;
+                                     // (-1 - j, -1 - j) for long-row block j (no chunks)
   const int32_t *t_bchunk;           // [tb_blocks + 1] first chunk of each A'-side work block
   const int32_t *ev_blk0, *ev_inst; // [K+1], [ev_blocks] evaluation blocks
   int32_t a_nchunks, t_nchunks, ab_blocks, tb_blocks, ev_blocks;
   // long rows of A (column-panel path): the first lr_R[q] rows of instance q; their panel sums are
-  // part[lr_base[q] + p * lr_R[q] + r], p < lr_P[q]. Of the instance's A-side blocks the first
-  // ab_nchunk[q] run chunks, the others finish kBlock long rows each. All zero without the path.
-  const int32_t *ab_nchunk, *lr_R, *lr_P;
+  // part[lr_base[q] + p * lr_R[q] + r], p < lr_P[q]; long-row block j of the instance's A-side
+  // blocks finishes its rows [kBlock j, kBlock (j + 1)). All zero without the path.
+  const int32_t *lr_R, *lr_P;
   const int64_t *lr_base;
   // A' side: instance q's |dx|^2 partials are p_primal[pb0[q] .. pb0[q+1]); cb_n[q] > 0 when its A'y
   // runs by column blocks (that many work groups of k_primal_cb; k_primal skips the instance).

@@ -401,11 +401,11 @@ __global__ __launch_bounds__(kPanelBlock) void k_panel_x(Layout L, Panels<T> Q, 
 template <typename Y>
 __global__ __launch_bounds__(kBlock) void k_long_sum(Layout L, const double *__restrict__ part, Y *__restrict__ y) {
   const WBlock w = work_block(L.ab0, L.ab_inst);
-  const int nch = L.ab_nchunk[w.inst];
-  if (w.lb < nch) return;
+  const int gb = L.ab0[w.inst] + w.lb;
+  if (L.a_bchunk[2 * gb] >= 0) return;
   const int Rq = L.lr_R[w.inst], Pq = L.lr_P[w.inst], r0 = L.row0[w.inst];
   const double *__restrict__ pq = part + L.lr_base[w.inst];
-  const int j = w.lb - nch;
+  const int j = -1 - L.a_bchunk[2 * gb];
   const int rhi = min((j + 1) * kBlock, Rq);
   for (int r = j * kBlock + (int)threadIdx.x; r < rhi; r += kBlock) {
     double s = 0.0;
@@ -469,21 +469,32 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   double acc[2] = {0.0, 0.0};
   auto pre = [&](int i) { return D.fetch(i); };
   auto epi = [&](int i, double s, const typename DualSide<T>::Pre &q) { D.row(i, s, q, acc); };
-  const int nch = P.L.ab_nchunk[w.inst];
-  if (w.lb < nch) {
-    const int gb = P.L.ab0[w.inst] + w.lb;
-    block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, P.L.a_bchunk[2 * gb],
+  const int gb = P.L.ab0[w.inst] + w.lb;
+  const int c_lo = P.L.a_bchunk[2 * gb];
+  if (c_lo >= 0) {
+    block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, c_lo,
                                P.L.a_bchunk[2 * gb + 1], pre, epi);
   } else {
     // long rows (column-panel path): the row sum is its panel sums added in panel order
     const int Rq = P.L.lr_R[w.inst], Pq = P.L.lr_P[w.inst], r0 = P.L.row0[w.inst];
     const double *__restrict__ part = P.part + P.L.lr_base[w.inst];
-    const int j = w.lb - nch;
+    const int j = -1 - c_lo;
     const int rhi = min((j + 1) * kBlock, Rq);
     for (int r = j * kBlock + (int)threadIdx.x; r < rhi; r += kBlock) {
       const typename DualSide<T>::Pre q = pre(r0 + r);
+      // the panel sums are read eight at a time (all loads issued before the first add; one block
+      // per kBlock long rows keeps few waves per compute unit) and added in panel order
+      constexpr int kU = 8;
       double s = 0.0;
-      for (int pn = 0; pn < Pq; ++pn) s += part[(int64_t)pn * Rq + r];
+      for (int p0 = 0; p0 < Pq; p0 += kU) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          v[u] = p0 + u < Pq ? __builtin_nontemporal_load(part + (int64_t)(p0 + u) * Rq + r) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (p0 + u < Pq) s += v[u];
+      }
       epi(r0 + r, s, q);
     }
   }
