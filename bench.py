@@ -32,8 +32,11 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; commands and raw figures in profiles/
-    # k_primal_cb on the 500k x 1M general sparse LP: FETCH_SIZE 113,296 KiB x 2 + WRITE_SIZE 13,682 KiB
-    ("zipf", "primal", "4584711858dca0f00c21a788acf68c2de036deac"): 246_040_576,
+    # A side (k_panel + k_dual) on the 500k x 1M general sparse LP: FETCH_SIZE (106,404 + 58,094) KiB x 2
+    # + WRITE_SIZE (21,050 + 6,091) KiB
+    ("zipf", "dual", "d03782e18d624172550ee955ca7d06c02c452fc6"): 364_684_288,
+    # k_primal_cb on the same LP: FETCH_SIZE 111,417 KiB x 2 + WRITE_SIZE 13,682 KiB
+    ("zipf", "primal", "d03782e18d624172550ee955ca7d06c02c452fc6"): 242_192_384,
 }
 
 
@@ -203,7 +206,8 @@ def main():
         bytes_ = algorithmic_bytes(name, lp.m, lp.n, lp.nnz, tb)
         gbs = bytes_ / (us * 1e-6) / 1e9 if us > 0 else None
         kern[name] = dict(launches=launches, avg_us=us, alg_bytes=bytes_, gbs=gbs,
-                          frac=(gbs / PEAK_HBM_GBS) if gbs else None)
+                          frac=(gbs / PEAK_HBM_GBS) if gbs else None,
+                          traffic=MEASURED_TRAFFIC.get((args.workload, name, kernel_source_sha1())))
     if ks["panel"]["launches"]:
         kern["dual"]["of_which_k_panel_us"] = ks["panel"]["avg_ms"] * 1e3
     dname = max(kern, key=lambda k: kern[k]["avg_us"])  # dominant by measured time per attempt
