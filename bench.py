@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm-start comparison")
     ap.add_argument("--warm-instances", type=int, default=200)
     ap.add_argument("--other-seeds", default="1,2", help="further seeds of the workload, solved once each")
-    ap.add_argument("--other-seeds-limit", type=int, default=150_000)
+    ap.add_argument("--other-seeds-limit", type=int, default=300_000)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--col-blocks", type=int, default=0,
                     help="pdlp_options.col_blocks for the solves (0 auto, 1 forced where possible, -1 off)")

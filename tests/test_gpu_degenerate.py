@@ -71,13 +71,28 @@ def test_infeasible_and_unbounded_stop_cleanly():
             assert info["iterations"] <= 5_000 + 64
 
 
-def test_batch_with_degenerate_members_matches_single():
-    lps = [box_only(2, n=50)[0], one_by_one(), g.set_cover(4, m=120, n=300, k=4), box_only(3, n=7)[0]]
-    with pdlp.Batch(lps, precision="fp32", tile_nnz=512) as b:
+def empty_lines():
+    """4 x 5 with an empty row (0 <= 2) and two empty columns (x2 -> 0 at c = 3, x4 -> 1 at c = -1)."""
+    rp = np.array([0, 2, 2, 4, 6], np.int32)
+    ci = np.array([0, 1, 1, 3, 0, 3], np.int32)
+    v = np.array([1.0, 1.0, 1.0, 1.0, 1.0, -1.0])
+    sense = np.array([ord("G"), ord("L"), ord("E"), ord("L")], np.uint8)
+    return g.LP(4, 5, rp, ci, v, np.array([1.0, 2.0, 3.0, 1.0, -1.0]), np.array([1.0, 2.0, 1.0, 0.5]), sense,
+                np.zeros(5), np.ones(5))
+
+
+@pytest.mark.parametrize("col_blocks", [0, 1])
+def test_batch_with_degenerate_members_matches_single(col_blocks):
+    """col_blocks = 1 puts every member with rows and columns on column blocks and row blocks
+    (a row-less member, a 1 x 1 member, empty rows and columns)."""
+    lps = [box_only(2, n=50)[0], one_by_one(), g.set_cover(4, m=120, n=300, k=4), box_only(3, n=7)[0],
+           empty_lines()]
+    with pdlp.Batch(lps, precision="fp32", tile_nnz=512, col_blocks=col_blocks) as b:
         infos = b.solve(tol=1e-6, iter_limit=30_000)
         sols = [b.get(i) for i in range(len(lps))]
     for lp, info, sol in zip(lps, infos, sols):
-        with pdlp.Problem(lp, precision="fp32", tile_nnz=512) as p:
+        assert info["status_name"] == "optimal", (lp.name, info["status_name"])
+        with pdlp.Problem(lp, precision="fp32", tile_nnz=512, col_blocks=col_blocks) as p:
             one = p.solve(tol=1e-6, iter_limit=30_000)
             s1 = p.get()
         assert info["iterations"] == one["iterations"] and info["status_name"] == one["status_name"]
