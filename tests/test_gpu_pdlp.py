@@ -235,6 +235,22 @@ def test_end_to_end_setcover(pdlp, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_setcover_seeds_reach_tolerance(pdlp, prec):
+    """Set cover 2,000 x 5,000, seeds 0-9 (the small-LP latency workload): every solve ends optimal
+    with the oracle's relative KKT error of the returned point at most 1e-4."""
+    worst = 0.0
+    for seed in range(10):
+        lp = g.set_cover(seed)
+        with pdlp.Problem(lp, precision=prec) as p:
+            info = p.solve(tol=1e-4, iter_limit=100_000)
+            sol = p.get()
+        k = oracle.kkt(lp, sol.x, sol.y)
+        worst = max(worst, k["rel_kkt"])
+        assert info["status"] == pdlp.OPTIMAL and k["rel_kkt"] <= 1e-4, (seed, info["iterations"], k["rel_kkt"])
+    say("setcover seeds 0-9", prec, "worst oracle rel_kkt %.3e" % worst)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_end_to_end_energy(pdlp, prec):
     lp = g.energy(4, T=96, N=8, K=6, E=16)
     f, xs, ys = P.highs(lp)
