@@ -40,6 +40,24 @@ MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; comman
 }
 
 
+def oracle_reference(args, info, chk):
+    """The stored FP64 oracle solve of the same LP to the same tolerance (written by
+    tests/golden/make_zipf500k_oracle.py), next to this solve's objectives. Both points meet the
+    relative KKT tolerance, so their objectives may differ by up to the tolerance's duality gap."""
+    path = os.path.join(ROOT, "tests", "golden", "zipf500k_seed0_oracle.json")
+    if args.workload != "zipf" or args.seed != 0 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ref = json.load(f)["solves"].get("%g" % args.tol)
+    if ref is None:
+        return None
+    pobj = info["primal_obj"]
+    return {"source": "FP64 oracle solve, tests/golden/zipf500k_seed0_oracle.json", "tol": ref["tol"],
+            "attempts": ref["iterations"], "pobj": ref["pobj"], "dobj": ref["dobj"],
+            "primal_obj_rel_diff": abs(pobj - ref["pobj"]) / max(1.0, abs(ref["pobj"])),
+            "this_dobj_oracle_evaluated": chk.get("dobj")}
+
+
 def kernel_source_sha1():
     import hashlib
     h = hashlib.sha1()
@@ -307,6 +325,7 @@ def main():
         "rel_kkt": info["rel_kkt"],
         "oracle_rel_kkt": chk["rel_kkt"],
         "primal_obj": info["primal_obj"],
+        "oracle_reference": oracle_reference(args, info, chk),
         "create_s": round(create_s, 3),
         "roofline": roofline,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
