@@ -68,7 +68,8 @@ typedef struct pdlp_options {
   int32_t device_ptrs;     /* 1 = data pointers are device pointers (default 0) */
   int32_t tile_nnz;        /* SpMV chunk size cap in nonzeros (512, 1024, 2048 or 4096);
                               0 = autotune (default 0) */
-  int32_t verbose;         /* 0 silent, 1 one line per solve, 2 one line per evaluation */
+  int32_t verbose;         /* 0 silent, 1 one line per solve, 2 also one line per evaluation (the
+                              first four instances; stderr) */
   int64_t device_mem_limit;/* > 0: cap on the bytes this handle may allocate (default 0 = none) */
   void *stream;            /* hipStream_t to order work on; NULL = library-owned stream */
   int32_t warm_fallback;   /* 1 = replace a warm start whose relative KKT error is not below the

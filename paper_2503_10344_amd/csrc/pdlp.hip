@@ -1422,10 +1422,11 @@ struct Solver {
   void run_loop(int64_t iter_limit) {
     const int64_t max_chunks = iter_limit / opt.eval_every + 3;
     int64_t ch = 0;
-    // PDLP_TRACE_EVALS=<period>: every <period> evaluations, print the relative errors of both
-    // candidates of the first instances (one interval in flight then; the results do not change)
+    // verbose >= 2 (or PDLP_TRACE_EVALS=<period>: every <period> evaluations): print the relative
+    // errors of both candidates of the first instances after each evaluation (one interval in flight
+    // then; the results do not change)
     static const char *trace_env = getenv("PDLP_TRACE_EVALS");
-    const int64_t trace_every = trace_env ? std::max<int64_t>(1, atoll(trace_env)) : 0;
+    const int64_t trace_every = opt.verbose >= 2 ? 1 : trace_env ? std::max<int64_t>(1, atoll(trace_env)) : 0;
     for (; ch < max_chunks; ++ch) {
       run_chunk(ch);
       if (trace_every && ch % trace_every == 0) {
