@@ -164,7 +164,8 @@ int pdlp_get(pdlp_problem *p, double *x, double *y, double *red_cost, pdlp_resul
  * y = A x (trans = 0, x [n], y [m]) or y = A' x (trans = 1, x [m], y [n]) with the ORIGINAL
  * (unscaled) matrix, computed by the library's SpMV kernels in the handle's precision on the
  * handle's stream. trans = 2 computes A x the way the PDHG iteration forms it (FP32 handles sum
- * the long rows of A by column panels, see pdlp_options.panel_rows; otherwise the same as 0), and
+ * the long rows of A by column panels, see pdlp_options.panel_rows, and the rows of narrow
+ * instances on column blocks by row blocks, see pdlp_options.col_blocks; otherwise the same as 0), and
  * trans = 3 computes A'x the way it does (FP32 handles may sum columns by column blocks, see
  * pdlp_options.col_blocks; otherwise the same as 1). x and y are host pointers unless device_ptrs
  * is set.
