@@ -489,7 +489,7 @@ struct Solver {
   int32_t *ia_chunk_row = nullptr;
   int8_t *ia_chunk_cls = nullptr;
   int32_t *d_ia_ab0 = nullptr, *d_ia_ab_inst = nullptr, *d_ia_bchunk = nullptr;
-  std::vector<int32_t> h_ia_ab0;
+  std::vector<int32_t> h_ia_ab0, h_ia_bc, h_t_bchunk;  // host copies of the last schedule built
   int ia_blocks = 1;
   // column blocks of A'y and row blocks of A x (FP32; nwg == 0: off). h_cb_n[q] / h_rb_n[q]: work
   // groups of instance q (0: the chunk engine); h_pb0 / h_db0: ranges of p_primal / p_dual pairs.
@@ -501,6 +501,8 @@ struct Solver {
   LineBlocksSrc cb_src, rb_src;
   std::vector<int32_t> h_cb_n, h_cb_nd, h_rb_n, h_rb_nd, h_pb0, h_db0;
   int32_t *d_cb_n = nullptr, *d_rb_n = nullptr, *d_pb0 = nullptr, *d_db0 = nullptr;
+  int4 *d_ia_desc = nullptr, *d_tb_desc = nullptr;  // start descriptors of k_dual / k_primal blocks
+  int2 *d_tb_rows = nullptr;
   bool chunk_primal = true;  // some instance runs A'y by the chunk engine (k_primal)
   bool chunk_dual = true;    // some instance runs A x by k_dual
   // reference snapshots (restart points within snap.rel_tol; off while snap.K == 0)
@@ -859,12 +861,39 @@ struct Solver {
     h_pb0.assign(1, 0);
     for (int q = 0; q < K; ++q) h_pb0.push_back(h_pb0.back() + (h_cb_n[q] > 0 ? h_cb_n[q] : h_tb0[q + 1] - h_tb0[q]));
     d_pb0 = alloc_upload(h_pb0);
+    build_block_descriptors();
     p_primal = mem.alloc<double>(std::max(h_pb0.back(), 1));
     p_restart = mem.alloc<double>(ev_blocks);
     p_eval = mem.alloc<double>((int64_t)ev_blocks * kEvalNV);
     p_final = mem.alloc<double>((int64_t)ev_blocks * 5);
     set_params();
     sync();
+  }
+
+  // Start descriptors of the k_dual and k_primal blocks (Layout::ia_desc, tb_desc, tb_rows): the
+  // same block -> work mapping as work_block and xcd_remap, resolved once here.
+  void build_block_descriptors() {
+    std::vector<int4> ia((size_t)std::max(ia_blocks, 1), make_int4(0, 0, 0, 0));
+    for (int q = 0; q < K; ++q) {
+      const int s0 = h_ia_ab0[q], nb = h_ia_ab0[q + 1] - s0;
+      for (int t = 0; t < nb; ++t) {
+        const int gb = s0 + xcd_remap(t, nb);
+        ia[(size_t)(s0 + t)] = make_int4(q, h_ia_bc[2 * (size_t)gb], h_ia_bc[2 * (size_t)gb + 1], h_db0[q] + t);
+      }
+    }
+    std::vector<int4> tb((size_t)std::max(tb_blocks, 1), make_int4(0, 0, 0, 0));
+    std::vector<int2> tr((size_t)std::max(tb_blocks, 1), make_int2(0, 0));
+    for (int q = 0; q < K; ++q) {
+      const int s0 = h_tb0[q], nb = h_tb0[q + 1] - s0;
+      const int64_t r0 = h_row0[q], mq = h_row0[q + 1] - r0;
+      for (int t = 0; t < nb; ++t) {
+        const int lb = xcd_remap(t, nb), gb = s0 + lb;
+        // the share() split of the rows, as k_primal computed it
+        tr[(size_t)(s0 + t)] = make_int2((int)(r0 + (lb * mq) / nb), (int)(r0 + ((lb + 1) * mq) / nb));
+        tb[(size_t)(s0 + t)] = make_int4(q, h_t_bchunk[(size_t)gb], h_t_bchunk[(size_t)gb + 1], h_pb0[q] + t);
+      }
+    }
+    d_ia_desc = alloc_upload(ia), d_tb_desc = alloc_upload(tb), d_tb_rows = alloc_upload(tr);
   }
 
   // Upload a line-block layout (column blocks or row blocks); the entries' CSR positions stay on
@@ -908,6 +937,7 @@ struct Solver {
     L.a_bchunk = d_ia_bchunk, L.t_bchunk = d_t_bchunk;
     L.lr_R = d_lr_R, L.lr_P = d_lr_P, L.lr_base = d_lr_base;
     L.pb0 = d_pb0, L.cb_n = d_cb_n, L.db0 = d_db0, L.rb_n = d_rb_n;
+    L.ia_desc = d_ia_desc, L.tb_desc = d_tb_desc, L.tb_rows = d_tb_rows;
     L.ev_blk0 = d_ev0, L.ev_inst = d_ev_inst;
     L.a_nchunks = a_nchunks, L.t_nchunks = t_nchunks, L.ab_blocks = ia_blocks, L.tb_blocks = tb_blocks;
     L.ev_blocks = ev_blocks;
@@ -985,6 +1015,7 @@ struct Solver {
     d_ab0 = alloc_upload(h_ab0), d_ab_inst = alloc_upload(ab_inst);
     d_tb0 = alloc_upload(h_tb0), d_tb_inst = alloc_upload(tb_inst);
     d_a_bchunk = alloc_upload(a_bchunk), d_t_bchunk = alloc_upload(t_bchunk);
+    h_t_bchunk = t_bchunk;
 
     // Iteration layout of the A side (k_dual). Per instance: a chunk over its long rows that no
     // block takes (their sums come from the column panels), the chunks of its other rows shared out
@@ -1036,6 +1067,7 @@ struct Solver {
       }
     }
     ia_blocks = h_ia_ab0.back();
+    h_ia_bc = ia_bc;
     ia_chunk_row = alloc_upload(ri), ia_chunk_cls = alloc_upload(ci8);
     d_ia_ab0 = alloc_upload(h_ia_ab0), d_ia_ab_inst = alloc_upload(ia_inst);
     d_ia_bchunk = alloc_upload(ia_bc);

@@ -97,6 +97,12 @@ struct Layout {
   // A side: instance q's (|dy|^2, dy'(A dx)) partial pairs are p_dual[2 (db0[q] .. db0[q+1])); rb_n[q]
   // > 0 when its A x runs by row blocks (that many work groups of k_dual_rb; k_dual skips it).
   const int32_t *db0, *rb_n;
+  // Per launch block of k_dual (ab_blocks) and of k_primal (tb_blocks), everything the block needs
+  // to start, with the XCD remapping applied: (instance, first chunk, end chunk, partial slot), and
+  // for k_primal its share (first, end) of the instance's rows. A long-row block of k_dual has the
+  // chunk pair (-1 - j, -1 - j).
+  const int4 *ia_desc, *tb_desc;
+  const int2 *tb_rows;
 };
 
 // Column-panel work groups: (row block, panel) pairs. A row block is a run of consecutive long rows

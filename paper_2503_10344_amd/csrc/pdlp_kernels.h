@@ -106,7 +106,7 @@ __device__ __forceinline__ A block_sum_scalar(A v) {
 // Workgroups are dispatched round-robin over the 8 XCDs. Give every XCD a contiguous range of an
 // instance's work blocks so that neighbouring chunks (which gather neighbouring parts of x in
 // structured matrices) share that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+__host__ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   constexpr int kXcd = 8;
   if (nb < kXcd) return bid;
   const int xcd = bid % kXcd, local = bid / kXcd;
@@ -461,23 +461,21 @@ struct DualSide {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
-  const WBlock w = work_block(P.L.ab0, P.L.ab_inst);
-  const State *st = P.st + w.inst;
-  if (st->done | st->stop | P.L.rb_n[w.inst]) return;
+  const int4 d = P.L.ia_desc[blockIdx.x];  // instance, chunk range, partial-pair slot: one load
+  const int inst = d.x, c_lo = d.y;
+  const State *st = P.st + inst;
+  if (st->done | st->stop | P.L.rb_n[inst]) return;
   const DualSide<T> D(P, st);
   const T *__restrict__ xn = P.x[D.cur ^ 1];
   double acc[2] = {0.0, 0.0};
   auto pre = [&](int i) { return D.fetch(i); };
   auto epi = [&](int i, double s, const typename DualSide<T>::Pre &q) { D.row(i, s, q, acc); };
-  const int gb = P.L.ab0[w.inst] + w.lb;
-  const int c_lo = P.L.a_bchunk[2 * gb];
   if (c_lo >= 0) {
-    block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, c_lo,
-                               P.L.a_bchunk[2 * gb + 1], pre, epi);
+    block_chunks<T, T, double>(P.a_rp, P.a_ci, P.a_val, xn, P.a_chunk_row, P.a_chunk_cls, c_lo, d.z, pre, epi);
   } else {
     // long rows (column-panel path): the row sum is its panel sums added in panel order
-    const int Rq = P.L.lr_R[w.inst], Pq = P.L.lr_P[w.inst], r0 = P.L.row0[w.inst];
-    const double *__restrict__ part = P.part + P.L.lr_base[w.inst];
+    const int Rq = P.L.lr_R[inst], Pq = P.L.lr_P[inst], r0 = P.L.row0[inst];
+    const double *__restrict__ part = P.part + P.L.lr_base[inst];
     const int j = -1 - c_lo;
     const int rhi = min((j + 1) * kBlock, Rq);
     for (int r = j * kBlock + (int)threadIdx.x; r < rhi; r += kBlock) {
@@ -500,9 +498,8 @@ __global__ __launch_bounds__(kBlock) void k_dual(Iter<T> P) {
   }
   block_sum<2>(acc);
   if (threadIdx.x == 0) {
-    const int slot = P.L.db0[w.inst] + ((int)blockIdx.x - P.L.ab0[w.inst]);
-    P.p_dual[2 * slot] = acc[0];
-    P.p_dual[2 * slot + 1] = acc[1];
+    P.p_dual[2 * d.w] = acc[0];
+    P.p_dual[2 * d.w + 1] = acc[1];
   }
 }
 
@@ -717,15 +714,16 @@ struct PrimalSide {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
-  const WBlock w = work_block(P.L.tb0, P.L.tb_inst);
-  const State *st = P.st + w.inst;
-  if (st->done || P.L.cb_n[w.inst] > 0) return;
+  // instance, chunk range, partial slot and share of the rows: two loads issued together
+  const int4 d = P.L.tb_desc[blockIdx.x];
+  const int2 rr = P.L.tb_rows[blockIdx.x];
+  const int inst = d.x, cb = d.y, ce = d.z;
+  const State *st = P.st + inst;
+  if (st->done || P.L.cb_n[inst] > 0) return;
   const PrimalSide<T> S(P, st);
   T *__restrict__ aty = P.aty;
   double acc[1] = {0.0};
   auto fetch = [&](int j) { return S.fetch(j); };
-  int cb, ce;
-  cb = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb], ce = P.L.t_bchunk[P.L.tb0[w.inst] + w.lb + 1];
   if (S.commit) {
     block_chunks<T, T, double>(P.t_rp, P.t_ci, P.t_val, P.y[S.cur], P.t_chunk_row, P.t_chunk_cls, cb, ce, fetch,
                                [&](int j, double s, const typename PrimalSide<T>::Pre &q) {
@@ -733,15 +731,13 @@ __global__ __launch_bounds__(kBlock) void k_primal(Iter<T> P) {
                                  aty[j] = atyj;
                                  S.column(j, atyj, q, acc[0]);
                                });
-    int rb, re;
-    share(P.L.row0[w.inst], P.L.row0[w.inst + 1] - P.L.row0[w.inst], w.lb, w.nb, &rb, &re);
-    S.rows(P, rb, re, (int)threadIdx.x, kBlock);
+    S.rows(P, rr.x, rr.y, (int)threadIdx.x, kBlock);
   } else if (!S.stop && ce > cb) {
     const int j0 = P.t_chunk_row[cb], j1 = P.t_chunk_row[ce];
     for (int j = j0 + (int)threadIdx.x; j < j1; j += kBlock) S.column(j, aty[j], S.fetch(j), acc[0]);
   }
   block_sum<1>(acc);
-  if (threadIdx.x == 0) P.p_primal[P.L.pb0[w.inst] + ((int)blockIdx.x - P.L.tb0[w.inst])] = acc[0];
+  if (threadIdx.x == 0) P.p_primal[d.w] = acc[0];
 }
 
 // ----------------------------------------------------------------------------------------------
