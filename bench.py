@@ -32,11 +32,11 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; commands and raw figures in profiles/
-    # A side (k_panel + k_dual) on the 500k x 1M general sparse LP: FETCH_SIZE (106,404 + 58,094) KiB x 2
-    # + WRITE_SIZE (21,050 + 6,091) KiB
-    ("zipf", "dual", "d03782e18d624172550ee955ca7d06c02c452fc6"): 364_684_288,
-    # k_primal_cb on the same LP: FETCH_SIZE 111,417 KiB x 2 + WRITE_SIZE 13,682 KiB
-    ("zipf", "primal", "d03782e18d624172550ee955ca7d06c02c452fc6"): 242_192_384,
+    # A side (k_panel + k_dual) on the 500k x 1M general sparse LP: FETCH_SIZE (106,231 + 58,480) KiB x 2
+    # + WRITE_SIZE (21,048 + 6,115) KiB
+    ("zipf", "dual", "627c688e7d13c85e0c263a09b716327ba1241e96"): 365_143_040,
+    # k_primal_cb on the same LP: FETCH_SIZE 111,424 KiB x 2 + WRITE_SIZE 13,682 KiB
+    ("zipf", "primal", "627c688e7d13c85e0c263a09b716327ba1241e96"): 242_206_720,
 }
 
 
