@@ -72,8 +72,10 @@ typedef struct pdlp_options {
                               first four instances; stderr) */
   int64_t device_mem_limit;/* > 0: cap on the bytes this handle may allocate (default 0 = none) */
   void *stream;            /* hipStream_t to order work on; NULL = library-owned stream */
-  int32_t warm_fallback;   /* 1 = replace a warm start whose relative KKT error is not below the
-                              cold start's by the cold start (default 1) */
+  int32_t warm_fallback;   /* what happens to a warm start whose relative KKT error is not below
+                              the cold start's: 2 = its point is replaced by the cold point and a
+                              given omega0 is kept (default 2); 1 = the cold start in full (the
+                              default primal weight too); 0 = the warm start is kept */
   int32_t kernel_timing;   /* 1 = time every launch of the iteration kernels with HIP events that
                               their own dispatches record (start and stop; graphs are not used then);
                               read the totals with pdlp_kernel_stats (default 0) */
@@ -147,8 +149,9 @@ int pdlp_create(pdlp_problem **out, int32_t m, int32_t n, int64_t nnz, const int
  * Solve to relative KKT tolerance tol (<= 0 means run to iter_limit) within iter_limit attempts.
  * x0 [n] / y0 [m] optional warm start in the original space (NULL = cold start at the projection
  * of 0); omega0 > 0 sets the initial primal weight (otherwise |c~|/|b~|). A warm start is projected
- * onto the bounds and sign sets; with warm_fallback set it is replaced by the cold start when its
- * relative KKT error is not smaller. Each call starts a fresh solve from its own start point.
+ * onto the bounds and sign sets; with warm_fallback set its point is replaced by the cold start's
+ * when its relative KKT error is not smaller (see pdlp_options.warm_fallback for omega0). Each call
+ * starts a fresh solve from its own start point.
  */
 int pdlp_solve(pdlp_problem *p, double tol, int64_t iter_limit, const double *x0, const double *y0,
                double omega0);

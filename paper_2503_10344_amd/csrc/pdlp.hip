@@ -1372,7 +1372,8 @@ struct Solver {
           const int32_t nq = h_col0[q + 1] - h_col0[q], mq = h_row0[q + 1] - h_row0[q];
           if (nq) HIPCHK(hipMemsetAsync(stage_n + h_col0[q], 0, sizeof(double) * (size_t)nq, stream));
           if (mq) HIPCHK(hipMemsetAsync(stage_m + h_row0[q], 0, sizeof(double) * (size_t)mq, stream));
-          if (omega0s && omega0s[q] > 0.0) h_st[q].omega = omega_default[q];
+          // 1: the cold start in full; 2: the cold point with the given primal weight kept
+          if (omega0s && omega0s[q] > 0.0 && opt.warm_fallback != 2) h_st[q].omega = omega_default[q];
         }
       if (any) {
         gather64(n, stage_n, d_perm_c, xd);
@@ -1797,7 +1798,7 @@ void pdlp_options_default(pdlp_options *o) {
   o->verbose = 0;
   o->device_mem_limit = 0;
   o->stream = nullptr;
-  o->warm_fallback = 1;
+  o->warm_fallback = 2;
   o->kernel_timing = 0;
 }
 

@@ -223,7 +223,7 @@ def _ptr(a):
 
 def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True, use_graphs=True,
             device_ptrs=False, tile_nnz=0, verbose=0, device_mem_limit=0, stream=None,
-            warm_fallback=True, kernel_timing=False, work_blocks=0, single_avg_updates=False,
+            warm_fallback=2, kernel_timing=False, work_blocks=0, single_avg_updates=False,
             panel_rows=0, col_blocks=0) -> Options:
     o = Options()
     load().pdlp_options_default(C.byref(o))
@@ -236,7 +236,7 @@ def options(precision="fp32", eval_every=64, ruiz_iters=10, pock_chambolle=True,
     o.tile_nnz = tile_nnz
     o.verbose = verbose
     o.device_mem_limit = device_mem_limit
-    o.warm_fallback = 1 if warm_fallback else 0
+    o.warm_fallback = int(warm_fallback)  # 0 keep, 1 cold start, 2 cold point keeping omega0
     o.kernel_timing = 1 if kernel_timing else 0
     o.work_blocks = work_blocks
     o.single_avg_updates = 1 if single_avg_updates else 0

@@ -68,7 +68,7 @@ def test_struct_layout_matches_header(lib, tmp_path):
     o = pdlp.Options()
     lib.pdlp_options_default(C.byref(o))
     assert (o.precision, o.eval_every, o.ruiz_iters, o.pock_chambolle, o.use_graphs) == (0, 64, 10, 1, 1)
-    assert o.warm_fallback == 1 and o.tile_nnz == 0
+    assert o.warm_fallback == 2 and o.tile_nnz == 0
 
 
 def _create(lib, lp, **over):

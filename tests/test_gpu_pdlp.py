@@ -406,6 +406,24 @@ def test_iteration_limit_and_warm_start(pdlp):
         assert info["fallback_used"] == 1 and info["status"] == pdlp.OPTIMAL
 
 
+def test_fallback_keeps_or_resets_the_given_primal_weight(pdlp):
+    """A rejected warm point is replaced by the cold point; with warm_fallback = 2 (default) the
+    given omega0 stays, so the solve is bit for bit the cold solve started with that omega0, and with
+    warm_fallback = 1 it is bit for bit the plain cold solve."""
+    lp = g.set_cover(5, m=600, n=1500)
+    bad_x, bad_y, om = np.full(lp.n, 1e6), np.full(lp.m, -1e6), 0.37
+    for fb, ref_omega in ((2, om), (1, None)):
+        with pdlp.Problem(lp, precision="fp32", warm_fallback=fb) as p:
+            w = p.solve(tol=1e-4, x0=bad_x, y0=bad_y, omega0=om)
+            sw = p.get()
+            c = p.solve(tol=1e-4, omega0=ref_omega) if ref_omega else p.solve(tol=1e-4)
+            sc = p.get()
+        say("fallback", fb, w["iterations"], c["iterations"])
+        assert w["fallback_used"] == 1 and w["status"] == pdlp.OPTIMAL
+        assert w["iterations"] == c["iterations"]
+        assert np.array_equal(sw.x, sc.x) and np.array_equal(sw.y, sc.y)
+
+
 def test_device_memory_cap(pdlp):
     lp = g.set_cover(1, m=500, n=1000)
     with pytest.raises(pdlp.PDLPError) as e:
