@@ -32,11 +32,11 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # figure stale (reported null).
 KERNEL_SOURCES = ["pdlp_internal.h", "pdlp_kernels.h", "pdlp.hip"]
 MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; commands and raw figures in profiles/
-    # A side (k_panel + k_dual) on the 500k x 1M general sparse LP: FETCH_SIZE (106,360 + 58,550) KiB x 2
-    # + WRITE_SIZE (21,050 + 6,082) KiB
-    ("zipf", "dual", "44f81fa96806f00bafc215876c9ec0a7aef3e4c8"): 365_518_848,
-    # k_primal_cb on the same LP: FETCH_SIZE 111,423 KiB x 2 + WRITE_SIZE 13,682 KiB
-    ("zipf", "primal", "44f81fa96806f00bafc215876c9ec0a7aef3e4c8"): 242_204_672,
+    # A side (k_panel + k_dual) on the 500k x 1M general sparse LP: FETCH_SIZE (100,391 + 58,435) KiB x 2
+    # + WRITE_SIZE (21,122 + 6,113) KiB
+    ("zipf", "dual", "a4ad068062111aa284e73b81559ce42b8d16c195"): 353_164_288,
+    # k_primal_cb on the same LP: FETCH_SIZE 111,420 KiB x 2 + WRITE_SIZE 13,682 KiB
+    ("zipf", "primal", "a4ad068062111aa284e73b81559ce42b8d16c195"): 242_198_528,
 }
 
 
