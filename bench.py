@@ -37,6 +37,10 @@ MEASURED_TRAFFIC = {  # {(workload, kernel, sha1): HBM bytes per launch}; comman
     ("zipf", "dual", "a4ad068062111aa284e73b81559ce42b8d16c195"): 353_164_288,
     # k_primal_cb on the same LP: FETCH_SIZE 111,420 KiB x 2 + WRITE_SIZE 13,682 KiB
     ("zipf", "primal", "a4ad068062111aa284e73b81559ce42b8d16c195"): 242_198_528,
+    # the energy-shaped LP: k_dual FETCH_SIZE 258,247 KiB x 2 + WRITE_SIZE 60,546 KiB; k_primal
+    # FETCH_SIZE 290,683 KiB x 2 + WRITE_SIZE 152,442 KiB (mean over accepted and deferred launches)
+    ("energy", "dual", "a4ad068062111aa284e73b81559ce42b8d16c195"): 590_888_960,
+    ("energy", "primal", "a4ad068062111aa284e73b81559ce42b8d16c195"): 751_419_392,
 }
 
 
